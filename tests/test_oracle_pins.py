@@ -1,0 +1,543 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test fixes one part of the oracle with something other than the oracle
+itself: closed forms, hand-derived small cases, brute-force dense algebra,
+invariants and the paper's own worked values.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import stokes_synth as S
+
+
+def dense(M):
+    return np.asarray(M.todense())
+
+
+# ---------------------------------------------------------------- assembly
+
+def test_assembly_counts_and_structure():
+    n = 6
+    A = oracle.stokes_matrix(n)
+    ni = (n - 2) ** 3
+    assert A.nnz == 40 * ni + 4 * (n ** 3 - ni)
+    interior = S.interior_nodes(n)
+    rows = np.diff(A.indptr).reshape(-1, 4)
+    assert np.all(rows[interior] == [9, 9, 9, 13])
+    assert np.all(rows[~interior] == 1)
+    # boundary rows are identity rows
+    D = dense(A)
+    for g in np.flatnonzero(~interior):
+        for c in range(4):
+            r = 4 * g + c
+            assert D[r, r] == 1.0 and np.count_nonzero(D[r]) == 1
+
+
+def test_assembly_interior_blocks_symmetric_with_viscosity():
+    """Interior-interior blocks satisfy A_gh = A_hg^T (symmetric indefinite interior,
+    Section 3); boundary columns make the full matrix nonsymmetric."""
+    n = 7
+    th = S.theta_field(n, 0.5, 11)
+    D = dense(oracle.stokes_matrix(n, th))
+    inter = np.flatnonzero(S.interior_nodes(n))
+    idx = (4 * inter[:, None] + np.arange(4)).ravel()
+    Dii = D[np.ix_(idx, idx)]
+    assert np.array_equal(Dii, Dii.T)
+    assert not np.array_equal(D, D.T)
+
+
+def test_assembly_velocity_rows_are_viscous_laplacian():
+    """Velocity rows: the u_c entries sum to zero (diffusion), and each off-diagonal is
+    minus the edge viscosity (mean of the 4 cells on the edge) over h^2."""
+    n = 5
+    th = S.theta_field(n, 1.0, 3)
+    A = oracle.stokes_matrix(n, th)
+    D = dense(A)
+    h2 = (n - 1) ** 2
+    g = 1 + n * (1 + n * 1)           # node (1,1,1)
+    r = 4 * g + 0
+    ucols = [4 * m for m in range(n ** 3)]
+    assert abs(D[r, ucols].sum()) < 1e-12 * abs(D[r, r])
+    # edge (1,1,1) -> (2,1,1): cells (1, j, k) for j, k in {0, 1}
+    cells = [1 + (n - 1) * (j + (n - 1) * k) for k in (0, 1) for j in (0, 1)]
+    mu = 0.25 * th[cells].sum()
+    assert D[r, 4 * (g + 1)] == pytest.approx(-mu * h2, rel=1e-15)
+    # pressure coupling +-1/(2h) and stabilization h^2 lap_h p
+    assert D[r, 4 * (g + 1) + 3] == 0.5 * (n - 1)
+    assert D[r, 4 * (g - 1) + 3] == -0.5 * (n - 1)
+    rp = 4 * g + 3
+    assert D[rp, rp] == -6.0 and D[rp, 4 * (g + n) + 3] == 1.0
+    assert D[rp, 4 * (g + 1)] == -0.5 * (n - 1) and D[rp, 4 * (g - 1)] == 0.5 * (n - 1)
+
+
+def test_assembly_closed_form_residual():
+    """A x* - b at interior rows equals 2((2 - 2cos h)/h^2 - 1) sin x cos y on u rows, its
+    negative-cosine counterpart on v rows, and 0 on w and p rows (central differences of
+    the manufactured u* and the linear p*); 0 on boundary rows."""
+    n = 16
+    A = oracle.stokes_matrix(n)
+    xs, b = S.mms_solution(n), S.mms_rhs(n)
+    res = (A @ xs - b).reshape(-1, 4)
+    h = 1.0 / (n - 1)
+    X = S.node_coords(n)
+    k = 2.0 * ((2.0 - 2.0 * np.cos(h)) / h ** 2 - 1.0)
+    inter = S.interior_nodes(n)
+    expect_u = k * np.sin(X[:, 0]) * np.cos(X[:, 1])
+    expect_v = -k * np.cos(X[:, 0]) * np.sin(X[:, 1])
+    scale = (n - 1) ** 2
+    assert np.allclose(res[inter, 0], expect_u[inter], atol=1e-12 * scale)
+    assert np.allclose(res[inter, 1], expect_v[inter], atol=1e-12 * scale)
+    assert np.allclose(res[inter, 2], 0.0, atol=1e-12 * scale)
+    assert np.allclose(res[inter, 3], 0.0, atol=1e-12 * n)
+    assert np.all(res[~inter] == 0.0)
+
+
+def _solve_tight(A, b):
+    s = oracle.Solver(A, 4)
+    x, info = s.solve(b, 1e-12)
+    assert info["converged"]
+    return x
+
+
+@pytest.mark.slow
+def test_discretization_second_order():
+    """Nodal error of the FD solution against the continuous manufactured solution falls
+    by about 4 per halving of h."""
+    errs = []
+    for n in (9, 17, 33):
+        A = oracle.stokes_matrix(n)
+        x = _solve_tight(A, S.mms_rhs(n))
+        e = (x - S.mms_solution(n)).reshape(-1, 4)
+        errs.append(np.abs(e[:, :3]).max())
+    # observed order over h = 1/8 .. 1/32 (pre-asymptotic ratios are 5.0 and 5.6)
+    order = np.log(errs[0] / errs[2]) / np.log(4.0)
+    assert 1.8 < order < 3.0 and errs[0] > errs[1] > errs[2], errs
+
+
+def paper_cube_triple(X):
+    """Analytic rotating flow of the unit-cube benchmark (Section 5.1, eq. UnitCubeProb).
+    The printed f equals -lap(u~) + grad(p) for u~ = u/pi, i.e. the printed velocity without
+    its leading factor pi (reading of a misprint; with mu = 1 the printed u and f differ by
+    that factor)."""
+    x, y, z = X[:, 0] * np.pi, X[:, 1] * np.pi, X[:, 2] * np.pi
+    s, c = np.sin, np.cos
+    u = np.stack([s(x) * c(y) - s(x) * c(z), s(y) * c(z) - s(y) * c(x),
+                  s(z) * c(x) - s(z) * c(y)], axis=1)
+    p = s(x) * s(y) * s(z) - 8.0 / np.pi ** 3
+    pi = np.pi
+    f = pi * np.stack([
+        2 * pi * s(x) * c(y) - 2 * pi * s(x) * c(z) + s(y) * s(z) * c(x),
+        -2 * pi * s(y) * c(x) + 2 * pi * s(y) * c(z) + s(x) * s(z) * c(y),
+        2 * pi * s(z) * c(x) - 2 * pi * s(z) * c(y) + s(x) * s(y) * c(z)], axis=1)
+    return u, p, f
+
+
+def test_paper_triple_closed_form():
+    """div u = 0, f = -lap(u) + grad p, and mean(p) = 0, checked with high-order central
+    differences at random points (independent of the FD operator under test)."""
+    rng = np.random.default_rng(0)
+    P = rng.uniform(0.1, 0.9, size=(50, 3))
+    d = 1e-3
+    E = np.eye(3) * d
+
+    def U(Q):
+        return paper_cube_triple(Q)[0]
+
+    def Pp(Q):
+        return paper_cube_triple(Q)[1]
+
+    lap = sum((U(P + E[a]) - 2 * U(P) + U(P - E[a])) / d ** 2 for a in range(3))
+    gradp = np.stack([(Pp(P + E[a]) - Pp(P - E[a])) / (2 * d) for a in range(3)], axis=1)
+    div = sum((U(P + E[a])[:, a] - U(P - E[a])[:, a]) / (2 * d) for a in range(3))
+    f = paper_cube_triple(P)[2]
+    assert np.allclose(f, -lap + gradp, atol=1e-4)
+    assert np.abs(div).max() < 1e-6
+    g = (np.arange(200) + 0.5) / 200
+    mean_sss = np.sin(np.pi * g).mean() ** 3
+    assert abs(mean_sss - 8 / np.pi ** 3) < 1e-4
+
+
+@pytest.mark.slow
+def test_paper_triple_second_order():
+    """The paper's analytic solution, imposed through boundary rows and f, is reproduced by
+    the FD operator to O(h^2)."""
+    errs = []
+    for n in (9, 17, 33):
+        A = oracle.stokes_matrix(n)
+        X = S.node_coords(n)
+        u, p, f = paper_cube_triple(X)
+        inter = S.interior_nodes(n)
+        xs = np.concatenate([u, p[:, None]], axis=1)
+        b = np.zeros((n ** 3, 4))
+        b[inter, :3] = f[inter]
+        b[~inter] = xs[~inter]
+        x = _solve_tight(A, b.ravel()).reshape(-1, 4)
+        errs.append(np.abs(x[:, :3] - u).max())
+    # the pi-frequency field is under-resolved at n = 9; the 17 -> 33 ratio is near 4
+    assert errs[0] > errs[1] > errs[2] and 3.3 < errs[1] / errs[2] < 4.7, errs
+
+
+def test_block_view_matches_paper_worked_example():
+    """The node (block) view the oracle gathers from scalar CSR reproduces the block CSR
+    arrays printed for the paper's 6x6 example (Section 4, block-valued backend)."""
+    import json, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "bsr_worked_example.json")) as f:
+        ex = json.load(f)
+    c = ex["csr"]
+    A = sp.csr_matrix((c["val"], c["col"], c["ptr"]), shape=(6, 6))
+    ptr, cols, vals = [0], [], []
+    for i in range(3):
+        bc, bv = oracle.gather_block_row(A, 2, i)
+        cols += bc.tolist()
+        vals += bv.tolist()
+        ptr.append(len(cols))
+    assert ptr == ex["bsr"]["ptr"] and cols == ex["bsr"]["col"]
+    assert vals == ex["bsr"]["val"]
+    # BSR and scalar CSR products agree bitwise (ascending order, exact zeros add +0)
+    x = np.random.default_rng(0).normal(size=6)
+    y = np.zeros(6)
+    for i in range(3):
+        for t in range(ptr[i], ptr[i + 1]):
+            for r in range(2):
+                for q in range(2):
+                    y[2 * i + r] += vals[t][r][q] * x[2 * cols[t] + q]
+    assert np.array_equal(y, oracle.spmv(A, x))
+
+
+# ---------------------------------------------------------------- hierarchy
+
+def chain(m):
+    """1D chain: identity rows at both ends, [-1, 2, -1] inside (columns to the ends kept)."""
+    rows, cols, vals = [0, m - 1], [0, m - 1], [1.0, 1.0]
+    for i in range(1, m - 1):
+        rows += [i, i, i]
+        cols += [i - 1, i, i + 1]
+        vals += [-1.0, 2.0, -1.0]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m, m))
+
+
+def test_aggregation_1d_hand_derived():
+    s = oracle.Solver(chain(11), 1, coarse_enough=1, max_levels=2)
+    L0 = s.level(0)
+    assert list(L0["agg"]) == [-1, 0, 0, 1, 1, 1, 2, 2, 2, 2, -1]
+    assert L0["n_agg"] == 3
+
+
+def test_prolongator_1d_hand_derived():
+    """1D Laplacian: Gershgorin bound 2, omega = 2/3; P entries by hand."""
+    s = oracle.Solver(chain(11), 1, coarse_enough=1, max_levels=2)
+    L0 = s.level(0)
+    assert L0["omega"] == pytest.approx(2.0 / 3.0, rel=1e-15)
+    P = dense(L0["P"])
+    expect = np.zeros((11, 3))
+    expect[1] = [2 / 3, 0, 0]
+    expect[2] = [2 / 3, 1 / 3, 0]
+    expect[3] = [1 / 3, 2 / 3, 0]
+    expect[4] = [0, 1, 0]
+    expect[5] = [0, 2 / 3, 1 / 3]
+    expect[6] = [0, 1 / 3, 2 / 3]
+    expect[7] = [0, 0, 1]
+    expect[8] = [0, 0, 1]
+    expect[9] = [0, 0, 2 / 3]
+    assert np.allclose(P, expect, atol=1e-15)
+    # rows of A_F summing to zero keep P 1 = P_tent 1 = 1
+    assert np.allclose(P[3:9].sum(axis=1), 1.0)
+
+
+@pytest.fixture(scope="module")
+def small_hierarchy():
+    n = 8
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 7))
+    s = oracle.Solver(A, 4, coarse_enough=40)
+    return n, A, s
+
+
+def test_aggregates_partition_and_connected(small_hierarchy):
+    n, A, s = small_hierarchy
+    assert s.nlevels() >= 3
+    for l in range(s.nlevels() - 1):
+        L = s.level(l)
+        agg = L["agg"]
+        nagg = L["n_agg"]
+        used = agg[agg >= 0]
+        assert set(used.tolist()) == set(range(nagg))
+        # an aggregate is connected through nonzero blocks of A
+        Ab = dense(L["A"])
+        nn = Ab.shape[0] // 4
+        G = np.zeros((nn, nn), bool)
+        for i in range(nn):
+            for j in range(nn):
+                G[i, j] = np.any(Ab[4 * i:4 * i + 4, 4 * j:4 * j + 4] != 0)
+        for a in range(nagg):
+            mem = np.flatnonzero(agg == a)
+            seen = {mem[0]}
+            stack = [mem[0]]
+            while stack:
+                v = stack.pop()
+                for w in mem:
+                    if w not in seen and (G[v, w] or G[w, v]):
+                        seen.add(w)
+                        stack.append(w)
+            assert len(seen) == len(mem)
+
+
+def test_tentative_prolongator_invariants(small_hierarchy):
+    """P_tent^T P_tent = diag(|agg|) I_b and P_tent 1 = 1 on non-isolated rows, with
+    P_tent rebuilt from the aggregates (unnormalized identity blocks)."""
+    n, A, s = small_hierarchy
+    L = s.level(0)
+    agg = L["agg"]
+    nn = agg.size
+    rows = [4 * i + c for i in range(nn) if agg[i] >= 0 for c in range(4)]
+    cols = [4 * agg[i] + c for i in range(nn) if agg[i] >= 0 for c in range(4)]
+    Pt = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(4 * nn, 4 * L["n_agg"]))
+    sizes = np.bincount(agg[agg >= 0], minlength=L["n_agg"])
+    assert np.array_equal(dense(Pt.T @ Pt), np.kron(np.diag(sizes), np.eye(4)))
+    one = Pt @ np.ones(Pt.shape[1])
+    assert np.array_equal(one.reshape(-1, 4)[agg >= 0], np.ones(((agg >= 0).sum(), 4)))
+    # the smoothed prolongator keeps P_tent's block pattern plus strong neighbours' aggregates
+    P = dense(L["P"])
+    for i in range(nn):
+        if agg[i] < 0:
+            assert not np.any(P[4 * i:4 * i + 4])
+        else:
+            assert np.any(P[4 * i:4 * i + 4, 4 * agg[i]:4 * agg[i] + 4])
+
+
+def test_galerkin_identity(small_hierarchy):
+    """A_{l+1} = R_l A_l P_l against a dense triple product; R_l = P_l^T exactly."""
+    n, A, s = small_hierarchy
+    for l in range(s.nlevels() - 1):
+        L, Lc = s.level(l), s.level(l + 1)
+        P, R, Al = dense(L["P"]), dense(L["R"]), dense(L["A"])
+        assert np.array_equal(R, P.T)
+        Ac = R @ Al @ P
+        scale = np.abs(R).max() * np.abs(Al).max() * np.abs(P).max()
+        assert np.abs(dense(Lc["A"]) - Ac).max() <= 1e-13 * scale
+
+
+def test_spai0_closed_forms():
+    """Block SPAI0 M minimizes ||I - M A||_F over block-diagonal M: random perturbations
+    never do better, and the residual of each row-block least-squares problem is
+    orthogonal to that block row (normal equations)."""
+    rng = np.random.default_rng(1)
+    nb, b = 5, 3
+    blocks = [rng.normal(size=(b, b)) + 4 * np.eye(b) for _ in range(nb)]
+    A = sp.random(nb * b, nb * b, density=0.3, random_state=2) + sp.csr_matrix(sp.block_diag(blocks))
+    A = sp.csr_matrix(A)
+    s = oracle.Solver(A, b, coarse_enough=1, max_levels=2)
+    if s.nlevels() < 2:
+        pytest.skip("random matrix did not coarsen")
+    M = s.level(0)["M"]
+    Ad_ = dense(A)
+    Mfull = sp.block_diag(list(M)).toarray()
+    base = np.linalg.norm(np.eye(nb * b) - Mfull @ Ad_)
+    for t in range(20):
+        Pm = Mfull + 1e-3 * sp.block_diag([rng.normal(size=(b, b)) for _ in range(nb)]).toarray()
+        assert np.linalg.norm(np.eye(nb * b) - Pm @ Ad_) >= base
+    # the normal equations of the row-block least squares at the optimum
+    for i in range(nb):
+        Ai = Ad_[b * i:b * i + b]
+        Ei = np.zeros_like(Ai)
+        Ei[:, b * i:b * i + b] = np.eye(b)
+        assert np.allclose((Ei - M[i] @ Ai) @ Ai.T, 0, atol=1e-12)
+
+
+def test_spai0_scalar_reduces():
+    A = chain(11) + sp.diags(np.linspace(0.1, 0.5, 11))
+    A = sp.csr_matrix(A)
+    s = oracle.Solver(A, 1, coarse_enough=1, max_levels=2)
+    M = s.level(0)["M"][:, 0, 0]
+    D = dense(A)
+    assert np.allclose(M, np.diag(D) / (D ** 2).sum(axis=1), rtol=1e-15)
+
+
+def vcycle_dense(s, l, nlev):
+    """Dense V(1,1) operator from its definition: B = M + (I - M A) M
+    + (I - M A) P B_c R (I - A M), with B_c the exact inverse at the coarsest level."""
+    L = s.level(l)
+    A = dense(L["A"])
+    if l == nlev - 1:
+        return np.linalg.inv(A)
+    M = sp.block_diag(list(L["M"])).toarray()
+    P, R = dense(L["P"]), dense(L["R"])
+    Bc = vcycle_dense(s, l + 1, nlev)
+    I = np.eye(A.shape[0])
+    return M + (I - M @ A) @ M + (I - M @ A) @ P @ Bc @ R @ (I - A @ M)
+
+
+def test_vcycle_brute_force(small_hierarchy):
+    n, A, s = small_hierarchy
+    B = vcycle_dense(s, 0, s.nlevels())
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.normal(size=A.shape[0])
+        z = s.precond(r)
+        assert np.allclose(z, B @ r, rtol=1e-10, atol=1e-12 * np.abs(B @ r).max())
+
+
+def test_transposed_vcycle_is_adjoint(small_hierarchy):
+    """<y, B x> = <B^T y, x> for the transposed-cycle preconditioner."""
+    n, A, s = small_hierarchy
+    rng = np.random.default_rng(4)
+    x, y = rng.normal(size=A.shape[0]), rng.normal(size=A.shape[0])
+    lhs = y @ s.precond(x)
+    rhs = s.precond(y, transposed=True) @ x
+    assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + 1)
+
+
+def test_single_level_is_exact():
+    """coarse_enough >= unknowns: the preconditioner is the exact inverse and BiCGStab
+    converges in one iteration."""
+    n = 4
+    A = oracle.stokes_matrix(n)
+    s = oracle.Solver(A, 4, coarse_enough=10 ** 6)
+    assert s.nlevels() == 1
+    b = S.mms_rhs(n)
+    x, info = s.solve(b, 1e-12)
+    assert info["iters"] == 1 and info["converged"]
+    xd = np.linalg.solve(dense(A), b)
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+# ---------------------------------------------------------------- Krylov
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+@pytest.mark.parametrize("krylov", [oracle.BICGSTAB, oracle.FGMRES])
+def test_solver_against_dense_lu(n, krylov):
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, n))
+    xs = S.mms_solution(n)
+    b = A @ xs
+    s = oracle.Solver(A, 4, krylov=krylov, coarse_enough=100)
+    x, info = s.solve(b, 1e-12)
+    xd = np.linalg.solve(dense(A), b)
+    assert info["converged"] and info["rel_resid"] <= 1e-12
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert np.linalg.norm(xd - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_fgmres_terminates_in_n_steps():
+    rng = np.random.default_rng(5)
+    m = 12
+    A = sp.csr_matrix(rng.normal(size=(m, m)) + 6 * np.eye(m))
+    s = oracle.Solver(A, 1, kind=oracle.KIND_IDENTITY, krylov=oracle.FGMRES, fgmres_m=m)
+    b = rng.normal(size=m)
+    x, info = s.solve(b, 1e-13)
+    assert info["iters"] <= m and info["converged"]
+    assert np.allclose(x, np.linalg.solve(A.toarray(), b), rtol=1e-11)
+
+
+def test_bicgstab_edge_cases():
+    n = 5
+    A = oracle.stokes_matrix(n)
+    s = oracle.Solver(A, 4, maxiter=1, max_restarts=0, coarse_enough=40)
+    x, info = s.solve(np.zeros(A.shape[0]))
+    assert info["converged"] and info["iters"] == 0 and not np.any(x)
+    x, info = s.solve(S.mms_rhs(n), 1e-14)
+    assert not info["converged"] and info["iters"] == 1
+
+
+# ---------------------------------------------------------------- Schur
+
+def test_schur_complement_closed_form():
+    """Constant viscosity: the interior stencil of S = C - B_lo diag(A_uu)^-1 B_up is
+    -6.25 at the node, 1 at the six neighbours and +1/24 at distance two."""
+    n = 9
+    A = oracle.stokes_matrix(n)
+    s = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES)
+    Sh = dense(s.level(0, which=1)["A"])
+    i = j = k = 4
+    g = i + n * (j + n * k)
+    row = Sh[g]
+    assert row[g] == pytest.approx(-6.25, rel=1e-14)
+    for d in (1, n, n * n):
+        assert row[g + d] == pytest.approx(1.0, rel=1e-14)
+        assert row[g - d] == pytest.approx(1.0, rel=1e-14)
+        assert row[g + 2 * d] == pytest.approx(1 / 24, rel=1e-12)
+        assert row[g - 2 * d] == pytest.approx(1 / 24, rel=1e-12)
+    assert np.count_nonzero(row) == 13
+
+
+def test_schur_apply_is_block_factorization():
+    """With single-level (exact) inner solves, the Schur preconditioner equals the dense
+    block factorization: z_p = S^-1 (r_p - B_lo A_uu^-1 r_u), z_u = A_uu^-1 (r_u - B_up z_p)."""
+    n = 5
+    A = oracle.stokes_matrix(n, S.theta_field(n, 1.0, 9))
+    s = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES, coarse_enough=10 ** 6)
+    D = dense(A)
+    nn = n ** 3
+    u = np.array([4 * g + c for g in range(nn) for c in range(3)])
+    p = 4 * np.arange(nn) + 3
+    Auu, Bup, Blo, Cc = D[np.ix_(u, u)], D[np.ix_(u, p)], D[np.ix_(p, u)], D[np.ix_(p, p)]
+    Sh = Cc - Blo @ np.diag(1 / np.diag(Auu)) @ Bup
+    assert np.allclose(dense(s.level(0, which=1)["A"]), Sh, rtol=1e-14, atol=1e-14)
+    r = np.random.default_rng(6).normal(size=4 * nn)
+    zp = np.linalg.solve(Sh, r[p] - Blo @ np.linalg.solve(Auu, r[u]))
+    zu = np.linalg.solve(Auu, r[u] - Bup @ zp)
+    z = s.precond(r)
+    assert np.allclose(z[u], zu, rtol=1e-9, atol=1e-12)
+    assert np.allclose(z[p], zp, rtol=1e-9, atol=1e-12)
+
+
+def test_schur_exact_complement_one_iteration():
+    """If the pressure operator were the exact Schur complement C - B_lo A_uu^-1 B_up, the
+    factorization would be A^-1 (eqs. SchurP/SchurU); the dense check of that identity pins
+    the order of the three steps used by the oracle."""
+    n = 4
+    A = dense(oracle.stokes_matrix(n, S.theta_field(n, 1.0, 9)))
+    nn = n ** 3
+    u = np.array([4 * g + c for g in range(nn) for c in range(3)])
+    p = 4 * np.arange(nn) + 3
+    Auu, Bup, Blo, Cc = A[np.ix_(u, u)], A[np.ix_(u, p)], A[np.ix_(p, u)], A[np.ix_(p, p)]
+    Sx = Cc - Blo @ np.linalg.solve(Auu, Bup)
+    r = np.random.default_rng(7).normal(size=4 * nn)
+    zp = np.linalg.solve(Sx, r[p] - Blo @ np.linalg.solve(Auu, r[u]))
+    zu = np.linalg.solve(Auu, r[u] - Bup @ zp)
+    z = np.empty(4 * nn)
+    z[u], z[p] = zu, zp
+    assert np.allclose(z, np.linalg.solve(A, r), rtol=1e-9, atol=1e-12)
+
+
+# ---------------------------------------------------------------- gradient
+
+def test_gradient_is_exact_linear_derivative():
+    """A is linear in theta, so dL/dtheta_e = -lambda^T (A(theta + e_e) - A(theta)) x
+    exactly; the edge formula must agree for every cell."""
+    n = 5
+    th = S.theta_field(n, 0.5, 12)
+    A = oracle.stokes_matrix(n, th)
+    rng = np.random.default_rng(8)
+    x, lam = rng.normal(size=A.shape[0]), rng.normal(size=A.shape[0])
+    g = oracle.theta_gradient(n, lam, x)
+    for e in range(0, (n - 1) ** 3, 3):
+        t2 = th.copy()
+        t2[e] += 1.0
+        dA = oracle.stokes_matrix(n, t2) - A
+        assert g[e] == pytest.approx(-(lam @ (dA @ x)), rel=1e-9, abs=1e-9)
+
+
+def test_gradient_matches_central_fd():
+    n = 6
+    th = S.theta_field(n, 0.5, 13)
+    thr = S.theta_field(n, 0.5, 14)
+    b = S.mms_rhs(n)
+
+    def solve(t):
+        s = oracle.Solver(oracle.stokes_matrix(n, t), 4, coarse_enough=100)
+        x, info = s.solve(b, 1e-13)
+        assert info["converged"]
+        return x, s
+
+    xt, _ = solve(thr)
+    x, s = solve(th)
+    lam, info = s.solve(x - xt, 1e-13, transposed=True)
+    assert info["converged"]
+    g = oracle.theta_gradient(n, lam, x)
+    loss = lambda t: 0.5 * np.sum((solve(t)[0] - xt) ** 2)
+    for e in S.fd_cells(n, 5, 15):
+        d = np.zeros_like(th)
+        d[e] = 1e-6
+        fd = (loss(th + d) - loss(th - d)) / 2e-6
+        assert fd == pytest.approx(g[e], rel=1e-5, abs=1e-9)
