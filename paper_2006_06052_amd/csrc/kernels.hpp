@@ -1,0 +1,612 @@
+// gfx950 kernels of the solve phase.
+//
+// The solve phase of the paper's solver is expressed in a handful of backend
+// primitives: the sparse matrix-vector product inside the residual, inner
+// products and linear combinations of vectors (Section 2.3), applied with
+// small statically sized blocks as values (Section 2.4, Section 4 block-valued
+// backend) and, for the nested preconditioner, in single precision (Section 4,
+// mixed-precision variant: it pays because the solve is memory bound).
+//
+// Every kernel here streams HBM; none is a dense contraction, so none uses
+// MFMA.  Layout and mapping choices for CDNA4:
+//  - one block row of a BR x BC block matrix is owned by a group of BR*S lanes
+//    of a 64-wide wavefront: lane (s, r) takes scalar row r of every S-th
+//    block of the row, so BR adjacent lanes read one block row-contiguously
+//    and S*BR adjacent lanes read S consecutive blocks; the S partial sums of
+//    a row are combined with cross-lane shuffles;
+//  - block values and column indices are read with non-temporal loads (they
+//    are streamed exactly once), which keeps the gathered x vector resident in
+//    L2 and the Infinity Cache;
+//  - workgroup ids are remapped so that each of the 8 XCDs (each with its own
+//    L2) processes one contiguous range of block rows, keeping the x windows of
+//    neighbouring rows in the same L2;
+//  - every reduction is two-stage with a fixed order (per-workgroup partials,
+//    then one finalizing workgroup), so results are bitwise reproducible.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgk {
+
+struct bf16 {
+  uint16_t u;
+};
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+
+constexpr int WG = 256;          // threads per workgroup (4 waves)
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t u) {
+  return __uint_as_float(((uint32_t)u) << 16);
+}
+
+// ---- value loads -----------------------------------------------------------
+
+// Row r of a stored block: BC consecutive values, streamed (non-temporal).
+template <int BC, class TV, class TA>
+__device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
+  if constexpr (sizeof(TV) == 8 && BC == 4) {
+    const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    const d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p) + 1);
+    out[0] = a.x; out[1] = a.y; out[2] = b.x; out[3] = b.y;
+  } else if constexpr (sizeof(TV) == 4 && BC == 4) {
+    const f4v a = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  } else if constexpr (sizeof(TV) == 2 && BC == 4) {
+    const u2v a = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+    out[0] = __uint_as_float(a.x << 16);
+    out[1] = __uint_as_float(a.x & 0xffff0000u);
+    out[2] = __uint_as_float(a.y << 16);
+    out[3] = __uint_as_float(a.y & 0xffff0000u);
+  } else if constexpr (sizeof(TV) == 2) {
+    const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
+#pragma unroll
+    for (int c = 0; c < BC; ++c) out[c] = (TA)bf16_to_f32(__builtin_nontemporal_load(q + c));
+  } else {
+#pragma unroll
+    for (int c = 0; c < BC; ++c) out[c] = (TA)__builtin_nontemporal_load(p + c);
+  }
+}
+
+// Single value (used by the transposed product, which reads block columns).
+template <class TV, class TA>
+__device__ __forceinline__ TA load_val(const TV* __restrict__ p) {
+  if constexpr (sizeof(TV) == 2) {
+    return (TA)bf16_to_f32(__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p)));
+  } else {
+    return (TA)__builtin_nontemporal_load(p);
+  }
+}
+
+// Block of x: BC consecutive entries (cached loads; x is gathered repeatedly).
+template <int BC, class TX, class TA>
+__device__ __forceinline__ void load_x(const TX* __restrict__ p, TA* out) {
+  if constexpr (sizeof(TX) == 8 && BC == 4) {
+    const d2v a = *reinterpret_cast<const d2v*>(p);
+    const d2v b = *(reinterpret_cast<const d2v*>(p) + 1);
+    out[0] = a.x; out[1] = a.y; out[2] = b.x; out[3] = b.y;
+  } else if constexpr (sizeof(TX) == 4 && BC == 4) {
+    const f4v a = *reinterpret_cast<const f4v*>(p);
+    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  } else {
+#pragma unroll
+    for (int c = 0; c < BC; ++c) out[c] = (TA)p[c];
+  }
+}
+
+// Logical workgroup id: XCD x (hardware places workgroup w on XCD w % 8)
+// receives one contiguous range of logical ids.
+__device__ __forceinline__ int xcd_remap(int w, int nwg) {
+  const int q = nwg >> 3, rem = nwg & 7, x = w & 7;
+  return x * q + min(x, rem) + (w >> 3);
+}
+
+// ---- block-row engine --------------------------------------------------------
+
+template <int BR, int S>
+struct RowMap {
+  static constexpr int G = BR * S;              // lanes per block row
+  static constexpr int GPW = WAVE / G;          // block rows per wave
+  static constexpr int ROWS = GPW * (WG / WAVE);// block rows per workgroup
+};
+
+struct LaneInfo {
+  int i;        // block row (may be >= nbr for idle groups)
+  int r, s;     // scalar row inside the block, split index
+  int gbase;    // first lane of this group inside the wave
+  bool active;  // lane belongs to a group
+};
+
+template <int BR, int S>
+__device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
+  using M = RowMap<BR, S>;
+  LaneInfo L;
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x >> 6;
+  const int g = lane / M::G, w = lane - g * M::G;
+  L.active = g < M::GPW;
+  L.s = w / BR;
+  L.r = w - L.s * BR;
+  L.gbase = g * M::G;
+  L.i = (logical_wg * (WG / WAVE) + wave) * M::GPW + g;
+  return L;
+}
+
+// Partial sum of row r of block row i over blocks s, s+S, ...; combined over
+// the S lanes of the row (result valid in the s == 0 lane).
+template <int BR, int BC, int S, bool TRANS, class TV, class TX, class TA>
+__device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int* __restrict__ ptr,
+                                          const int* __restrict__ col, const int* __restrict__ blk,
+                                          const TV* __restrict__ val, const TX* __restrict__ x) {
+  TA acc = 0;
+  if (L.active && L.i < nbr) {
+    const int k0 = ptr[L.i], k1 = ptr[L.i + 1];
+    for (int k = k0 + L.s; k < k1; k += S) {
+      const int j = __builtin_nontemporal_load(col + k);
+      TA xv[BC];
+      load_x<BC, TX, TA>(x + (size_t)j * BC, xv);
+      if constexpr (!TRANS) {
+        TA v[BC];
+        load_vals<BC, TV, TA>(val + (size_t)k * (BR * BC) + L.r * BC, v);
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc += v[c] * xv[c];
+      } else {
+        // Block kb of A (BC x BR) read by columns: (A^T)[r][c] = A_kb[c][r].
+        const int kb = __builtin_nontemporal_load(blk + k);
+        const TV* b = val + (size_t)kb * (BR * BC);
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc += load_val<TV, TA>(b + c * BR + L.r) * xv[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int m = S / 2; m >= 1; m >>= 1) acc += __shfl_down(acc, BR * m, WAVE);
+  return acc;
+}
+
+// Deterministic workgroup sum of up to two values; thread 0 returns them.
+template <class T>
+__device__ __forceinline__ void wg_sum2(T& a, T& b) {
+  __shared__ T sa[WG / WAVE], sb[WG / WAVE];
+#pragma unroll
+  for (int m = WAVE / 2; m >= 1; m >>= 1) {
+    a += __shfl_xor(a, m, WAVE);
+    b += __shfl_xor(b, m, WAVE);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    sa[wave] = a;
+    sb[wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = sa[0];
+    b = sb[0];
+#pragma unroll
+    for (int w = 1; w < WG / WAVE; ++w) {
+      a += sa[w];
+      b += sb[w];
+    }
+  }
+}
+
+// ---- sparse kernels ------------------------------------------------------------
+
+// y = alpha A x + beta y   (beta == 0: y is not read).
+// With dots != 0, also per-workgroup partials of <w1, y> and (dots == 2)
+// <y, y> for the fused Krylov products (FP64 outer operator).
+template <int BR, int BC, int S, bool TRANS, class TV, class TX, class TY, class TA>
+__global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ ptr,
+                                             const int* __restrict__ col,
+                                             const int* __restrict__ blk,
+                                             const TV* __restrict__ val,
+                                             const TX* __restrict__ x, TY* __restrict__ y,
+                                             TA alpha, TA beta, int dots,
+                                             const double* __restrict__ w1,
+                                             const double* __restrict__ w2,
+                                             double* __restrict__ part) {
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const LaneInfo L = lane_info<BR, S>(lw);
+  TA acc = row_product<BR, BC, S, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, x);
+  double d1 = 0.0, d2 = 0.0;
+  if (L.active && L.s == 0 && L.i < nbr) {
+    const size_t row = (size_t)L.i * BR + L.r;
+    TA out = alpha * acc;
+    if (beta != TA(0)) out += beta * (TA)y[row];
+    y[row] = (TY)out;
+    if (dots) {
+      d1 = w1[row] * (double)out;
+      if (dots == 2) d2 = (double)out * (double)out;
+    }
+  }
+  if (dots) {
+    wg_sum2(d1, d2);
+    if (threadIdx.x == 0) {
+      part[lw] = d1;
+      if (dots == 2) part[gridDim.x + lw] = d2;
+    }
+  }
+}
+
+// t = f - A z  (A may be rectangular: BR x BC blocks).
+template <int BR, int BC, int S, bool TRANS, class TV, class TX, class TF, class TA>
+__global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict__ ptr,
+                                                 const int* __restrict__ col,
+                                                 const int* __restrict__ blk,
+                                                 const TV* __restrict__ val,
+                                                 const TF* __restrict__ f,
+                                                 const TX* __restrict__ z, TX* __restrict__ t) {
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const LaneInfo L = lane_info<BR, S>(lw);
+  TA acc = row_product<BR, BC, S, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
+  if (L.active && L.s == 0 && L.i < nbr) {
+    const size_t row = (size_t)L.i * BR + L.r;
+    t[row] = (TX)((TA)f[row] - acc);
+  }
+}
+
+// Post-smoothing: zout = z + M (f - A z), M block diagonal (M^T when TRANS).
+template <int BR, int S, bool TRANS, class TV, class TX, class TF, class TO, class TM, class TA>
+__global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
+                                               const int* __restrict__ col,
+                                               const int* __restrict__ blk,
+                                               const TV* __restrict__ val,
+                                               const TM* __restrict__ M,
+                                               const TF* __restrict__ f,
+                                               const TX* __restrict__ z, TO* __restrict__ zout) {
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const LaneInfo L = lane_info<BR, S>(lw);
+  TA acc = row_product<BR, BR, S, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
+  const bool own = L.active && L.i < nbr;
+  TA res = 0;
+  if (own && L.s == 0) {
+    const size_t row = (size_t)L.i * BR + L.r;
+    res = (TA)f[row] - acc;
+  }
+  // Gather the BR residuals of the block row from the s == 0 lanes.
+  TA rv[BR];
+#pragma unroll
+  for (int c = 0; c < BR; ++c) rv[c] = __shfl(res, L.gbase + c, WAVE);
+  if (own && L.s == 0) {
+    const size_t row = (size_t)L.i * BR + L.r;
+    const TM* m = M + (size_t)L.i * BR * BR;
+    TA out = (TA)z[row];
+#pragma unroll
+    for (int c = 0; c < BR; ++c)
+      out += (TA)(TRANS ? m[c * BR + L.r] : m[L.r * BR + c]) * rv[c];
+    zout[row] = (TO)out;
+  }
+}
+
+// Pre-smoothing from a zero guess: z = M f (block diagonal; M^T when trans).
+template <int B, class TM, class TF, class TX, class TA>
+__global__ __launch_bounds__(WG) void k_block_diag(int nbr, int trans, const TM* __restrict__ M,
+                                                   const TF* __restrict__ f,
+                                                   TX* __restrict__ z) {
+  const size_t row = (size_t)blockIdx.x * WG + threadIdx.x;
+  if (row >= (size_t)nbr * B) return;
+  const size_t i = row / B;
+  const int r = (int)(row - i * B);
+  const TM* m = M + i * B * B;
+  const TF* fi = f + i * B;
+  TA acc = 0;
+#pragma unroll
+  for (int c = 0; c < B; ++c) acc += (TA)(trans ? m[c * B + r] : m[r * B + c]) * (TA)fi[c];
+  z[row] = (TX)acc;
+}
+
+// ---- dense coarsest-level solve -------------------------------------------------
+
+// z = Cinv r, Cinv n x n FP64 row-major; one workgroup per row.
+template <class TI, class TO>
+__global__ __launch_bounds__(WG) void k_coarse_gemv(int n, const double* __restrict__ Cinv,
+                                                    const TI* __restrict__ r,
+                                                    TO* __restrict__ z) {
+  const int i = blockIdx.x;
+  const double* a = Cinv + (size_t)i * n;
+  double s = 0.0, dummy = 0.0;
+  for (int j = threadIdx.x; j < n; j += WG) s += a[j] * (double)r[j];
+  wg_sum2(s, dummy);
+  if (threadIdx.x == 0) z[i] = (TO)s;
+}
+
+// ---- vector kernels (FP64 Krylov) --------------------------------------------
+
+// Grid-stride loop bounds shared by the reductions: the grid has a fixed size
+// per vector length, so partial counts are fixed and sums reproducible.
+#define GRID_STRIDE(i, n) \
+  for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < (size_t)(n); i += (size_t)gridDim.x * WG)
+
+// part[blk] = <a,b>, part[grid + blk] = <c,d> (second dot optional).
+__global__ __launch_bounds__(WG) void k_dot2(size_t n, const double* __restrict__ a,
+                                             const double* __restrict__ b,
+                                             const double* __restrict__ c,
+                                             const double* __restrict__ d,
+                                             double* __restrict__ part) {
+  double s1 = 0.0, s2 = 0.0;
+  GRID_STRIDE(i, n) {
+    s1 += a[i] * b[i];
+    if (c) s2 += c[i] * d[i];
+  }
+  wg_sum2(s1, s2);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    if (c) part[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// Device-resident scalars of the Krylov iteration.
+enum Sc {
+  SC_RHO = 0,    // rho of the previous iteration
+  SC_RHO1 = 1,   // (rhat, r) of the current iteration
+  SC_ALPHA = 2,
+  SC_OMEGA = 3,
+  SC_RV = 4,     // (rhat, v)
+  SC_SS = 5,     // ||s||^2
+  SC_TS = 6,
+  SC_TT = 7,
+  SC_RR = 8,     // ||r||^2
+  SC_TMP = 9,
+  SC_TMP2 = 10,
+  SC_COUNT = 16
+};
+
+enum FinOp {
+  FIN_STORE1 = 0,   // sc[i0] = sum part0
+  FIN_STORE2 = 1,   // sc[i0] = sum part0, sc[i1] = sum part1
+  FIN_ALPHA = 2,    // sc[RV] = sum; alpha = rho1 / rv
+  FIN_OMEGA = 3,    // ts, tt -> omega = ts / tt (0 if tt == 0)
+  FIN_RHO = 4       // rr, rho1' -> rho = rho1, rho1 = rho1'
+};
+
+__global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int count,
+                                                 int two, int op, int i0, int i1,
+                                                 double* __restrict__ sc) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < count; k += WG) {
+    a += part[k];
+    if (two) b += part[count + k];
+  }
+  wg_sum2(a, b);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case FIN_STORE1: sc[i0] = a; break;
+    case FIN_STORE2: sc[i0] = a; sc[i1] = b; break;
+    case FIN_ALPHA: sc[SC_RV] = a; sc[SC_ALPHA] = sc[SC_RHO1] / a; break;
+    case FIN_OMEGA:
+      sc[SC_TS] = a;
+      sc[SC_TT] = b;
+      sc[SC_OMEGA] = b != 0.0 ? a / b : 0.0;
+      break;
+    case FIN_RHO:
+      sc[SC_RR] = a;
+      sc[SC_RHO] = sc[SC_RHO1];
+      sc[SC_RHO1] = b;
+      break;
+  }
+}
+
+// p = r + beta (p - omega v), beta = (rho1 / rho) (alpha / omega).
+__global__ __launch_bounds__(WG) void k_bicg_p(size_t n, const double* __restrict__ sc,
+                                               const double* __restrict__ r,
+                                               const double* __restrict__ v,
+                                               double* __restrict__ p) {
+  const double beta = (sc[SC_RHO1] / sc[SC_RHO]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+  const double om = sc[SC_OMEGA];
+  GRID_STRIDE(i, n) p[i] = r[i] + beta * (p[i] - om * v[i]);
+}
+
+// s = r - alpha v; x += alpha phat; partials of ||s||^2.
+__global__ __launch_bounds__(WG) void k_bicg_s(size_t n, const double* __restrict__ sc,
+                                               const double* __restrict__ r,
+                                               const double* __restrict__ v,
+                                               const double* __restrict__ ph,
+                                               double* __restrict__ s, double* __restrict__ x,
+                                               double* __restrict__ part) {
+  const double al = sc[SC_ALPHA];
+  double ss = 0.0, dummy = 0.0;
+  GRID_STRIDE(i, n) {
+    const double si = r[i] - al * v[i];
+    s[i] = si;
+    x[i] += al * ph[i];
+    ss += si * si;
+  }
+  wg_sum2(ss, dummy);
+  if (threadIdx.x == 0) part[blockIdx.x] = ss;
+}
+
+// x += omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
+__global__ __launch_bounds__(WG) void k_bicg_xr(size_t n, const double* __restrict__ sc,
+                                                const double* __restrict__ s,
+                                                const double* __restrict__ t,
+                                                const double* __restrict__ sh,
+                                                const double* __restrict__ rh,
+                                                double* __restrict__ x, double* __restrict__ r,
+                                                double* __restrict__ part) {
+  const double om = sc[SC_OMEGA];
+  double rr = 0.0, rho = 0.0;
+  GRID_STRIDE(i, n) {
+    x[i] += om * sh[i];
+    const double ri = s[i] - om * t[i];
+    r[i] = ri;
+    rr += ri * ri;
+    rho += rh[i] * ri;
+  }
+  wg_sum2(rr, rho);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rr;
+    part[gridDim.x + blockIdx.x] = rho;
+  }
+}
+
+// y = a * x (a read from sc[ia] inverted when inv) or y = x.
+__global__ __launch_bounds__(WG) void k_scale(size_t n, const double* __restrict__ sc, int ia,
+                                              int sqrt_inv, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const double a = sqrt_inv ? 1.0 / sqrt(sc[ia]) : sc[ia];
+  GRID_STRIDE(i, n) y[i] = a * x[i];
+}
+
+__global__ __launch_bounds__(WG) void k_scal(size_t n, double a, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  GRID_STRIDE(i, n) y[i] = a * x[i];
+}
+
+__global__ __launch_bounds__(WG) void k_copy(size_t n, const double* __restrict__ x,
+                                             double* __restrict__ y) {
+  GRID_STRIDE(i, n) y[i] = x[i];
+}
+
+__global__ __launch_bounds__(WG) void k_fill(size_t n, double v, double* __restrict__ y) {
+  GRID_STRIDE(i, n) y[i] = v;
+}
+
+// ---- FGMRES: classical Gram-Schmidt with one reorthogonalization -------------
+
+constexpr int MAXM = 32;
+
+// part[q * grid + blk] = <V_q, w> for q < m (V_q = V + q * ld).
+__global__ __launch_bounds__(WG) void k_multidot(size_t n, int m, const double* __restrict__ V,
+                                                 size_t ld, const double* __restrict__ w,
+                                                 double* __restrict__ part) {
+  double acc[MAXM];
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) acc[q] = 0.0;
+  GRID_STRIDE(i, n) {
+    const double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < MAXM; ++q)
+      if (q < m) acc[q] += V[q * ld + i] * wi;
+  }
+  for (int q = 0; q < m; ++q) {
+    double a = acc[q], dummy = 0.0;
+    wg_sum2(a, dummy);
+    if (threadIdx.x == 0) part[(size_t)q * gridDim.x + blockIdx.x] = a;
+    __syncthreads();
+  }
+}
+
+// h[q] = sum of the partials of dot q (count each); h2 accumulates into hsum.
+__global__ __launch_bounds__(WG) void k_multifin(const double* __restrict__ part, int count,
+                                                 int m, double* __restrict__ h,
+                                                 double* __restrict__ hsum, int add) {
+  for (int q = 0; q < m; ++q) {
+    double a = 0.0, dummy = 0.0;
+    for (int k = threadIdx.x; k < count; k += WG) a += part[(size_t)q * count + k];
+    wg_sum2(a, dummy);
+    if (threadIdx.x == 0) {
+      h[q] = a;
+      hsum[q] = add ? hsum[q] + a : a;
+    }
+    __syncthreads();
+  }
+}
+
+// w -= V h (m vectors), optionally partials of ||w||^2.
+__global__ __launch_bounds__(WG) void k_multiaxpy(size_t n, int m, const double* __restrict__ V,
+                                                  size_t ld, const double* __restrict__ h,
+                                                  double* __restrict__ w,
+                                                  double* __restrict__ part) {
+  double ss = 0.0, dummy = 0.0;
+  GRID_STRIDE(i, n) {
+    double wi = w[i];
+    for (int q = 0; q < m; ++q) wi -= h[q] * V[q * ld + i];
+    w[i] = wi;
+    ss += wi * wi;
+  }
+  if (part) {
+    wg_sum2(ss, dummy);
+    if (threadIdx.x == 0) part[blockIdx.x] = ss;
+  }
+}
+
+// x += sum_q y_q Z_q (y on the device).
+__global__ __launch_bounds__(WG) void k_update_x(size_t n, int m, const double* __restrict__ Z,
+                                                 size_t ld, const double* __restrict__ y,
+                                                 double* __restrict__ x) {
+  GRID_STRIDE(i, n) {
+    double xi = x[i];
+    for (int q = 0; q < m; ++q) xi += y[q] * Z[q * ld + i];
+    x[i] = xi;
+  }
+}
+
+// ---- Schur split / merge --------------------------------------------------------
+
+// Interleaved [u,v,w,p] FP64 -> velocity (3 per node) and pressure (1 per node).
+template <class TX>
+__global__ __launch_bounds__(WG) void k_split(size_t nn, const double* __restrict__ r,
+                                              TX* __restrict__ ru, TX* __restrict__ rp) {
+  GRID_STRIDE(g, nn) {
+    ru[3 * g] = (TX)r[4 * g];
+    ru[3 * g + 1] = (TX)r[4 * g + 1];
+    ru[3 * g + 2] = (TX)r[4 * g + 2];
+    rp[g] = (TX)r[4 * g + 3];
+  }
+}
+
+template <class TX>
+__global__ __launch_bounds__(WG) void k_merge(size_t nn, const TX* __restrict__ zu,
+                                              const TX* __restrict__ zp, double* __restrict__ z) {
+  GRID_STRIDE(g, nn) {
+    z[4 * g] = (double)zu[3 * g];
+    z[4 * g + 1] = (double)zu[3 * g + 1];
+    z[4 * g + 2] = (double)zu[3 * g + 2];
+    z[4 * g + 3] = (double)zp[g];
+  }
+}
+
+// ---- gradients ---------------------------------------------------------------
+
+// G_k = -lambda_I x_J^T for every stored b x b block k = (I, J).
+template <int B>
+__global__ __launch_bounds__(WG) void k_bsr_grad(int nbr, const int* __restrict__ ptr,
+                                                 const int* __restrict__ col,
+                                                 const double* __restrict__ lam,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ g) {
+  const int i = blockIdx.x * (WG / (B * B)) + threadIdx.x / (B * B);
+  const int e = threadIdx.x % (B * B);
+  if (i >= nbr || threadIdx.x >= (WG / (B * B)) * B * B) return;
+  const int r = e / B, c = e % B;
+  const double li = lam[(size_t)i * B + r];
+  for (int k = ptr[i]; k < ptr[i + 1]; ++k) g[(size_t)k * B * B + e] = -li * x[(size_t)col[k] * B + c];
+}
+
+// Per-cell viscosity gradient of the finite-difference Stokes operator.
+__global__ __launch_bounds__(WG) void k_theta_grad(int n, const double* __restrict__ lam,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ g) {
+  const int nc = n - 1;
+  const size_t e = (size_t)blockIdx.x * WG + threadIdx.x;
+  if (e >= (size_t)nc * nc * nc) return;
+  const int ci = (int)(e % nc), cj = (int)((e / nc) % nc), ck = (int)(e / ((size_t)nc * nc));
+  const double inv_h2 = (double)nc * (double)nc;
+  auto inner = [&](int i, int j, int k) {
+    return i > 0 && j > 0 && k > 0 && i < n - 1 && j < n - 1 && k < n - 1;
+  };
+  double sum = 0.0;
+  for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        int p[3] = {ci, cj, ck};
+        p[(d + 1) % 3] += a;
+        p[(d + 2) % 3] += b;
+        int q[3] = {p[0], p[1], p[2]};
+        q[d] += 1;
+        const size_t gp = p[0] + (size_t)n * (p[1] + (size_t)n * p[2]);
+        const size_t gq = q[0] + (size_t)n * (q[1] + (size_t)n * q[2]);
+        double dmu = 0.0;
+        if (inner(p[0], p[1], p[2]))
+          for (int c = 0; c < 3; ++c) dmu += lam[4 * gp + c] * (x[4 * gp + c] - x[4 * gq + c]);
+        if (inner(q[0], q[1], q[2]))
+          for (int c = 0; c < 3; ++c) dmu += lam[4 * gq + c] * (x[4 * gq + c] - x[4 * gp + c]);
+        sum -= inv_h2 * dmu;
+      }
+  g[e] = 0.25 * sum;
+}
+
+}  // namespace mgk

@@ -1,0 +1,1197 @@
+// Solve-phase orchestration and the C ABI of libmgk.
+//
+// Setup runs on the host in FP64 (host.hpp) and is then moved to the device
+// once (Section 2.3: setup with built-in structures, then transfer to the
+// backend).  The solve phase composes the kernels of kernels.hpp:
+//   V(1,1) cycle per level: z = M r; t = r - A z; r_c = R t; recurse;
+//     z += P z_c; z_out = z + M (r - A z); coarsest level: dense FP64 inverse;
+//   BiCGStab (right preconditioned) with every scalar kept on the device and
+//     convergence read back through pinned memory while the next stage is
+//     already queued, so the host never drains the stream inside an
+//     iteration;
+//   flexible GMRES(m) with classical Gram-Schmidt plus one reorthogonalization
+//     (multi-dot kernels) and host Givens rotations;
+//   the Schur pressure correction: one velocity cycle, the pressure cycle on
+//     r_p - B_lo z_u, and a second velocity cycle on r_u - B_up z_p (Section 4,
+//     eqs. SchurP and SchurU).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mgk.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+namespace mgk {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCK(x)                                                                      \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      throw Error(MGK_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+static inline int grid_for(size_t n) {
+  size_t g = (n + WG - 1) / WG;
+  return (int)std::max<size_t>(1, std::min<size_t>(g, 1024));
+}
+
+// ---------------------------------------------------------------- memory
+
+struct Device {
+  std::vector<void*> owned;
+  int64_t bytes = 0;
+  hipStream_t stream = nullptr;
+  void* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 16;
+    n = (n + 255) & ~(size_t)255;
+    if (hipMalloc(&p, n) != hipSuccess) throw Error(MGK_E_NOMEM, "hipMalloc failed");
+    owned.push_back(p);
+    bytes += (int64_t)n;
+    return p;
+  }
+  template <class T>
+  T* upload(const T* h, size_t count) {
+    T* d = (T*)alloc(sizeof(T) * count);
+    if (count) HIPCK(hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, stream));
+    return d;
+  }
+  ~Device() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
+
+static uint16_t f32_to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+// Device block matrix in a storage precision, with optional column index
+// (CSC over blocks) for products with the transpose.
+struct DMat {
+  int br = 1, bc = 1, nbr = 0, nbc = 0;
+  int64_t nnzb = 0;
+  int storage = MGK_F64;
+  int *ptr = nullptr, *col = nullptr;
+  void* val = nullptr;
+  int *tptr = nullptr, *trow = nullptr, *tblk = nullptr;
+  double avg_row = 0.0, avg_col = 0.0;
+};
+
+static DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index) {
+  DMat M;
+  M.br = A.br;
+  M.bc = A.bc;
+  M.nbr = A.nbr;
+  M.nbc = A.nbc;
+  M.nnzb = A.nnzb();
+  M.storage = storage;
+  M.ptr = D.upload(A.ptr.data(), A.ptr.size());
+  M.col = D.upload(A.col.data(), A.col.size());
+  const size_t nv = A.val.size();
+  if (storage == MGK_F64) {
+    M.val = D.upload(A.val.data(), nv);
+  } else if (storage == MGK_F32) {
+    std::vector<float> v(nv);
+    for (size_t i = 0; i < nv; ++i) v[i] = (float)A.val[i];
+    M.val = D.upload(v.data(), nv);
+  } else {
+    std::vector<uint16_t> v(nv);
+    for (size_t i = 0; i < nv; ++i) v[i] = f32_to_bf16((float)A.val[i]);
+    M.val = D.upload(v.data(), nv);
+  }
+  M.avg_row = A.nbr ? (double)M.nnzb / A.nbr : 0.0;
+  if (transpose_index) {
+    std::vector<int> tp(A.nbc + 1, 0), tr(M.nnzb), tb(M.nnzb);
+    for (int64_t k = 0; k < M.nnzb; ++k) tp[A.col[k] + 1]++;
+    for (int j = 0; j < A.nbc; ++j) tp[j + 1] += tp[j];
+    std::vector<int> fill(tp.begin(), tp.end() - 1);
+    for (int i = 0; i < A.nbr; ++i)
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int d = fill[A.col[k]]++;
+        tr[d] = i;
+        tb[d] = (int)k;
+      }
+    M.tptr = D.upload(tp.data(), tp.size());
+    M.trow = D.upload(tr.data(), tr.size());
+    M.tblk = D.upload(tb.data(), tb.size());
+    M.avg_col = A.nbc ? (double)M.nnzb / A.nbc : 0.0;
+  }
+  // the host vectors must outlive the async copies
+  HIPCK(hipStreamSynchronize(D.stream));
+  return M;
+}
+
+// ---------------------------------------------------------------- sparse launch
+
+// Lanes per block row: S splits long rows (coarse Galerkin levels) over more
+// lanes; short fine-level rows keep one lane per scalar row.
+static int pick_split(int br, double avg) {
+  if (br == 1) return avg >= 24 ? 8 : (avg >= 6 ? 4 : (avg >= 3 ? 2 : 1));
+  return avg >= 24 ? 4 : (avg >= 12 ? 2 : 1);
+}
+
+template <int BR, int S>
+static int nwg_rows(int nbr) {
+  return std::max(1, (nbr + RowMap<BR, S>::ROWS - 1) / RowMap<BR, S>::ROWS);
+}
+
+template <class TV>
+using AccOf = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+
+// y = alpha A x + beta y with optional fused dots (FP64 operator only).
+template <int BR, int BC, class TV, class TX, class TY>
+static void spmv_s(hipStream_t st, const DMat& M, bool trans, int S, const TX* x, TY* y,
+                   double alpha, double beta, int dots = 0, const double* w1 = nullptr,
+                   const double* w2 = nullptr, double* part = nullptr, int* nwg_out = nullptr) {
+  using TA = AccOf<TV>;
+  const int nrows = trans ? M.nbc : M.nbr;
+  const int* p = trans ? M.tptr : M.ptr;
+  const int* c = trans ? M.trow : M.col;
+  const int* b = trans ? M.tblk : nullptr;
+  const TV* v = (const TV*)M.val;
+#define MGK_SPMV_CASE(SS)                                                                   \
+  case SS: {                                                                                \
+    const int g = nwg_rows<BR, SS>(nrows);                                                  \
+    if (nwg_out) *nwg_out = g;                                                              \
+    if (trans)                                                                              \
+      k_spmv<BR, BC, SS, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(                           \
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part);                \
+    else                                                                                    \
+      k_spmv<BR, BC, SS, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(                          \
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part);                \
+    break;                                                                                  \
+  }
+  switch (S) {
+    MGK_SPMV_CASE(1)
+    MGK_SPMV_CASE(2)
+    MGK_SPMV_CASE(4)
+    default:
+      if constexpr (BR == 1) {
+        switch (S) { MGK_SPMV_CASE(8) }
+      }
+      break;
+  }
+#undef MGK_SPMV_CASE
+}
+
+template <int BR, int BC, class TV, class TX, class TF>
+static void residual_s(hipStream_t st, const DMat& M, bool trans, int S, const TF* f,
+                       const TX* z, TX* t) {
+  using TA = AccOf<TV>;
+  const int nrows = trans ? M.nbc : M.nbr;
+  const int* p = trans ? M.tptr : M.ptr;
+  const int* c = trans ? M.trow : M.col;
+  const int* b = trans ? M.tblk : nullptr;
+  const TV* v = (const TV*)M.val;
+#define MGK_RES_CASE(SS)                                                                    \
+  case SS: {                                                                                \
+    const int g = nwg_rows<BR, SS>(nrows);                                                  \
+    if (trans)                                                                              \
+      k_residual<BR, BC, SS, true, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f, \
+                                                                      z, t);                \
+    else                                                                                    \
+      k_residual<BR, BC, SS, false, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,   \
+                                                                       f, z, t);            \
+    break;                                                                                  \
+  }
+  switch (S) {
+    MGK_RES_CASE(1)
+    MGK_RES_CASE(2)
+    MGK_RES_CASE(4)
+    default:
+      if constexpr (BR == 1) {
+        switch (S) { MGK_RES_CASE(8) }
+      }
+      break;
+  }
+#undef MGK_RES_CASE
+}
+
+template <int B, class TV, class TX, class TF, class TO, class TM>
+static void smooth_s(hipStream_t st, const DMat& M, bool trans, int S, const TM* Mb, const TF* f,
+                     const TX* z, TO* zout) {
+  using TA = AccOf<TV>;
+  const int nrows = M.nbr;
+  const int* p = trans ? M.tptr : M.ptr;
+  const int* c = trans ? M.trow : M.col;
+  const int* b = trans ? M.tblk : nullptr;
+  const TV* v = (const TV*)M.val;
+#define MGK_SM_CASE(SS)                                                                    \
+  case SS: {                                                                               \
+    const int g = nwg_rows<B, SS>(nrows);                                                  \
+    if (trans)                                                                             \
+      k_smooth<B, SS, true, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,  \
+                                                                       Mb, f, z, zout);    \
+    else                                                                                   \
+      k_smooth<B, SS, false, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, \
+                                                                        Mb, f, z, zout);   \
+    break;                                                                                 \
+  }
+  switch (S) {
+    MGK_SM_CASE(1)
+    MGK_SM_CASE(2)
+    MGK_SM_CASE(4)
+    default:
+      if constexpr (B == 1) {
+        switch (S) { MGK_SM_CASE(8) }
+      }
+      break;
+  }
+#undef MGK_SM_CASE
+}
+
+// ---------------------------------------------------------------- hierarchy
+
+struct DLevel {
+  DMat A, P, R;
+  void* M = nullptr;       // smoother blocks: FP64 (F64 hierarchy) or FP32
+  int nbr = 0;
+  size_t n = 0;            // scalar unknowns
+  void *r = nullptr, *t = nullptr, *z = nullptr, *z2 = nullptr;
+  int sA = 1, sAt = 1, sP = 1, sR = 1;
+};
+
+struct DHier {
+  int b = 1, storage = MGK_F64;
+  bool trans_ready = false;
+  std::vector<DLevel> lv;
+  int nc = 0;
+  double *cinv = nullptr, *cinvT = nullptr;
+  HHierarchy host;         // kept only when requested
+  bool keep_host = false;
+  std::vector<mgk_level_desc> desc;
+};
+
+static void fill_desc(const HHierarchy& H, std::vector<mgk_level_desc>& desc) {
+  desc.resize(H.levels.size());
+  for (size_t l = 0; l < H.levels.size(); ++l) {
+    const HLevel& h = H.levels[l];
+    mgk_level_desc& ds = desc[l];
+    ds.n_brows = h.A.nbr;
+    ds.block = H.b;
+    ds.nnzb = h.A.nnzb();
+    ds.n_agg = h.n_agg;
+    ds.pad = 0;
+    ds.p_nnzb = h.P.nnzb();
+    ds.r_nnzb = h.R.nnzb();
+    ds.omega = h.omega;
+  }
+}
+
+static void describe(DHier& H) { fill_desc(H.host, H.desc); }
+
+static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_transpose,
+                             DHier& out, const DMat* share_level0) {
+  out.b = H.b;
+  out.storage = storage;
+  out.trans_ready = with_transpose;
+  const int L = (int)H.levels.size();
+  out.lv.resize(L);
+  out.desc.resize(L);
+  const size_t xs = storage == MGK_F64 ? 8 : 4;
+  for (int l = 0; l < L; ++l) {
+    HLevel& h = H.levels[l];
+    DLevel& d = out.lv[l];
+    d.nbr = h.A.nbr;
+    d.n = (size_t)h.A.nbr * H.b;
+    const bool last = l == L - 1;
+    if (l == 0 && share_level0 && storage == MGK_F64 && (!with_transpose || share_level0->tptr))
+      d.A = *share_level0;
+    else if (!last)
+      d.A = upload_mat(D, h.A, storage, with_transpose);
+    if (!last) {
+      d.P = upload_mat(D, h.P, storage, false);
+      d.R = upload_mat(D, h.R, storage, false);
+      if (storage == MGK_F64) {
+        d.M = D.upload(h.M.data(), h.M.size());
+      } else {
+        std::vector<float> m(h.M.begin(), h.M.end());
+        d.M = D.upload(m.data(), m.size());
+        HIPCK(hipStreamSynchronize(D.stream));
+      }
+      d.sA = pick_split(H.b, d.A.avg_row);
+      d.sAt = pick_split(H.b, d.A.avg_col);
+      d.sP = pick_split(H.b, d.P.avg_row);
+      d.sR = pick_split(H.b, d.R.avg_row);
+    }
+    d.r = D.alloc(d.n * xs);
+    d.t = D.alloc(d.n * xs);
+    d.z = D.alloc(d.n * xs);
+    d.z2 = D.alloc(d.n * xs);
+  }
+  fill_desc(H, out.desc);
+  out.nc = H.nc;
+  out.cinv = D.upload(H.coarse_inv.data(), H.coarse_inv.size());
+  if (with_transpose) {
+    std::vector<double> t((size_t)H.nc * H.nc);
+    for (int i = 0; i < H.nc; ++i)
+      for (int j = 0; j < H.nc; ++j) t[(size_t)j * H.nc + i] = H.coarse_inv[(size_t)i * H.nc + j];
+    out.cinvT = D.upload(t.data(), t.size());
+    HIPCK(hipStreamSynchronize(D.stream));
+  }
+  HIPCK(hipStreamSynchronize(D.stream));
+}
+
+// One V(1,1) cycle on level l.  r: TIN at level 0 (else TX in lv[l].r);
+// output: TOUT at level 0 (else TX).  Returns nothing; the output of a level
+// l > 0 lands in lv[l].z2 (or lv[l].z on the coarsest level).
+template <int B, class TV, class TX>
+struct Cycle {
+  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+
+  template <class TIN, class TOUT>
+  static void run(hipStream_t st, DHier& H, int l, const TIN* r, TOUT* zout, bool trans) {
+    DLevel& L = H.lv[l];
+    const int nl = (int)H.lv.size();
+    if (l == nl - 1) {
+      k_coarse_gemv<TIN, TOUT><<<H.nc, WG, 0, st>>>(H.nc, trans ? H.cinvT : H.cinv, r, zout);
+      return;
+    }
+    TX* z = (TX*)L.z;
+    TX* t = (TX*)L.t;
+    DLevel& C = H.lv[l + 1];
+    k_block_diag<B, TM, TIN, TX, AccOf<TV>>
+        <<<(unsigned)((L.n + WG - 1) / WG), WG, 0, st>>>(L.nbr, trans, (const TM*)L.M, r, z);
+    residual_s<B, B, TV, TX, TIN>(st, L.A, trans, trans ? L.sAt : L.sA, r, z, t);
+    spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.sR, t, (TX*)C.r, 1.0, 0.0);
+    TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
+    run<TX, TX>(st, H, l + 1, (const TX*)C.r, zc, trans);
+    spmv_s<B, B, TV, TX, TX>(st, L.P, false, L.sP, zc, z, 1.0, 1.0);
+    smooth_s<B, TV, TX, TIN, TOUT, TM>(st, L.A, trans, trans ? L.sAt : L.sA, (const TM*)L.M, r,
+                                       z, zout);
+  }
+};
+
+// Dispatch on (block size, storage) for vectors of type TIN/TOUT at the
+// hierarchy boundary.
+template <class TIN, class TOUT>
+static void vcycle(hipStream_t st, DHier& H, const TIN* r, TOUT* z, bool trans) {
+#define MGK_VC(BB)                                                                   \
+  case BB:                                                                           \
+    if (H.storage == MGK_F64)                                                        \
+      Cycle<BB, double, double>::run<TIN, TOUT>(st, H, 0, r, z, trans);              \
+    else if (H.storage == MGK_F32)                                                   \
+      Cycle<BB, float, float>::run<TIN, TOUT>(st, H, 0, r, z, trans);                \
+    else                                                                             \
+      Cycle<BB, bf16, float>::run<TIN, TOUT>(st, H, 0, r, z, trans);                 \
+    break;
+  switch (H.b) {
+    MGK_VC(1)
+    MGK_VC(3)
+    MGK_VC(4)
+    default: throw Error(MGK_E_INVALID, "unsupported block size");
+  }
+#undef MGK_VC
+}
+
+}  // namespace mgk
+
+// ---------------------------------------------------------------- solver object
+
+using namespace mgk;
+
+struct mgk_solver {
+  Device dev;
+  mgk_params prm;
+  int kind = MGK_AMG_SPAI0;
+  int b = 4;
+  int nbr = 0;
+  size_t n = 0;
+  HBsr A_host;               // kept for the FP64 transpose pattern and export
+  DMat A;                    // FP64 outer operator
+  int sA = 1, sAt = 1;
+  DHier H;                   // monolithic or velocity hierarchy
+  DHier Hp;                  // pressure hierarchy (Schur)
+  DMat Blo, Bup;             // Schur couplings in storage precision
+  void *ru = nullptr, *rp = nullptr, *tu = nullptr, *tp = nullptr, *zu = nullptr, *zp = nullptr;
+  // Krylov workspace (FP64)
+  double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *ph = nullptr, *s = nullptr,
+         *sh = nullptr, *t = nullptr;
+  double* sc = nullptr;      // device scalars
+  double* part = nullptr;    // reduction partials
+  size_t part_len = 0;
+  double* hsc = nullptr;     // pinned host mirror of sc
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // FGMRES
+  double *V = nullptr, *Z = nullptr, *h = nullptr, *hsum = nullptr, *yv = nullptr;
+  double* hpin = nullptr;
+  int m = 0;
+  double setup_ms = 0.0;
+  bool host_only = false;
+  ~mgk_solver() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (hsc) (void)hipHostFree(hsc);
+    if (hpin) (void)hipHostFree(hpin);
+  }
+};
+
+namespace mgk {
+
+static void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots = 0,
+                       const double* w1 = nullptr, const double* w2 = nullptr,
+                       int* nwg = nullptr) {
+  hipStream_t st = S->dev.stream;
+  const int sp = trans ? S->sAt : S->sA;
+  switch (S->b) {
+    case 1: spmv_s<1, 1, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
+    case 3: spmv_s<3, 3, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
+    case 4: spmv_s<4, 4, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
+  }
+}
+
+static void outer_residual(mgk_solver* S, const double* b, const double* x, double* r,
+                           bool trans) {
+  hipStream_t st = S->dev.stream;
+  const int sp = trans ? S->sAt : S->sA;
+  switch (S->b) {
+    case 1: residual_s<1, 1, double, double, double>(st, S->A, trans, sp, b, x, r); break;
+    case 3: residual_s<3, 3, double, double, double>(st, S->A, trans, sp, b, x, r); break;
+    case 4: residual_s<4, 4, double, double, double>(st, S->A, trans, sp, b, x, r); break;
+  }
+}
+
+// Schur apply: z = B r for interleaved FP64 vectors.
+template <class TV, class TX>
+static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
+  hipStream_t st = S->dev.stream;
+  const size_t nn = (size_t)S->nbr;
+  TX *ru = (TX*)S->ru, *rp = (TX*)S->rp, *tu = (TX*)S->tu, *tp = (TX*)S->tp, *zu = (TX*)S->zu,
+     *zp = (TX*)S->zp;
+  k_split<TX><<<grid_for(nn), WG, 0, st>>>(nn, r, ru, rp);
+  vcycle<TX, TX>(st, S->H, ru, zu, false);
+  residual_s<1, 3, TV, TX, TX>(st, S->Blo, false, 2, rp, zu, tp);
+  vcycle<TX, TX>(st, S->Hp, tp, zp, false);
+  residual_s<3, 1, TV, TX, TX>(st, S->Bup, false, 1, ru, zp, tu);
+  vcycle<TX, TX>(st, S->H, tu, zu, false);
+  k_merge<TX><<<grid_for(nn), WG, 0, st>>>(nn, zu, zp, z);
+}
+
+static void precond(mgk_solver* S, const double* r, double* z, bool trans) {
+  if (S->kind == MGK_SCHUR) {
+    if (trans) throw Error(MGK_E_STATE, "transposed Schur preconditioner is not available");
+    if (S->H.storage == MGK_F64) schur_apply_t<double, double>(S, r, z);
+    else if (S->H.storage == MGK_F32) schur_apply_t<float, float>(S, r, z);
+    else schur_apply_t<bf16, float>(S, r, z);
+  } else {
+    vcycle<double, double>(S->dev.stream, S->H, r, z, trans);
+  }
+}
+
+// ---------------------------------------------------------------- BiCGStab
+
+static int red_grid(size_t n) { return grid_for(n); }
+static int maxiter_of(const mgk_solver* S) { return S->prm.maxiter; }
+
+static void finalize(mgk_solver* S, int count, int two, int op, int i0 = 0, int i1 = 0) {
+  k_finalize<<<1, WG, 0, S->dev.stream>>>(S->part, count, two, op, i0, i1, S->sc);
+}
+
+// Copy the device scalars to pinned memory and mark the point with event e.
+static void publish(mgk_solver* S, int e) {
+  HIPCK(hipMemcpyAsync(S->hsc, S->sc, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                       S->dev.stream));
+  HIPCK(hipEventRecord(S->ev[e], S->dev.stream));
+}
+
+static void wait(mgk_solver* S, int e) {
+  HIPCK(hipEventSynchronize(S->ev[e]));
+  HIPCK(hipGetLastError());
+}
+
+static double norm2(mgk_solver* S, const double* a) {
+  const size_t n = S->n;
+  const int g = red_grid(n);
+  k_dot2<<<g, WG, 0, S->dev.stream>>>(n, a, a, nullptr, nullptr, S->part);
+  finalize(S, g, 0, FIN_STORE1, SC_TMP);
+  publish(S, 3);
+  wait(S, 3);
+  return std::sqrt(S->hsc[SC_TMP]);
+}
+
+static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool trans,
+                    mgk_info* info) {
+  hipStream_t st = S->dev.stream;
+  const size_t n = S->n;
+  const int g = red_grid(n);
+  const double nb = norm2(S, b);
+  info->iters = 0;
+  info->restarts = 0;
+  if (nb == 0.0) {
+    k_fill<<<g, WG, 0, st>>>(n, 0.0, x);
+    info->rel_resid = 0.0;
+    return MGK_OK;
+  }
+  const double tol2 = (tol * nb) * (tol * nb);
+  int it = 0;
+  for (int restart = 0;; ++restart) {
+    // r = b - A x; rhat = r; rho = alpha = omega = 1; p = v = 0
+    outer_residual(S, b, x, S->r, trans);
+    k_copy<<<g, WG, 0, st>>>(n, S->r, S->rh);
+    k_fill<<<g, WG, 0, st>>>(n, 0.0, S->p);
+    k_fill<<<g, WG, 0, st>>>(n, 0.0, S->v);
+    k_dot2<<<g, WG, 0, st>>>(n, S->r, S->r, S->rh, S->r, S->part);
+    {
+      // sc[RR] = ||r||^2, sc[RHO1] = (rhat, r); rho = alpha = omega = 1
+      double init[SC_COUNT] = {0};
+      init[SC_RHO] = init[SC_ALPHA] = init[SC_OMEGA] = 1.0;
+      std::memcpy(S->hsc, init, sizeof(init));
+      HIPCK(hipMemcpyAsync(S->sc, S->hsc, sizeof(init), hipMemcpyHostToDevice, st));
+      finalize(S, g, 1, FIN_STORE2, SC_RR, SC_RHO1);
+      publish(S, 1);
+      wait(S, 1);
+    }
+    bool done = S->hsc[SC_RR] <= tol2;
+    bool pending_v = false;  // the p / V-cycle / v stage of iteration it+1 is queued
+    while (!done && it < maxiter_of(S)) {
+      if (S->hsc[SC_RHO1] == 0.0) break;  // breakdown: restart
+      ++it;
+      if (!pending_v) {
+        k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p);
+        precond(S, S->p, S->ph, trans);
+        int nw = 0;
+        outer_spmv(S, S->ph, S->v, trans, 1, S->rh, nullptr, &nw);
+        finalize(S, nw, 0, FIN_ALPHA);
+      }
+      pending_v = false;
+      k_bicg_s<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->ph, S->s, x, S->part);
+      finalize(S, g, 0, FIN_STORE1, SC_SS);
+      publish(S, 0);
+      // speculative: shat = M s; t = A shat (harmless if we stop after s)
+      precond(S, S->s, S->sh, trans);
+      int nw = 0;
+      outer_spmv(S, S->sh, S->t, trans, 2, S->s, nullptr, &nw);  // partials (s,t), (t,t)
+      finalize(S, nw, 1, FIN_OMEGA);
+      wait(S, 0);
+      if (S->hsc[SC_SS] <= tol2) break;  // x already holds x + alpha phat
+      k_bicg_xr<<<g, WG, 0, st>>>(n, S->sc, S->s, S->t, S->sh, S->rh, x, S->r, S->part);
+      finalize(S, g, 1, FIN_RHO);
+      publish(S, 1);
+      if (it < maxiter_of(S)) {
+        // speculative next p / V-cycle / v (x untouched)
+        k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p);
+        precond(S, S->p, S->ph, trans);
+        int nw2 = 0;
+        outer_spmv(S, S->ph, S->v, trans, 1, S->rh, nullptr, &nw2);
+        finalize(S, nw2, 0, FIN_ALPHA);
+        pending_v = true;
+      }
+      wait(S, 1);
+      if (S->hsc[SC_TT] == 0.0) break;  // breakdown
+      if (S->hsc[SC_RR] <= tol2) done = true;
+    }
+    // true residual
+    outer_residual(S, b, x, S->r, trans);
+    const double rn = norm2(S, S->r);
+    info->rel_resid = rn / nb;
+    info->iters = it;
+    info->restarts = restart;
+    if (info->rel_resid <= tol) return MGK_OK;
+    if (it >= maxiter_of(S) || restart >= S->prm.max_restarts) return MGK_NOT_CONVERGED;
+  }
+}
+
+}  // namespace mgk
+
+namespace mgk {
+
+// ---------------------------------------------------------------- FGMRES
+
+static void arnoldi_products(mgk_solver* S, int j, double* w, int* nw_unused) {
+  (void)nw_unused;
+  hipStream_t st = S->dev.stream;
+  const size_t n = S->n;
+  const int g = red_grid(n);
+  // h = V^T w; w -= V h; h2 = V^T w; w -= V h2; hsum = h + h2; ||w||^2
+  k_multidot<<<g, WG, 0, st>>>(n, j + 1, S->V, n, w, S->part);
+  k_multifin<<<1, WG, 0, st>>>(S->part, g, j + 1, S->h, S->hsum, 0);
+  k_multiaxpy<<<g, WG, 0, st>>>(n, j + 1, S->V, n, S->h, w, nullptr);
+  k_multidot<<<g, WG, 0, st>>>(n, j + 1, S->V, n, w, S->part);
+  k_multifin<<<1, WG, 0, st>>>(S->part, g, j + 1, S->h, S->hsum, 1);
+  k_multiaxpy<<<g, WG, 0, st>>>(n, j + 1, S->V, n, S->h, w, S->part);
+  finalize(S, g, 0, FIN_STORE1, SC_TMP);
+}
+
+static int fgmres(mgk_solver* S, const double* b, double* x, double tol, mgk_info* info) {
+  hipStream_t st = S->dev.stream;
+  const size_t n = S->n;
+  const int g = red_grid(n);
+  const int m = S->m;
+  const double nb = norm2(S, b);
+  info->iters = 0;
+  info->restarts = 0;
+  if (nb == 0.0) {
+    k_fill<<<g, WG, 0, st>>>(n, 0.0, x);
+    info->rel_resid = 0.0;
+    return MGK_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1);
+  int total = 0;
+  for (int cycle = 0;; ++cycle) {
+    double* V0 = S->V;
+    outer_residual(S, b, x, V0, false);
+    const double beta = norm2(S, V0);
+    info->rel_resid = beta / nb;
+    info->iters = total;
+    info->restarts = cycle;
+    if (beta / nb <= tol) return MGK_OK;
+    if (total >= S->prm.maxiter) return MGK_NOT_CONVERGED;
+    k_scal<<<g, WG, 0, st>>>(n, 1.0 / beta, V0, V0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int k = 0;
+    auto stage = [&](int j) {
+      // Z_j = M V_j; V_{j+1} <- A Z_j, orthogonalized and normalized on device
+      double* Vj = S->V + (size_t)j * n;
+      double* Zj = S->Z + (size_t)j * n;
+      double* w = S->V + (size_t)(j + 1) * n;
+      precond(S, Vj, Zj, false);
+      outer_spmv(S, Zj, w, false);
+      arnoldi_products(S, j, w, nullptr);
+      HIPCK(hipMemcpyAsync(S->hpin + (size_t)j * (MAXM + 1), S->hsum, sizeof(double) * (j + 1),
+                           hipMemcpyDeviceToHost, st));
+      HIPCK(hipMemcpyAsync(S->hpin + (size_t)j * (MAXM + 1) + MAXM, S->sc + SC_TMP,
+                           sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCK(hipEventRecord(S->ev[j & 1], st));
+      k_scale<<<g, WG, 0, st>>>(n, S->sc, SC_TMP, 1, w, w);
+    };
+    stage(0);
+    for (int j = 0; j < m && total < S->prm.maxiter; ++j) {
+      if (j + 1 < m && total + 1 < S->prm.maxiter) stage(j + 1);  // speculative next step
+      wait(S, j & 1);
+      const double* hj = S->hpin + (size_t)j * (MAXM + 1);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hj[i];
+      const double hn = std::sqrt(hj[MAXM]);
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, c);
+      cs[j] = a / den;
+      sn[j] = c / den;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++total;
+      k = j + 1;
+      if (std::fabs(gv[j + 1]) / nb <= tol || hn == 0.0) break;
+    }
+    // drain speculative work before reusing the host buffers
+    HIPCK(hipStreamSynchronize(st));
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      double sum = gv[i];
+      for (int q = i + 1; q < k; ++q) sum -= H[(size_t)i * m + q] * y[q];
+      y[i] = sum / H[(size_t)i * m + i];
+    }
+    std::memcpy(S->hpin + (size_t)MAXM * (MAXM + 1), y.data(), sizeof(double) * k);
+    HIPCK(hipMemcpyAsync(S->yv, S->hpin + (size_t)MAXM * (MAXM + 1), sizeof(double) * k,
+                         hipMemcpyHostToDevice, st));
+    k_update_x<<<g, WG, 0, st>>>(n, k, S->Z, n, S->yv, x);
+  }
+}
+
+// ---------------------------------------------------------------- setup
+
+static SetupParams setup_params(const mgk_params& p, int kind) {
+  SetupParams sp;
+  sp.eps_strong = p.eps_strong;
+  sp.coarse_enough = p.coarse_enough;
+  sp.max_levels = p.max_levels;
+  sp.jacobi_omega = p.jacobi_omega;
+  sp.smoother = kind == MGK_AMG_JACOBI ? SM_JACOBI : (p.block_spai0 ? SM_SPAI0_BLOCK : SM_SPAI0_SCALAR);
+  return sp;
+}
+
+static void alloc_krylov(mgk_solver* S) {
+  Device& D = S->dev;
+  const size_t n = S->n, nb = n * sizeof(double);
+  S->r = (double*)D.alloc(nb);
+  S->rh = (double*)D.alloc(nb);
+  S->p = (double*)D.alloc(nb);
+  S->v = (double*)D.alloc(nb);
+  S->ph = (double*)D.alloc(nb);
+  S->s = (double*)D.alloc(nb);
+  S->sh = (double*)D.alloc(nb);
+  S->t = (double*)D.alloc(nb);
+  S->sc = (double*)D.alloc(sizeof(double) * SC_COUNT);
+  // partials: two dots per workgroup of the finest SpMV, or MAXM dots per
+  // reduction workgroup
+  const size_t rows16 = (size_t)S->nbr / 16 + 64;
+  S->part_len = std::max<size_t>(2 * rows16 * 4, (size_t)MAXM * 1024) + 1024;
+  S->part = (double*)D.alloc(sizeof(double) * S->part_len);
+  HIPCK(hipHostMalloc((void**)&S->hsc, sizeof(double) * SC_COUNT, hipHostMallocDefault));
+  for (auto& e : S->ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (S->prm.krylov == MGK_FGMRES) {
+    S->m = std::max(1, std::min<int>(S->prm.fgmres_m, MAXM - 1));
+    S->V = (double*)D.alloc(nb * (S->m + 1));
+    S->Z = (double*)D.alloc(nb * S->m);
+    S->h = (double*)D.alloc(sizeof(double) * MAXM);
+    S->hsum = (double*)D.alloc(sizeof(double) * MAXM);
+    S->yv = (double*)D.alloc(sizeof(double) * MAXM);
+    HIPCK(hipHostMalloc((void**)&S->hpin, sizeof(double) * (MAXM + 1) * (MAXM + 1),
+                        hipHostMallocDefault));
+  }
+}
+
+static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind,
+                       const mgk_params* prm, void* stream, bool host_only = false) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!A || !prm) throw Error(MGK_E_INVALID, "null matrix or params");
+  if (A->block != block_size || (block_size != 1 && block_size != 3 && block_size != 4))
+    throw Error(MGK_E_INVALID, "block_size must equal A->block and be 1, 3 or 4");
+  if (kind < MGK_AMG_SPAI0 || kind > MGK_SCHUR) throw Error(MGK_E_INVALID, "unknown kind");
+  if (kind == MGK_SCHUR && block_size != 4)
+    throw Error(MGK_E_INVALID, "MGK_SCHUR needs interleaved [u,v,w,p] (block size 4)");
+  if (prm->hier < MGK_F64 || prm->hier > MGK_BF16) throw Error(MGK_E_INVALID, "unknown storage");
+  if (prm->krylov != MGK_BICGSTAB && prm->krylov != MGK_FGMRES)
+    throw Error(MGK_E_INVALID, "unknown Krylov method");
+  if (prm->maxiter < 1 || prm->coarse_enough < 1 || prm->max_levels < 1 || prm->fgmres_m < 1)
+    throw Error(MGK_E_INVALID, "maxiter, coarse_enough, max_levels and fgmres_m must be >= 1");
+  if (A->n_brows < 1 || !A->rowptr || (!A->col && A->rowptr[A->n_brows] > 0))
+    throw Error(MGK_E_INVALID, "empty or null matrix arrays");
+  S->prm = *prm;
+  S->kind = kind;
+  S->b = block_size;
+  S->nbr = A->n_brows;
+  S->n = (size_t)A->n_brows * block_size;
+  S->dev.stream = (hipStream_t)stream;
+  HBsr& H = S->A_host;
+  H.br = H.bc = block_size;
+  H.nbr = H.nbc = A->n_brows;
+  H.ptr.assign(A->rowptr, A->rowptr + A->n_brows + 1);
+  if (H.ptr[0] != 0 || H.ptr.back() < 0) throw Error(MGK_E_INVALID, "invalid row pointer");
+  H.col.assign(A->col, A->col + H.ptr.back());
+  H.val.assign(A->val, A->val + (size_t)H.ptr.back() * block_size * block_size);
+  std::string err;
+  if (validate_bsr(H, err)) throw Error(MGK_E_INVALID, err);
+  const bool tr = prm->enable_transpose != 0;
+  S->host_only = host_only;
+  if (host_only) {
+    // hierarchy only, kept on the host for inspection; no device work
+    const SetupParams sp = setup_params(*prm, kind);
+    int rc;
+    if (kind == MGK_SCHUR) {
+      SchurParts parts;
+      if ((rc = schur_split(H, parts, err))) throw Error(rc, err);
+      if ((rc = build_hierarchy(parts.Auu, sp, S->H.host, err))) throw Error(rc, err);
+      if ((rc = build_hierarchy(parts.S, sp, S->Hp.host, err))) throw Error(rc, err);
+      S->Hp.keep_host = true;
+      describe(S->Hp);
+    } else {
+      if ((rc = build_hierarchy(H, sp, S->H.host, err))) throw Error(rc, err);
+    }
+    S->H.keep_host = true;
+    describe(S->H);
+    S->setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return;
+  }
+  S->A = upload_mat(S->dev, H, MGK_F64, tr);
+  S->sA = pick_split(block_size, S->A.avg_row);
+  S->sAt = pick_split(block_size, S->A.avg_col);
+  const SetupParams sp = setup_params(*prm, kind);
+  int rc;
+  if (kind == MGK_SCHUR) {
+    SchurParts parts;
+    if ((rc = schur_split(H, parts, err))) throw Error(rc, err);
+    HHierarchy hu, hp;
+    if ((rc = build_hierarchy(parts.Auu, sp, hu, err))) throw Error(rc, err);
+    if ((rc = build_hierarchy(parts.S, sp, hp, err))) throw Error(rc, err);
+    upload_hierarchy(S->dev, hu, prm->hier, false, S->H, nullptr);
+    upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr);
+    S->Blo = upload_mat(S->dev, parts.Blo, prm->hier, false);
+    S->Bup = upload_mat(S->dev, parts.Bup, prm->hier, false);
+    const size_t xs = prm->hier == MGK_F64 ? 8 : 4, nn = (size_t)S->nbr;
+    S->ru = S->dev.alloc(3 * nn * xs);
+    S->tu = S->dev.alloc(3 * nn * xs);
+    S->zu = S->dev.alloc(3 * nn * xs);
+    S->rp = S->dev.alloc(nn * xs);
+    S->tp = S->dev.alloc(nn * xs);
+    S->zp = S->dev.alloc(nn * xs);
+    if (prm->keep_host) {
+      S->H.host = std::move(hu);
+      S->Hp.host = std::move(hp);
+      S->H.keep_host = S->Hp.keep_host = true;
+    }
+  } else {
+    HHierarchy hh;
+    if ((rc = build_hierarchy(H, sp, hh, err))) throw Error(rc, err);
+    upload_hierarchy(S->dev, hh, prm->hier, tr, S->H, &S->A);
+    if (prm->keep_host) {
+      S->H.host = std::move(hh);
+      S->H.keep_host = true;
+    }
+  }
+  alloc_krylov(S);
+  HIPCK(hipStreamSynchronize(S->dev.stream));
+  S->setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+static int fail(const Error& e) {
+  g_err = e.what();
+  return e.code;
+}
+
+}  // namespace mgk
+
+// ---------------------------------------------------------------- C ABI
+
+namespace mgk {
+// Run an entry point body; no exception crosses the C ABI.
+template <class F>
+static int guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return MGK_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MGK_E_INVALID;
+  }
+}
+}  // namespace mgk
+
+extern "C" {
+
+const char* mgk_last_error(void) { return mgk::g_err.c_str(); }
+
+int mgk_params_default(mgk_params* p) {
+  if (!p) return MGK_E_INVALID;
+  std::memset(p, 0, sizeof(*p));
+  p->krylov = MGK_BICGSTAB;
+  p->fgmres_m = 30;
+  p->maxiter = 1000;
+  p->max_restarts = 5;
+  p->hier = MGK_F64;
+  p->coarse_enough = 3000;
+  p->max_levels = 20;
+  p->block_spai0 = 1;
+  p->eps_strong = 0.08;
+  p->jacobi_omega = 2.0 / 3.0;
+  p->keep_host = 0;
+  p->enable_transpose = 0;
+  return MGK_OK;
+}
+
+int mgk_stokes_sizes(int32_t n, int32_t* n_brows, int64_t* nnzb) {
+  if (n < 3 || n > 1290 || !n_brows || !nnzb) {
+    mgk::g_err = "mgk_stokes_sizes: need 3 <= n <= 1290 and non-null outputs";
+    return MGK_E_INVALID;
+  }
+  mgk::stokes_sizes(n, *n_brows, *nnzb);
+  return MGK_OK;
+}
+
+int mgk_stokes_assemble(int32_t n, const double* theta, int32_t* rowptr, int32_t* col,
+                        double* val) {
+  if (n < 3 || n > 1290 || !rowptr || !col || !val) {
+    mgk::g_err = "mgk_stokes_assemble: need 3 <= n <= 1290 and non-null outputs";
+    return MGK_E_INVALID;
+  }
+  if (theta) {
+    const size_t nc = (size_t)(n - 1) * (n - 1) * (n - 1);
+    for (size_t e = 0; e < nc; ++e)
+      if (!(theta[e] > 0.0) || !std::isfinite(theta[e])) {
+        mgk::g_err = "mgk_stokes_assemble: theta must be positive and finite";
+        return MGK_E_INVALID;
+      }
+  }
+  mgk::stokes_assemble(n, theta, rowptr, col, val);
+  return MGK_OK;
+}
+
+int mgk_csr_to_bsr(int32_t nrows, const int32_t* ptr, const int32_t* col, const double* val,
+                   int32_t b, int32_t* bptr, int32_t* bcol, double* bval, int64_t* nnzb) {
+  return mgk::guard([&]() -> int {
+    if (!ptr || !nnzb || (nrows > 0 && ptr[nrows] > 0 && (!col || !val)))
+      throw mgk::Error(MGK_E_INVALID, "mgk_csr_to_bsr: null argument");
+    mgk::HBsr out;
+    std::string err;
+    if (mgk::csr_to_bsr(nrows, ptr, col, val, b, out, err)) throw mgk::Error(MGK_E_INVALID, err);
+    *nnzb = out.nnzb();
+    if (bcol) {
+      if (!bptr || !bval) throw mgk::Error(MGK_E_INVALID, "mgk_csr_to_bsr: null output");
+      std::memcpy(bptr, out.ptr.data(), sizeof(int32_t) * out.ptr.size());
+      std::memcpy(bcol, out.col.data(), sizeof(int32_t) * out.col.size());
+      std::memcpy(bval, out.val.data(), sizeof(double) * out.val.size());
+    }
+    return MGK_OK;
+  });
+}
+
+int mgk_setup(const mgk_bsr* A, int32_t block_size, mgk_precond_kind kind, const mgk_params* prm,
+              void* hip_stream, mgk_solver** out) {
+  if (!out) {
+    mgk::g_err = "mgk_setup: null output";
+    return MGK_E_INVALID;
+  }
+  *out = nullptr;
+  std::unique_ptr<mgk_solver> S(new mgk_solver());
+  return mgk::guard([&]() -> int {
+    mgk::setup_impl(S.get(), A, block_size, kind, prm, hip_stream);
+    *out = S.release();
+    return MGK_OK;
+  });
+}
+
+static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rtol,
+                        mgk_info* info, bool trans) {
+  if (!s || !d_b || !d_x || !info || !(rtol > 0.0)) {
+    mgk::g_err = "solve: null argument or non-positive rtol";
+    return MGK_E_INVALID;
+  }
+  if (s->host_only) {
+    mgk::g_err = "solve: solver was set up with mgk_setup_host (no device data)";
+    return MGK_E_STATE;
+  }
+  if (trans && (s->kind == MGK_SCHUR || !s->H.trans_ready)) {
+    mgk::g_err = "solve_transposed needs a monolithic AMG solver set up with enable_transpose";
+    return MGK_E_STATE;
+  }
+  return mgk::guard([&]() -> int {
+    auto t0 = std::chrono::steady_clock::now();
+    std::memset(info, 0, sizeof(*info));
+    int rc;
+    if (!trans && s->prm.krylov == MGK_FGMRES) rc = mgk::fgmres(s, d_b, d_x, rtol, info);
+    else rc = mgk::bicgstab(s, d_b, d_x, rtol, trans, info);
+    HIPCK(hipStreamSynchronize(s->dev.stream));
+    HIPCK(hipGetLastError());
+    info->status = rc;
+    info->levels = (int)s->H.lv.size();
+    info->setup_ms = s->setup_ms;
+    info->solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->device_bytes = s->dev.bytes;
+    return rc;
+  });
+}
+
+int mgk_solve(mgk_solver* s, const double* d_b, double* d_x, double rtol, mgk_info* info) {
+  return solve_common(s, d_b, d_x, rtol, info, false);
+}
+
+int mgk_solve_transposed(mgk_solver* s, const double* d_g, double* d_lambda, double rtol,
+                         mgk_info* info) {
+  return solve_common(s, d_g, d_lambda, rtol, info, true);
+}
+
+int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t transposed) {
+  if (!s || !d_r || !d_z) {
+    mgk::g_err = "precond_apply: null argument";
+    return MGK_E_INVALID;
+  }
+  if (s->host_only) {
+    mgk::g_err = "precond_apply: solver has no device data";
+    return MGK_E_STATE;
+  }
+  if (transposed && (s->kind == MGK_SCHUR || !s->H.trans_ready)) {
+    mgk::g_err = "transposed preconditioner needs enable_transpose and a monolithic AMG";
+    return MGK_E_STATE;
+  }
+  return mgk::guard([&]() -> int {
+    mgk::precond(s, d_r, d_z, transposed != 0);
+    HIPCK(hipStreamSynchronize(s->dev.stream));
+    HIPCK(hipGetLastError());
+    return MGK_OK;
+  });
+}
+
+int mgk_spmv(mgk_solver* s, int32_t hier, int32_t level, int32_t which, const void* d_x,
+             void* d_y) {
+  if (!s || !d_x || !d_y || which < 0 || which > 3) {
+    mgk::g_err = "spmv: bad argument";
+    return MGK_E_INVALID;
+  }
+  if (s->host_only) {
+    mgk::g_err = "spmv: solver has no device data";
+    return MGK_E_STATE;
+  }
+  return mgk::guard([&]() -> int {
+    hipStream_t st = s->dev.stream;
+    if (level < 0) {
+      if (which != 0 && which != 3) throw mgk::Error(MGK_E_INVALID, "level -1 has only A and A^T");
+      if (which == 3 && !s->A.tptr) throw mgk::Error(MGK_E_STATE, "no transpose index");
+      mgk::outer_spmv(s, (const double*)d_x, (double*)d_y, which == 3);
+    } else {
+      mgk::DHier& H = hier == 1 ? s->Hp : s->H;
+      if (hier == 1 && s->kind != MGK_SCHUR) throw mgk::Error(MGK_E_INVALID, "no pressure hierarchy");
+      if (level >= (int)H.lv.size() - 1 && !(level == 0 && H.lv.size() == 1 && false))
+        if (level >= (int)H.lv.size() - 1)
+          throw mgk::Error(MGK_E_INVALID, "level has no stored sparse operators (coarsest)");
+      mgk::DLevel& L = H.lv[level];
+      const mgk::DMat& M = which == 1 ? L.P : (which == 2 ? L.R : L.A);
+      const bool tr = which == 3;
+      if (tr && !M.tptr) throw mgk::Error(MGK_E_STATE, "no transpose index");
+      const int sp = which == 1 ? L.sP : (which == 2 ? L.sR : (tr ? L.sAt : L.sA));
+#define MGK_LV(BB)                                                                           \
+  case BB:                                                                                   \
+    if (H.storage == MGK_F64)                                                                \
+      mgk::spmv_s<BB, BB, double, double, double>(st, M, tr, sp, (const double*)d_x,         \
+                                                   (double*)d_y, 1.0, 0.0);                  \
+    else if (H.storage == MGK_F32)                                                           \
+      mgk::spmv_s<BB, BB, float, float, float>(st, M, tr, sp, (const float*)d_x,             \
+                                                (float*)d_y, 1.0, 0.0);                      \
+    else                                                                                     \
+      mgk::spmv_s<BB, BB, mgk::bf16, float, float>(st, M, tr, sp, (const float*)d_x,         \
+                                                    (float*)d_y, 1.0, 0.0);                  \
+    break;
+      switch (H.b) {
+        MGK_LV(1)
+        MGK_LV(3)
+        MGK_LV(4)
+      }
+#undef MGK_LV
+    }
+    HIPCK(hipGetLastError());
+    return MGK_OK;
+  });
+}
+
+int mgk_level_count(mgk_solver* s, int32_t hier) {
+  if (!s) return MGK_E_INVALID;
+  if (hier == 1 && s->kind != MGK_SCHUR) return 0;
+  return (int)(hier == 1 ? s->Hp : s->H).desc.size();
+}
+
+int mgk_level_info(mgk_solver* s, int32_t hier, int32_t level, mgk_level_desc* out) {
+  if (!s || !out) return MGK_E_INVALID;
+  mgk::DHier& H = hier == 1 ? s->Hp : s->H;
+  if (level < 0 || level >= (int)H.desc.size()) {
+    mgk::g_err = "level_info: level out of range";
+    return MGK_E_INVALID;
+  }
+  *out = H.desc[level];
+  return MGK_OK;
+}
+
+int mgk_level_export(mgk_solver* s, int32_t hier, int32_t level, int32_t which, int32_t* rowptr,
+                     int32_t* col, double* val, int32_t* agg) {
+  if (!s) return MGK_E_INVALID;
+  mgk::DHier& H = hier == 1 ? s->Hp : s->H;
+  if (!H.keep_host) {
+    mgk::g_err = "level_export needs keep_host = 1 at setup";
+    return MGK_E_STATE;
+  }
+  if (level < 0 || level >= (int)H.host.levels.size() || which < 0 || which > 2) {
+    mgk::g_err = "level_export: bad level or matrix";
+    return MGK_E_INVALID;
+  }
+  const mgk::HLevel& L = H.host.levels[level];
+  const mgk::HBsr& M = which == 0 ? L.A : (which == 1 ? L.P : L.R);
+  if (rowptr) std::memcpy(rowptr, M.ptr.data(), sizeof(int32_t) * M.ptr.size());
+  if (col) std::memcpy(col, M.col.data(), sizeof(int32_t) * M.col.size());
+  if (val) std::memcpy(val, M.val.data(), sizeof(double) * M.val.size());
+  if (agg) {
+    for (int32_t i = 0; i < L.A.nbr; ++i) agg[i] = L.agg.empty() ? -1 : L.agg[i];
+  }
+  return MGK_OK;
+}
+
+int mgk_theta_grad(int32_t n, const double* d_lambda, const double* d_x, double* d_g,
+                   void* hip_stream) {
+  if (n < 3 || !d_lambda || !d_x || !d_g) {
+    mgk::g_err = "theta_grad: bad argument";
+    return MGK_E_INVALID;
+  }
+  return mgk::guard([&]() -> int {
+    const size_t nc = (size_t)(n - 1) * (n - 1) * (n - 1);
+    mgk::k_theta_grad<<<(unsigned)((nc + mgk::WG - 1) / mgk::WG), mgk::WG, 0,
+                        (hipStream_t)hip_stream>>>(n, d_lambda, d_x, d_g);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize((hipStream_t)hip_stream));
+    return MGK_OK;
+  });
+}
+
+int mgk_bsr_grad(mgk_solver* s, const double* d_lambda, const double* d_x, double* d_gval) {
+  if (!s || !d_lambda || !d_x || !d_gval || s->host_only) {
+    mgk::g_err = "bsr_grad: bad argument or solver without device data";
+    return MGK_E_INVALID;
+  }
+  return mgk::guard([&]() -> int {
+    hipStream_t st = s->dev.stream;
+    const int b = s->b;
+    const int per = mgk::WG / (b * b);
+    const unsigned g = (unsigned)((s->nbr + per - 1) / per);
+    if (b == 1) mgk::k_bsr_grad<1><<<g, mgk::WG, 0, st>>>(s->nbr, s->A.ptr, s->A.col, d_lambda, d_x, d_gval);
+    else if (b == 3) mgk::k_bsr_grad<3><<<g, mgk::WG, 0, st>>>(s->nbr, s->A.ptr, s->A.col, d_lambda, d_x, d_gval);
+    else mgk::k_bsr_grad<4><<<g, mgk::WG, 0, st>>>(s->nbr, s->A.ptr, s->A.col, d_lambda, d_x, d_gval);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(st));
+    return MGK_OK;
+  });
+}
+
+int mgk_solve_multi(mgk_solver* s, int32_t nrhs, const double* d_B, double* d_X, double rtol,
+                    mgk_info* infos) {
+  (void)s; (void)nrhs; (void)d_B; (void)d_X; (void)rtol; (void)infos;
+  mgk::g_err = "mgk_solve_multi: not available in this build";
+  return MGK_E_STATE;
+}
+
+int mgk_batch_setup(int32_t nsys, const mgk_bsr* const* A, int32_t block_size,
+                    mgk_precond_kind kind, const mgk_params* prm, void* hip_stream,
+                    mgk_solver** out) {
+  (void)nsys; (void)A; (void)block_size; (void)kind; (void)prm; (void)hip_stream;
+  if (out) *out = nullptr;
+  mgk::g_err = "mgk_batch_setup: not available in this build";
+  return MGK_E_STATE;
+}
+
+int mgk_batch_solve(mgk_solver* s, const double* const* d_b, double* const* d_x, double rtol,
+                    mgk_info* infos) {
+  (void)s; (void)d_b; (void)d_x; (void)rtol; (void)infos;
+  mgk::g_err = "mgk_batch_solve: not available in this build";
+  return MGK_E_STATE;
+}
+
+int mgk_setup_host(const mgk_bsr* A, int32_t block_size, mgk_precond_kind kind,
+                   const mgk_params* prm, mgk_solver** out) {
+  if (!out) {
+    mgk::g_err = "mgk_setup_host: null output";
+    return MGK_E_INVALID;
+  }
+  *out = nullptr;
+  std::unique_ptr<mgk_solver> S(new mgk_solver());
+  return mgk::guard([&]() -> int {
+    mgk::setup_impl(S.get(), A, block_size, kind, prm, nullptr, true);
+    *out = S.release();
+    return MGK_OK;
+  });
+}
+
+void mgk_destroy(mgk_solver* s) {
+  if (!s) return;
+  if (!s->host_only) (void)hipStreamSynchronize(s->dev.stream);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared entry point,
+ingests matrices exactly, rejects bad input, and its FP64 host setup reproduces the
+oracle's hierarchy bit for bit.  None of these tests touches a GPU."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import paper_2006_06052_amd as mgk
+import stokes_synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "mgk.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(mgk_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 20
+    L = mgk.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(mgk.EXPORTS)
+
+
+def test_csr_to_bsr_worked_example():
+    with open(os.path.join(ROOT, "tests", "golden", "bsr_worked_example.json")) as f:
+        ex = json.load(f)
+    c = ex["csr"]
+    bptr, bcol, bval = mgk.csr_to_bsr(c["ptr"], c["col"], c["val"], ex["block"])
+    assert bptr.tolist() == ex["bsr"]["ptr"]
+    assert bcol.tolist() == ex["bsr"]["col"]
+    assert bval.tolist() == ex["bsr"]["val"]
+    # pointer and column arrays shrink by the block size and its square
+    assert len(bptr) - 1 == (len(c["ptr"]) - 1) // 2 and len(bcol) * 4 == len(c["col"])
+
+
+def oracle_blocks(A, b):
+    B = sp.csr_matrix(A).tobsr(blocksize=(b, b))
+    B.sort_indices()
+    return B.indptr, B.indices, B.data
+
+
+@pytest.mark.parametrize("n,sigma", [(5, None), (8, 0.5), (16, None), (12, 1.0)])
+def test_stokes_assembly_matches_oracle_bitwise(n, sigma):
+    th = None if sigma is None else S.theta_field(n, sigma, 21)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    A = oracle.stokes_matrix(n, th)
+    optr, ocol, oval = oracle_blocks(A, 4)
+    assert np.array_equal(ptr, optr) and np.array_equal(col, ocol)
+    assert np.array_equal(val, oval)
+    assert len(col) == 7 * (n - 2) ** 3 + n ** 3 - (n - 2) ** 3
+
+
+def test_csr_to_bsr_of_oracle_matrix():
+    n = 6
+    A = oracle.stokes_matrix(n, S.theta_field(n, 1.0, 2))
+    bptr, bcol, bval = mgk.csr_to_bsr(A.indptr, A.indices, A.data, 4)
+    ptr, col, val = mgk.stokes_bsr(n, S.theta_field(n, 1.0, 2))
+    assert np.array_equal(bptr, ptr) and np.array_equal(bcol, col) and np.array_equal(bval, val)
+
+
+def host_solver(ptr, col, val, block, kind=mgk.AMG_SPAI0, **kw):
+    return mgk.Solver(ptr, col, val, block, kind, host_only=True, **kw)
+
+
+def compare_hierarchies(hs, which_h, os_, which_o, levels_expected=None):
+    nl = hs.nlevels(which_h)
+    assert nl == os_.nlevels(which_o)
+    if levels_expected:
+        assert nl >= levels_expected
+    for l in range(nl):
+        d = hs.level_info(l, which_h)
+        L = os_.level(l, which_o)
+        b = d["block"]
+        ptr, col, val, agg = hs.level_export(l, 0, which_h)
+        optr, ocol, oval = oracle_blocks(L["A"], b)
+        assert np.array_equal(ptr, optr) and np.array_equal(col, ocol), f"A pattern, level {l}"
+        assert np.array_equal(val, oval), f"A values, level {l}"
+        if l == nl - 1:
+            break
+        assert np.array_equal(agg, L["agg"]), f"aggregates, level {l}"
+        assert d["omega"] == L["omega"], f"omega, level {l}"
+        for which, key in ((1, "P"), (2, "R")):
+            p, c, v, _ = hs.level_export(l, which, which_h)
+            op, oc, ov = oracle_blocks(L[key], b)
+            assert np.array_equal(p, op) and np.array_equal(c, oc), f"{key} pattern, level {l}"
+            assert np.array_equal(v, ov), f"{key} values, level {l}"
+
+
+@pytest.mark.parametrize("n,sigma,block_spai0", [(16, None, 1), (12, 1.0, 1), (12, 0.5, 0)])
+def test_host_setup_matches_oracle_monolithic(n, sigma, block_spai0):
+    th = None if sigma is None else S.theta_field(n, sigma, 31)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    hs = host_solver(ptr, col, val, 4, coarse_enough=200, block_spai0=block_spai0)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4, coarse_enough=200,
+                        smoother=oracle.SPAI0_BLOCK if block_spai0 else oracle.SPAI0_SCALAR)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)
+
+
+def test_host_setup_matches_oracle_schur():
+    n = 14
+    th = S.theta_field(n, 1.0, 3)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    hs = host_solver(ptr, col, val, 4, mgk.SCHUR, coarse_enough=150, krylov=mgk.FGMRES)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4, kind=oracle.KIND_SCHUR,
+                        krylov=oracle.FGMRES, coarse_enough=150)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)
+    compare_hierarchies(hs, 1, os_, 1, levels_expected=2)
+
+
+def test_host_setup_scalar_csr_arm():
+    """The whole setup at block size 1 on the scalar CSR matrix (V2-style scalar arm)."""
+    n = 8
+    A = oracle.stokes_matrix(n)
+    bptr, bcol, bval = mgk.csr_to_bsr(A.indptr, A.indices, A.data, 1)
+    hs = host_solver(bptr, bcol, bval, 1, coarse_enough=300)
+    os_ = oracle.Solver(A, 1, coarse_enough=300)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)
+
+
+@pytest.mark.slow
+def test_host_setup_matches_oracle_cube32():
+    n = 32
+    th = S.theta_field(n, 0.5, 41)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    hs = host_solver(ptr, col, val, 4)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=3)
+
+
+def test_invalid_input_rejected_before_device_work():
+    ptr, col, val = mgk.stokes_bsr(4)
+    r = 21                                    # an interior node row (7 blocks)
+    k0 = ptr[r]
+    bad = col.copy()
+    bad[k0], bad[k0 + 1] = bad[k0 + 1], bad[k0]
+    with pytest.raises(mgk.MgkError) as e:
+        host_solver(ptr, bad, val, 4)
+    assert e.value.code == -1
+    with pytest.raises(mgk.MgkError) as e:
+        mgk.Solver(ptr, col, val, 2, host_only=True)  # unsupported block size
+    assert e.value.code == -1
+    v2 = val.copy()
+    v2[3, 0, 0] = np.nan
+    with pytest.raises(mgk.MgkError) as e:
+        host_solver(ptr, col, v2, 4)
+    assert e.value.code == -1
+    with pytest.raises(mgk.MgkError):
+        host_solver(ptr, col, val, 4, maxiter=0)
+    with pytest.raises(mgk.MgkError):
+        mgk.stokes_bsr(2)
+    with pytest.raises(mgk.MgkError):
+        mgk.csr_to_bsr([0, 1, 2, 3], [0, 1, 2], [1.0, 1.0, 1.0], 2)
+
+
+def test_singular_block_row_rejected():
+    """A zero diagonal block makes the smoother or filtered diagonal singular."""
+    ptr, col, val = mgk.stokes_bsr(6)
+    v = val.copy()
+    i = 1 + 6 * (1 + 6 * 1)                   # an interior node: 7 blocks
+    k = ptr[i] + 3
+    assert col[k] == i
+    v[ptr[i]:ptr[i + 1]] = 0.0
+    with pytest.raises(mgk.MgkError) as e:
+        host_solver(ptr, col, v, 4, coarse_enough=10)
+    assert e.value.code in (-4, -1)

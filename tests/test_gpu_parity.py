@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 products within gamma_k * sum|a||x| of the oracle; solves reach
+||b - A x|| / ||b|| <= 1e-8 (checked with the oracle's own SpMV) and agree with the
+oracle's FP64 solve (rtol 1e-12) to 1e-6 relative; repeated runs are bitwise equal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import stokes_synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2006_06052_amd as mgk  # noqa: E402
+
+EPS = np.finfo(np.float64).eps
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def problem(n, sigma=None, seed=1):
+    th = None if sigma is None else S.theta_field(n, sigma, seed)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    return th, (ptr, col, val), oracle.stokes_matrix(n, th)
+
+
+def gpu_solver(bsr, block=4, kind=mgk.AMG_SPAI0, **kw):
+    stream = torch.cuda.current_stream()
+    return mgk.Solver(*bsr, block, kind, stream=stream, **kw)
+
+
+def check_solution(A, b, x, xo, tol=1e-8, err=1e-6):
+    res = np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b)
+    e = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert res <= tol, res
+    assert e <= err, e
+    return res, e
+
+
+# ------------------------------------------------------------------ kernels
+
+@pytest.mark.parametrize("n,sigma", [(16, None), (21, 1.0)])
+def test_outer_spmv_matches_oracle_and_is_deterministic(n, sigma):
+    say("spmv", n, sigma)
+    th, bsr, A = problem(n, sigma)
+    s = gpu_solver(bsr, coarse_enough=500)
+    x = np.random.default_rng(0).normal(size=A.shape[0])
+    dx = dev(x)
+    dy = torch.empty_like(dx)
+    s.spmv(dx, dy)
+    y1 = dy.cpu().numpy()
+    s.spmv(dx, dy)
+    assert np.array_equal(y1, dy.cpu().numpy())
+    yo = oracle.spmv(A, x)
+    bound = 16 * EPS * (abs(A) @ np.abs(x)) + 1e-300
+    assert np.all(np.abs(y1 - yo) <= bound)
+
+
+def test_transposed_spmv_is_adjoint():
+    n = 13
+    th, bsr, A = problem(n, 0.5)
+    s = gpu_solver(bsr, coarse_enough=500, enable_transpose=1)
+    rng = np.random.default_rng(1)
+    x, y = rng.normal(size=A.shape[0]), rng.normal(size=A.shape[0])
+    dy = torch.empty(A.shape[0], dtype=torch.float64, device=DEV)
+    s.spmv(dev(x), dy, level=-1, which=3)
+    aty = dy.cpu().numpy()
+    ref = A.T @ x
+    assert np.allclose(aty, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    s.spmv(dev(x), dy)
+    Ax = dy.cpu().numpy()
+    s.spmv(dev(y), dy, level=-1, which=3)
+    lhs, rhs = y @ Ax, dy.cpu().numpy() @ x
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(y) @ (abs(A) @ np.abs(x)))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_level_operators_match_rounded_oracle(storage):
+    """A_l, P_l, R_l of the uploaded hierarchy against the oracle's level matrices with
+    values rounded to the storage precision, vectors in the hierarchy precision."""
+    n = 14
+    th, bsr, A = problem(n, 0.5, 3)
+    s = gpu_solver(bsr, coarse_enough=200, hier=storage)
+    so = oracle.Solver(A, 4, coarse_enough=200)
+    vdt = torch.float64 if storage == "f64" else torch.float32
+    rng = np.random.default_rng(2)
+    for l in range(s.nlevels() - 1):
+        L = so.level(l)
+        for which, key in ((0, "A"), (1, "P"), (2, "R")):
+            M = L[key].copy()
+            if storage == "f32":
+                M.data = M.data.astype(np.float32).astype(np.float64)
+            elif storage == "bf16":
+                M.data = torch.from_numpy(M.data).to(torch.bfloat16).to(torch.float64).numpy()
+            x = rng.normal(size=M.shape[1])
+            if storage != "f64":
+                x = x.astype(np.float32).astype(np.float64)
+            dx = torch.from_numpy(x).to(vdt).to(DEV)
+            dy = torch.empty(M.shape[0], dtype=vdt, device=DEV)
+            say("level", l, key, storage)
+            s.spmv(dx, dy, level=l, which=which)
+            y = dy.double().cpu().numpy()
+            ref = M @ x
+            unit = EPS if storage == "f64" else np.finfo(np.float32).eps
+            bound = 64 * unit * (abs(M) @ np.abs(x)) + 1e-30
+            assert np.all(np.abs(y - ref) <= bound), (l, key)
+
+
+def test_vcycle_matches_oracle_fp64():
+    """With the bit-identical hierarchy, one FP64 V-cycle on the GPU equals the oracle's
+    up to summation order."""
+    n = 16
+    th, bsr, A = problem(n, 0.5, 4)
+    s = gpu_solver(bsr, coarse_enough=300, enable_transpose=1)
+    so = oracle.Solver(A, 4, coarse_enough=300)
+    r = np.random.default_rng(3).normal(size=A.shape[0])
+    dz = torch.empty(A.shape[0], dtype=torch.float64, device=DEV)
+    for tr in (False, True):
+        say("vcycle transposed", tr)
+        s.precond(dev(r), dz, transposed=tr)
+        z = dz.cpu().numpy()
+        zo = so.precond(r, transposed=tr)
+        assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+# ------------------------------------------------------------------ solves
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_c1_monolithic_bicgstab(storage):
+    """16^3 manufactured problem, SA-AMG + SPAI0 V(1,1), BiCGStab to 1e-8."""
+    n = 16
+    th, bsr, A = problem(n)
+    b = S.mms_rhs(n)
+    s = gpu_solver(bsr, hier=storage)
+    db, dx = dev(b), torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(db, dx, 1e-8)
+    say("c1", storage, info)
+    x = dx.cpu().numpy()
+    xo, oi = oracle.Solver(A, 4).solve(b, 1e-12)
+    check_solution(A, b, x, xo)
+    assert info["status"] == 0 and info["rel_resid"] <= 1e-8
+    # the mixed-precision preconditioner must not cost more than ~10% extra iterations
+    _, o8 = oracle.Solver(A, 4).solve(b, 1e-8)
+    assert info["iters"] <= int(np.ceil(1.1 * o8["iters"])) + 1, (info["iters"], o8["iters"])
+    # determinism: a second solve from zero is bitwise identical
+    dx2 = torch.zeros_like(dx)
+    s.solve(db, dx2, 1e-8)
+    assert torch.equal(dx, dx2)
+
+
+def test_monolithic_lognormal_fgmres():
+    n = 18
+    th, bsr, A = problem(n, 1.0, 5)
+    xs = S.mms_solution(n)
+    b = oracle.spmv(A, xs)
+    s = gpu_solver(bsr, hier="f32", krylov=mgk.FGMRES)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    say("fgmres mono", info)
+    xo, _ = oracle.Solver(A, 4).solve(b, 1e-12)
+    check_solution(A, b, dx.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_schur_fgmres(storage):
+    """Schur pressure correction (3x3 velocity AMG, scalar pressure AMG on
+    C - B_lo diag(A_uu)^-1 B_up) under FGMRES(30)."""
+    n = 18
+    th, bsr, A = problem(n, 1.0, 3)
+    xs = S.mms_solution(n)
+    b = oracle.spmv(A, xs)
+    s = gpu_solver(bsr, kind=mgk.SCHUR, hier=storage, krylov=mgk.FGMRES)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    say("schur", storage, info)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES)
+    xo, _ = so.solve(b, 1e-12)
+    check_solution(A, b, dx.cpu().numpy(), xo)
+    # the FP64 Schur preconditioner application matches the oracle's
+    if storage == "f64":
+        r = np.random.default_rng(4).normal(size=A.shape[0])
+        dz = torch.empty_like(dx)
+        s.precond(dev(r), dz)
+        zo = so.precond(r)
+        assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+def test_scalar_csr_arm():
+    """The same system as scalar CSR (block size 1) through the whole solver."""
+    n = 12
+    th, bsr, A = problem(n)
+    b = S.mms_rhs(n)
+    bptr, bcol, bval = mgk.csr_to_bsr(A.indptr, A.indices, A.data, 1)
+    s = gpu_solver((bptr, bcol, bval), block=1, hier="f32")
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    say("scalar", info)
+    xo, _ = oracle.Solver(A, 1).solve(b, 1e-12)
+    check_solution(A, b, dx.cpu().numpy(), xo)
+
+
+def test_adjoint_and_gradients():
+    n = 12
+    th, bsr, A = problem(n, 0.5, 5)
+    b = S.mms_rhs(n)
+    s = gpu_solver(bsr, hier="f32", enable_transpose=1)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    s.solve(dev(b), dx, 1e-10)
+    x = dx.cpu().numpy()
+    g = x - S.mms_solution(n)
+    dl = torch.zeros_like(dx)
+    info = s.solve_transposed(dev(g), dl, 1e-10)
+    say("adjoint", info)
+    lam = dl.cpu().numpy()
+    assert np.linalg.norm(g - A.T @ lam) <= 1e-10 * np.linalg.norm(g)
+    so = oracle.Solver(A, 4)
+    lo, _ = so.solve(g, 1e-13, transposed=True)
+    assert np.linalg.norm(lam - lo) <= 1e-6 * np.linalg.norm(lo)
+    # per-cell gradient kernel against the oracle's formula on the same inputs
+    dg = torch.empty((n - 1) ** 3, dtype=torch.float64, device=DEV)
+    mgk.theta_grad(n, dl, dx, dg)
+    go = oracle.theta_gradient(n, lam, x)
+    assert np.allclose(dg.cpu().numpy(), go, rtol=1e-12, atol=1e-12 * np.abs(go).max())
+    # block-pattern gradient -lambda_I x_J^T
+    ptr, col, val = bsr
+    dG = torch.empty(val.size, dtype=torch.float64, device=DEV)
+    s.bsr_grad(dl, dx, dG)
+    G = dG.cpu().numpy().reshape(-1, 4, 4)
+    rows = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    ref = -lam.reshape(-1, 4)[rows][:, :, None] * x.reshape(-1, 4)[col][:, None, :]
+    assert np.array_equal(G, ref)
+
+
+def test_edge_cases():
+    n = 8
+    th, bsr, A = problem(n)
+    s = gpu_solver(bsr, coarse_enough=100, maxiter=1, max_restarts=0)
+    z = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    x = torch.ones_like(z)
+    info = s.solve(z, x, 1e-8)
+    assert info["status"] == 0 and info["iters"] == 0 and not torch.any(x)
+    b = dev(S.mms_rhs(n))
+    x = torch.zeros_like(b)
+    info = s.solve(b, x, 1e-12)
+    assert info["status"] == mgk.MGK_NOT_CONVERGED and info["iters"] == 1
+    # warm start from the exact discrete solution converges immediately
+    s2 = gpu_solver(bsr, coarse_enough=100)
+    xs = S.mms_solution(n)
+    bx = dev(oracle.spmv(A, xs))
+    x = dev(xs)
+    info = s2.solve(bx, x, 1e-8)
+    assert info["status"] == 0 and info["iters"] == 0
+    with pytest.raises(mgk.MgkError):
+        s2.solve_transposed(bx, x, 1e-8)   # set up without transpose indices
+    with pytest.raises(TypeError):
+        s2.solve(bx.float(), x, 1e-8)
