@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the AMG-preconditioned Krylov Stokes solve on one MI355X.
+
+Workload: stabilized equal-order finite-difference Stokes on the unit cube with
+96^3 nodes (3,538,944 unknowns, interleaved [u,v,w,p] in 4x4 blocks), manufactured
+right-hand side plus seeded N(0, 1e-3) noise on interior rows; monolithic
+smoothed-aggregation AMG with SPAI(0), one V(1,1) cycle per BiCGStab iteration,
+solved from x0 = 0 to ||b - A x|| <= 1e-8 ||b||.
+
+One step = one complete solve with the matrix, hierarchy and right-hand side
+already resident in HBM.  The headline arm stores the hierarchy in FP32 under the
+FP64 BiCGStab (the paper's mixed-precision variant); the FP64 BSR arm, the BF16
+arm and the scalar-CSR FP64 arm (block size 1 throughout) run the same solve for
+the speedup figures.
+
+The roofline entry is the FP64 4x4 BSR SpMV of the outer operator (two launches per
+BiCGStab iteration, the largest single kernel of the solve): every launch inside the
+timed solves is bracketed by HIP events on the library's stream, and the average
+duration is set against the algorithmic bytes nnzb*(16*8 + 4) + 4*(n_brows + 1)
++ 2*n_brows*4*8 per launch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve time to rtol 1e-8 (s) + BSR SpMV HBM GB/s; mixed-precision vs FP64 speedup"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bsr_to_scalar_csr(ptr, col, val):
+    """Scalar CSR of a 4x4 BSR matrix keeping only nonzero entries (input preparation for
+    the scalar arm)."""
+    import numpy as np
+    nb = len(ptr) - 1
+    rows = np.repeat(np.arange(nb), np.diff(ptr))
+    r = (4 * rows[:, None, None] + np.arange(4)[None, :, None]) * np.ones((1, 1, 4), np.int64)
+    c = (4 * col[:, None, None] + np.arange(4)[None, None, :]) * np.ones((1, 4, 1), np.int64)
+    keep = val != 0.0
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val[keep], (r[keep], c[keep])), shape=(4 * nb, 4 * nb))
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+
+
+def time_solves(s, db, steps, warmup, torch):
+    """K timed solves from x0 = 0; also the summed HIP-event durations of the outer
+    SpMV launches inside those solves."""
+    dx = torch.zeros_like(db)
+    info = None
+    for _ in range(warmup):
+        dx.zero_()
+        info = s.solve(db, dx, 1e-8)
+    torch.cuda.synchronize()
+    times, spmv_ms, spmv_calls = [], 0.0, 0
+    for _ in range(steps):
+        dx.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(db, dx, 1e-8)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        spmv_ms += info["spmv_ms"]
+        spmv_calls += info["spmv_calls"]
+    return times, info, dx, (spmv_ms, spmv_calls)
+
+
+def spmv_timing(s, n_rows, torch, reps=50):
+    """Average duration of the FP64 outer BSR SpMV over reps back-to-back launches,
+    with HIP events recorded on the stream the library launches on."""
+    x = torch.rand(n_rows, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        s.spmv(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        s.spmv(x, y)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def cpu_baseline(n, b_np, iters_scale, log_fn):
+    """The oracle as it stands (scalar CSR FP64, OpenMP SpMV) on the host cores: setup once
+    (not part of the metric), then a bounded run of 3 BiCGStab iterations, scaled to the
+    iteration count of a full solve."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    A = oracle.stokes_matrix(n)
+    s = oracle.Solver(A, 4, maxiter=3, max_restarts=0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, info = s.solve(b_np, 1e-8)
+    t_it = (time.perf_counter() - t0) / max(info["iters"], 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log_fn(f"cpu_baseline: setup {t_setup:.1f}s, {t_it:.3f}s per iteration, {threads} threads")
+    return {"value": t_it * iters_scale, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle setup at {n}^3 ({t_setup:.1f}s, not in the metric), then "
+                      f"{info['iters']} BiCGStab iterations timed ({t_it:.3f}s each) and "
+                      f"scaled to {iters_scale} iterations (the FP64 GPU arm's count)",
+            "setup_s": t_setup, "s_per_iter": t_it}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=96)
+    ap.add_argument("--arms", default="bsr_f32,bsr_f64,bsr_bf16,csr_f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="only the FP64 BSR SpMV loop (for counter collection)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
+                                   "slab decomposition is a design note, not built"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2006_06052_amd as mgk
+    import stokes_synth as S
+
+    n = args.n
+    log(f"bench: assembling {n}^3")
+    ptr, col, val = mgk.stokes_bsr(n)
+    b = S.c2_rhs(n)
+    N = b.size
+    db = torch.from_numpy(b).cuda()
+    stream = torch.cuda.current_stream()
+    nnzb = int(ptr[-1])
+
+    def make(arm):
+        t0 = time.perf_counter()
+        if arm == "csr_f64":
+            sp_, sc_, sv_ = bsr_to_scalar_csr(ptr, col, val)
+            bp, bc, bv = mgk.csr_to_bsr(sp_, sc_, sv_, 1)
+            s = mgk.Solver(bp, bc, bv, 1, mgk.AMG_SPAI0, stream=stream, hier=mgk.F64)
+        else:
+            hier = {"bsr_f64": mgk.F64, "bsr_f32": mgk.F32, "bsr_bf16": mgk.BF16}[arm]
+            s = mgk.Solver(ptr, col, val, 4, mgk.AMG_SPAI0, stream=stream, hier=hier,
+                           time_spmv=1)
+        return s, time.perf_counter() - t0
+
+    spmv_bytes = nnzb * (16 * 8 + 4) + 4 * (len(ptr)) + 2 * (len(ptr) - 1) * 4 * 8
+    if args.spmv_only:
+        s, _ = make("bsr_f64")
+        t = spmv_timing(s, N, torch, reps=200)
+        log(f"spmv: {t * 1e6:.1f} us, {spmv_bytes / t / 1e9:.0f} GB/s")
+        return
+
+    arms = [a for a in args.arms.split(",") if a]
+    head = arms[0]
+    results = {}
+    roofline = None
+    for arm in arms:
+        log(f"bench: setup {arm}")
+        s, t_setup = make(arm)
+        steps = args.steps if arm == head else 1
+        times, info, dx, (sp_ms, sp_calls) = time_solves(s, db, steps,
+                                                         args.warmup if arm == head else 1,
+                                                         torch)
+        res = {"solve_s": float(np.median(times)), "times_s": times, "iters": info["iters"],
+               "rel_resid": info["rel_resid"], "status": info["status"],
+               "levels": info["levels"], "setup_s": t_setup,
+               "device_bytes": info["device_bytes"]}
+        if sp_calls:
+            t_in = sp_ms * 1e-3 / sp_calls
+            res["outer_spmv_us"] = t_in * 1e6
+            res["outer_spmv_gbs"] = spmv_bytes / t_in / 1e9
+        log(f"bench: {arm}: {res['solve_s']:.3f}s, {info['iters']} iterations, "
+            f"resid {info['rel_resid']:.2e}, setup {t_setup:.1f}s, "
+            f"outer spmv {res.get('outer_spmv_us', 0):.1f}us")
+        if arm == head:
+            head_times = times
+            t_iso = spmv_timing(s, N, torch)
+            ach = spmv_bytes / (sp_ms * 1e-3 / sp_calls) / 1e9
+            roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "mgk::k_spmv<4, 4, S, U, false, double, double, double, "
+                                  "double> (FP64 4x4 BSR outer operator)",
+                        "bytes_per_launch": spmv_bytes,
+                        "avg_launch_us": sp_ms * 1e3 / sp_calls, "launches": sp_calls,
+                        "isolated_loop_us": t_iso * 1e6,
+                        "isolated_loop_gbs": spmv_bytes / t_iso / 1e9}
+        results[arm] = res
+        del s
+        torch.cuda.empty_cache()
+
+    tpath = os.path.join(ROOT, "profiles", "spmv_bsr4_f64_cube96_traffic.json")
+    if roofline and os.path.exists(tpath):
+        with open(tpath) as f:
+            tr = json.load(f)
+        if tr.get("kernel") == roofline["kernel"]:
+            roofline["traffic"] = tr.get("bytes_per_launch")
+
+    value = float(np.median(head_times))
+    out = {"metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": value * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": {"bsr_f32": "f64+f32", "bsr_bf16": "f64+bf16"}.get(head, "f64"),
+           "data": "synthetic",
+           "config": {"workload": f"cube{n}_stabilized_stokes_mms_noise", "n_nodes": n ** 3,
+                      "unknowns": N, "block": 4, "nnzb": nnzb,
+                      "precond": "SA-AMG, SPAI(0), V(1,1)", "krylov": "BiCGStab",
+                      "rtol": 1e-8, "arm": head},
+           "arms": results}
+    if "bsr_f64" in results:
+        f64 = results["bsr_f64"]["solve_s"]
+        for a in ("bsr_f32", "bsr_bf16", "csr_f64"):
+            if a in results:
+                out[f"speedup_{a}_vs_bsr_f64"] = f64 / results[a]["solve_s"]
+    out["roofline"] = roofline
+    if not args.no_cpu_baseline and os.environ.get("BENCH_NO_CPU") != "1":
+        scale = results.get("bsr_f64", results[head])["iters"]
+        out["cpu_baseline"] = cpu_baseline(n, b, scale, log)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,6 +87,9 @@ typedef struct {
   int32_t keep_host;       /* 1: keep FP64 host copies of every level for
                               mgk_level_export (default 0) */
   int32_t enable_transpose;/* 1: build the A^T indices for adjoint solves (default 0) */
+  int32_t time_spmv;       /* 1: time every outer-operator SpMV of a solve with HIP
+                              events on the solver's stream (mgk_info.spmv_ms) */
+  int32_t reserved;
 } mgk_params;
 
 typedef struct {
@@ -98,6 +101,9 @@ typedef struct {
   double setup_ms;
   double solve_ms;
   int64_t device_bytes;    /* device memory held by the solver */
+  double spmv_ms;          /* with time_spmv: summed duration of the outer SpMVs */
+  int32_t spmv_calls;      /* ... and their number */
+  int32_t reserved;
 } mgk_info;
 
 typedef struct {

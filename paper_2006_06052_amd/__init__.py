@@ -39,13 +39,15 @@ class Params(C.Structure):
                 ("max_restarts", C.c_int32), ("hier", C.c_int32), ("coarse_enough", C.c_int32),
                 ("max_levels", C.c_int32), ("block_spai0", C.c_int32),
                 ("eps_strong", C.c_double), ("jacobi_omega", C.c_double),
-                ("keep_host", C.c_int32), ("enable_transpose", C.c_int32)]
+                ("keep_host", C.c_int32), ("enable_transpose", C.c_int32),
+                ("time_spmv", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("levels", C.c_int32), ("restarts", C.c_int32),
                 ("status", C.c_int32), ("rel_resid", C.c_double), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double), ("device_bytes", C.c_int64)]
+                ("solve_ms", C.c_double), ("device_bytes", C.c_int64),
+                ("spmv_ms", C.c_double), ("spmv_calls", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -136,30 +136,53 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
 }
 
 // Partial sum of row r of block row i over blocks s, s+S, ...; combined over
-// the S lanes of the row (result valid in the s == 0 lane).
-template <int BR, int BC, int S, bool TRANS, class TV, class TX, class TA>
+// the S lanes of the row (result valid in the s == 0 lane).  U blocks are
+// handled per step with every load issued before the first use, so each lane
+// keeps U independent gathers in flight (the fine-level rows are short and the
+// loop would otherwise be bound by one dependent col -> x chain per block).
+// The accumulation order is ascending k for every (U, S).
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA>
 __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int* __restrict__ ptr,
                                           const int* __restrict__ col, const int* __restrict__ blk,
                                           const TV* __restrict__ val, const TX* __restrict__ x) {
   TA acc = 0;
   if (L.active && L.i < nbr) {
     const int k0 = ptr[L.i], k1 = ptr[L.i + 1];
-    for (int k = k0 + L.s; k < k1; k += S) {
-      const int j = __builtin_nontemporal_load(col + k);
-      TA xv[BC];
-      load_x<BC, TX, TA>(x + (size_t)j * BC, xv);
-      if constexpr (!TRANS) {
-        TA v[BC];
-        load_vals<BC, TV, TA>(val + (size_t)k * (BR * BC) + L.r * BC, v);
+    for (int kb = k0 + L.s; kb < k1; kb += S * U) {
+      int j[U], kk[U];
+      bool ok[U];
 #pragma unroll
-        for (int c = 0; c < BC; ++c) acc += v[c] * xv[c];
-      } else {
-        // Block kb of A (BC x BR) read by columns: (A^T)[r][c] = A_kb[c][r].
-        const int kb = __builtin_nontemporal_load(blk + k);
-        const TV* b = val + (size_t)kb * (BR * BC);
-#pragma unroll
-        for (int c = 0; c < BC; ++c) acc += load_val<TV, TA>(b + c * BR + L.r) * xv[c];
+      for (int u = 0; u < U; ++u) {
+        const int k = kb + u * S;
+        ok[u] = k < k1;
+        j[u] = ok[u] ? __builtin_nontemporal_load(col + k) : 0;
+        kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
       }
+      TA v[U][BC], xv[U][BC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ok[u]) {
+          load_x<BC, TX, TA>(x + (size_t)j[u] * BC, xv[u]);
+          if constexpr (!TRANS) {
+            load_vals<BC, TV, TA>(val + (size_t)kk[u] * (BR * BC) + L.r * BC, v[u]);
+          } else {
+            // Block kk of A (BC x BR) read by columns: (A^T)[r][c] = A_kk[c][r].
+            const TV* b = val + (size_t)kk[u] * (BR * BC);
+#pragma unroll
+            for (int c = 0; c < BC; ++c) v[u][c] = load_val<TV, TA>(b + c * BR + L.r);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < BC; ++c) {
+            v[u][c] = 0;
+            xv[u][c] = 0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc += v[u][c] * xv[u][c];
     }
   }
 #pragma unroll
@@ -197,8 +220,11 @@ __device__ __forceinline__ void wg_sum2(T& a, T& b) {
 
 // y = alpha A x + beta y   (beta == 0: y is not read).
 // With dots != 0, also per-workgroup partials of <w1, y> and (dots == 2)
-// <y, y> for the fused Krylov products (FP64 outer operator).
-template <int BR, int BC, int S, bool TRANS, class TV, class TX, class TY, class TA>
+// <y, y> for the fused Krylov products (FP64 outer operator).  Workgroup w
+// processes the contiguous row tiles [w*T/G, (w+1)*T/G) of the T tiles, so a
+// reduced grid (G < T) keeps the partial count, and the finalizing reduction,
+// small.
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TY, class TA>
 __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ ptr,
                                              const int* __restrict__ col,
                                              const int* __restrict__ blk,
@@ -207,19 +233,23 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
                                              TA alpha, TA beta, int dots,
                                              const double* __restrict__ w1,
                                              const double* __restrict__ w2,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, int ntiles) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const LaneInfo L = lane_info<BR, S>(lw);
-  TA acc = row_product<BR, BC, S, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, x);
+  const int t0 = (int)(((long long)lw * ntiles) / gridDim.x);
+  const int t1 = (int)(((long long)(lw + 1) * ntiles) / gridDim.x);
   double d1 = 0.0, d2 = 0.0;
-  if (L.active && L.s == 0 && L.i < nbr) {
-    const size_t row = (size_t)L.i * BR + L.r;
-    TA out = alpha * acc;
-    if (beta != TA(0)) out += beta * (TA)y[row];
-    y[row] = (TY)out;
-    if (dots) {
-      d1 = w1[row] * (double)out;
-      if (dots == 2) d2 = (double)out * (double)out;
+  for (int tile = t0; tile < t1; ++tile) {
+    const LaneInfo L = lane_info<BR, S>(tile);
+    TA acc = row_product<BR, BC, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, x);
+    if (L.active && L.s == 0 && L.i < nbr) {
+      const size_t row = (size_t)L.i * BR + L.r;
+      TA out = alpha * acc;
+      if (beta != TA(0)) out += beta * (TA)y[row];
+      y[row] = (TY)out;
+      if (dots) {
+        d1 += w1[row] * (double)out;
+        if (dots == 2) d2 += (double)out * (double)out;
+      }
     }
   }
   if (dots) {
@@ -229,10 +259,11 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
       if (dots == 2) part[gridDim.x + lw] = d2;
     }
   }
+  (void)w2;
 }
 
 // t = f - A z  (A may be rectangular: BR x BC blocks).
-template <int BR, int BC, int S, bool TRANS, class TV, class TX, class TF, class TA>
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TF, class TA>
 __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const int* __restrict__ blk,
@@ -241,7 +272,7 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
                                                  const TX* __restrict__ z, TX* __restrict__ t) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S>(lw);
-  TA acc = row_product<BR, BC, S, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
+  TA acc = row_product<BR, BC, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
   if (L.active && L.s == 0 && L.i < nbr) {
     const size_t row = (size_t)L.i * BR + L.r;
     t[row] = (TX)((TA)f[row] - acc);
@@ -249,7 +280,8 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
 }
 
 // Post-smoothing: zout = z + M (f - A z), M block diagonal (M^T when TRANS).
-template <int BR, int S, bool TRANS, class TV, class TX, class TF, class TO, class TM, class TA>
+template <int BR, int S, int U, bool TRANS, class TV, class TX, class TF, class TO, class TM,
+          class TA>
 __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
                                                const int* __restrict__ col,
                                                const int* __restrict__ blk,
@@ -259,7 +291,7 @@ __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ 
                                                const TX* __restrict__ z, TO* __restrict__ zout) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S>(lw);
-  TA acc = row_product<BR, BR, S, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
+  TA acc = row_product<BR, BR, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
   const bool own = L.active && L.i < nbr;
   TA res = 0;
   if (own && L.s == 0) {
@@ -365,26 +397,34 @@ enum FinOp {
 __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int count,
                                                  int two, int op, int i0, int i1,
                                                  double* __restrict__ sc) {
-  double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < count; k += WG) {
-    a += part[k];
-    if (two) b += part[count + k];
+  double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < count; k += 4 * WG) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kq = k + q * WG;
+      if (kq < count) {
+        a[q] += part[kq];
+        if (two) b[q] += part[count + kq];
+      }
+    }
   }
-  wg_sum2(a, b);
+  double sa = (a[0] + a[1]) + (a[2] + a[3]), sb = (b[0] + b[1]) + (b[2] + b[3]);
+  wg_sum2(sa, sb);
   if (threadIdx.x != 0) return;
+  const double a0 = sa, b0 = sb;
   switch (op) {
-    case FIN_STORE1: sc[i0] = a; break;
-    case FIN_STORE2: sc[i0] = a; sc[i1] = b; break;
-    case FIN_ALPHA: sc[SC_RV] = a; sc[SC_ALPHA] = sc[SC_RHO1] / a; break;
+    case FIN_STORE1: sc[i0] = a0; break;
+    case FIN_STORE2: sc[i0] = a0; sc[i1] = b0; break;
+    case FIN_ALPHA: sc[SC_RV] = a0; sc[SC_ALPHA] = sc[SC_RHO1] / a0; break;
     case FIN_OMEGA:
-      sc[SC_TS] = a;
-      sc[SC_TT] = b;
-      sc[SC_OMEGA] = b != 0.0 ? a / b : 0.0;
+      sc[SC_TS] = a0;
+      sc[SC_TT] = b0;
+      sc[SC_OMEGA] = b0 != 0.0 ? a0 / b0 : 0.0;
       break;
     case FIN_RHO:
-      sc[SC_RR] = a;
+      sc[SC_RR] = a0;
       sc[SC_RHO] = sc[SC_RHO1];
-      sc[SC_RHO1] = b;
+      sc[SC_RHO1] = b0;
       break;
   }
 }

@@ -19,8 +19,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -84,6 +88,10 @@ static uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
+struct Tile {
+  int s = 1, u = 4;
+};
+
 // Device block matrix in a storage precision, with optional column index
 // (CSC over blocks) for products with the transpose.
 struct DMat {
@@ -94,6 +102,7 @@ struct DMat {
   void* val = nullptr;
   int *tptr = nullptr, *trow = nullptr, *tblk = nullptr;
   double avg_row = 0.0, avg_col = 0.0;
+  Tile tile, ttile;          // engine tiles for products with A and with A^T
 };
 
 static DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index) {
@@ -142,13 +151,6 @@ static DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_ind
 
 // ---------------------------------------------------------------- sparse launch
 
-// Lanes per block row: S splits long rows (coarse Galerkin levels) over more
-// lanes; short fine-level rows keep one lane per scalar row.
-static int pick_split(int br, double avg) {
-  if (br == 1) return avg >= 24 ? 8 : (avg >= 6 ? 4 : (avg >= 3 ? 2 : 1));
-  return avg >= 24 ? 4 : (avg >= 12 ? 2 : 1);
-}
-
 template <int BR, int S>
 static int nwg_rows(int nbr) {
   return std::max(1, (nbr + RowMap<BR, S>::ROWS - 1) / RowMap<BR, S>::ROWS);
@@ -157,10 +159,34 @@ static int nwg_rows(int nbr) {
 template <class TV>
 using AccOf = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
 
+// Tile of the block-row engine: S lanes split a block row, U blocks per step.
+// Candidates below: few lanes and deep unrolling for the short fine-level rows,
+// many lanes for the long rows of coarse Galerkin levels and restrictions.
+#define MGK_TILES_B(CASE) \
+  CASE(1, 4) CASE(1, 8) CASE(2, 4) CASE(2, 8) CASE(4, 4) CASE(8, 4) CASE(16, 2)
+#define MGK_TILES_1(CASE) CASE(1, 8) CASE(2, 4) CASE(4, 4) CASE(8, 4) CASE(16, 2) CASE(32, 2)
+
+template <int BR, class F>
+static void tile_switch(const Tile& t, F&& launch) {
+#define MGK_TCASE(SS, UU)                                   \
+  if (t.s == SS && t.u == UU) {                             \
+    launch(std::integral_constant<int, SS>(), std::integral_constant<int, UU>()); \
+    return;                                                 \
+  }
+  if constexpr (BR == 1) {
+    MGK_TILES_1(MGK_TCASE)
+  } else {
+    MGK_TILES_B(MGK_TCASE)
+  }
+#undef MGK_TCASE
+  throw Error(MGK_E_INVALID, "no kernel for tile s=" + std::to_string(t.s) + " u=" +
+                                 std::to_string(t.u));
+}
+
 // y = alpha A x + beta y with optional fused dots (FP64 operator only).
 template <int BR, int BC, class TV, class TX, class TY>
-static void spmv_s(hipStream_t st, const DMat& M, bool trans, int S, const TX* x, TY* y,
-                   double alpha, double beta, int dots = 0, const double* w1 = nullptr,
+static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TX* x,
+                   TY* y, double alpha, double beta, int dots = 0, const double* w1 = nullptr,
                    const double* w2 = nullptr, double* part = nullptr, int* nwg_out = nullptr) {
   using TA = AccOf<TV>;
   const int nrows = trans ? M.nbc : M.nbr;
@@ -168,33 +194,24 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, int S, const TX* x
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const TV* v = (const TV*)M.val;
-#define MGK_SPMV_CASE(SS)                                                                   \
-  case SS: {                                                                                \
-    const int g = nwg_rows<BR, SS>(nrows);                                                  \
-    if (nwg_out) *nwg_out = g;                                                              \
-    if (trans)                                                                              \
-      k_spmv<BR, BC, SS, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(                           \
-          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part);                \
-    else                                                                                    \
-      k_spmv<BR, BC, SS, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(                          \
-          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part);                \
-    break;                                                                                  \
-  }
-  switch (S) {
-    MGK_SPMV_CASE(1)
-    MGK_SPMV_CASE(2)
-    MGK_SPMV_CASE(4)
-    default:
-      if constexpr (BR == 1) {
-        switch (S) { MGK_SPMV_CASE(8) }
-      }
-      break;
-  }
-#undef MGK_SPMV_CASE
+  tile_switch<BR>(tile, [&](auto SS, auto UU) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+    const int nt = nwg_rows<BR, S_>(nrows);
+    // fused dots: at most 2048 workgroups (one full occupancy wave of 4-wave
+    // groups on 256 CUs), each over a contiguous range of row tiles
+    const int g = dots ? std::min(nt, 2048) : nt;
+    if (nwg_out) *nwg_out = g;
+    if (trans)
+      k_spmv<BR, BC, S_, U_, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part, nt);
+    else
+      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part, nt);
+  });
 }
 
 template <int BR, int BC, class TV, class TX, class TF>
-static void residual_s(hipStream_t st, const DMat& M, bool trans, int S, const TF* f,
+static void residual_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TF* f,
                        const TX* z, TX* t) {
   using TA = AccOf<TV>;
   const int nrows = trans ? M.nbc : M.nbr;
@@ -202,61 +219,165 @@ static void residual_s(hipStream_t st, const DMat& M, bool trans, int S, const T
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const TV* v = (const TV*)M.val;
-#define MGK_RES_CASE(SS)                                                                    \
-  case SS: {                                                                                \
-    const int g = nwg_rows<BR, SS>(nrows);                                                  \
-    if (trans)                                                                              \
-      k_residual<BR, BC, SS, true, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f, \
-                                                                      z, t);                \
-    else                                                                                    \
-      k_residual<BR, BC, SS, false, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,   \
-                                                                       f, z, t);            \
-    break;                                                                                  \
-  }
-  switch (S) {
-    MGK_RES_CASE(1)
-    MGK_RES_CASE(2)
-    MGK_RES_CASE(4)
-    default:
-      if constexpr (BR == 1) {
-        switch (S) { MGK_RES_CASE(8) }
-      }
-      break;
-  }
-#undef MGK_RES_CASE
+  tile_switch<BR>(tile, [&](auto SS, auto UU) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+    const int g = nwg_rows<BR, S_>(nrows);
+    if (trans)
+      k_residual<BR, BC, S_, U_, true, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
+                                                                          z, t);
+    else
+      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
+                                                                           z, t);
+  });
 }
 
 template <int B, class TV, class TX, class TF, class TO, class TM>
-static void smooth_s(hipStream_t st, const DMat& M, bool trans, int S, const TM* Mb, const TF* f,
-                     const TX* z, TO* zout) {
+static void smooth_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TM* Mb,
+                     const TF* f, const TX* z, TO* zout) {
   using TA = AccOf<TV>;
   const int nrows = M.nbr;
   const int* p = trans ? M.tptr : M.ptr;
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const TV* v = (const TV*)M.val;
-#define MGK_SM_CASE(SS)                                                                    \
-  case SS: {                                                                               \
-    const int g = nwg_rows<B, SS>(nrows);                                                  \
-    if (trans)                                                                             \
-      k_smooth<B, SS, true, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,  \
-                                                                       Mb, f, z, zout);    \
-    else                                                                                   \
-      k_smooth<B, SS, false, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, \
-                                                                        Mb, f, z, zout);   \
-    break;                                                                                 \
+  tile_switch<B>(tile, [&](auto SS, auto UU) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+    const int g = nwg_rows<B, S_>(nrows);
+    if (trans)
+      k_smooth<B, S_, U_, true, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, Mb,
+                                                                           f, z, zout);
+    else
+      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,
+                                                                            Mb, f, z, zout);
+  });
+}
+
+// ---------------------------------------------------------------- tile autotuner
+
+// Picks the fastest engine tile for one stored operator by timing its SpMV on
+// the device (a few launches per candidate); results are cached per matrix
+// shape for the process and, when MGK_TUNE_CACHE names a file, in that JSON
+// file across processes.
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::string, Tile> m;
+  bool loaded = false;
+  static TuneCache& get() {
+    static TuneCache c;
+    return c;
   }
-  switch (S) {
-    MGK_SM_CASE(1)
-    MGK_SM_CASE(2)
-    MGK_SM_CASE(4)
-    default:
-      if constexpr (B == 1) {
-        switch (S) { MGK_SM_CASE(8) }
+  void load() {
+    if (loaded) return;
+    loaded = true;
+    const char* path = getenv("MGK_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int s, u;
+    // one entry per line: "key": [s, u],
+    char line[512];
+    while (fgets(line, sizeof line, f))
+      if (sscanf(line, " \"%255[^\"]\": [%d, %d]", key, &s, &u) == 3) m[key] = Tile{s, u};
+    fclose(f);
+  }
+  void save() {
+    const char* path = getenv("MGK_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto& kv : m)
+      fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.s, kv.second.u,
+              ++i < m.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+  }
+};
+
+template <int BR, int BC, class TV, class TX>
+static Tile autotune(Device& D, const DMat& M, bool trans) {
+  const int nrows = trans ? M.nbc : M.nbr, ncols = trans ? M.nbr : M.nbc;
+  if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4} : Tile{1, 4};
+  char key[200];
+  snprintf(key, sizeof key, "b%dx%d_v%d_x%d_t%d_r%d_nnz%lld", BR, BC, (int)sizeof(TV),
+           (int)sizeof(TX), (int)trans, nrows, (long long)M.nnzb);
+  TuneCache& C = TuneCache::get();
+  {
+    std::lock_guard<std::mutex> g(C.mu);
+    C.load();
+    auto it = C.m.find(key);
+    if (it != C.m.end()) {
+      bool known = false;
+      auto probe = [&](int ss, int uu) { known |= it->second.s == ss && it->second.u == uu; };
+#define MGK_PROBE(SS, UU) probe(SS, UU);
+      if (BR == 1) {
+        MGK_TILES_1(MGK_PROBE)
+      } else {
+        MGK_TILES_B(MGK_PROBE)
       }
-      break;
+#undef MGK_PROBE
+      if (known) return it->second;
+    }
   }
-#undef MGK_SM_CASE
+  std::vector<Tile> cands;
+  if (BR == 1) cands = {{1, 8}, {2, 4}, {4, 4}, {8, 4}, {16, 2}, {32, 2}};
+  else cands = {{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 4}, {8, 4}, {16, 2}};
+  TX *x = nullptr, *y = nullptr;
+  HIPCK(hipMalloc(&x, sizeof(TX) * (size_t)ncols * (trans ? BR : BC) + 64));
+  HIPCK(hipMalloc(&y, sizeof(TX) * (size_t)nrows * (trans ? BC : BR) + 64));
+  HIPCK(hipMemsetAsync(x, 0, sizeof(TX) * (size_t)ncols * (trans ? BR : BC), D.stream));
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  Tile best = cands[0];
+  float best_ms = 1e30f;
+  for (const Tile& t : cands) {
+    spmv_s<BR, BC, TV, TX, TX>(D.stream, M, trans, t, x, y, 1.0, 0.0);
+    HIPCK(hipEventRecord(e0, D.stream));
+    for (int r = 0; r < 3; ++r) spmv_s<BR, BC, TV, TX, TX>(D.stream, M, trans, t, x, y, 1.0, 0.0);
+    HIPCK(hipEventRecord(e1, D.stream));
+    HIPCK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(x);
+  (void)hipFree(y);
+  std::lock_guard<std::mutex> g(C.mu);
+  C.m[key] = best;
+  C.save();
+  return best;
+}
+
+// Tune the tiles of one stored operator for its storage and vector precision.
+static void tune_mat(Device& D, DMat& M, int storage, bool with_trans) {
+  auto run = [&](auto BRc, auto BCc) {
+    constexpr int BR = decltype(BRc)::value, BC = decltype(BCc)::value;
+    if (storage == MGK_F64) {
+      M.tile = autotune<BR, BC, double, double>(D, M, false);
+      if (with_trans && BR == BC) M.ttile = autotune<BR, BC, double, double>(D, M, true);
+    } else if (storage == MGK_F32) {
+      M.tile = autotune<BR, BC, float, float>(D, M, false);
+      if (with_trans && BR == BC) M.ttile = autotune<BR, BC, float, float>(D, M, true);
+    } else {
+      M.tile = autotune<BR, BC, bf16, float>(D, M, false);
+      if (with_trans && BR == BC) M.ttile = autotune<BR, BC, bf16, float>(D, M, true);
+    }
+  };
+  using std::integral_constant;
+  if (M.br == 1 && M.bc == 1) run(integral_constant<int, 1>(), integral_constant<int, 1>());
+  else if (M.br == 3 && M.bc == 3) run(integral_constant<int, 3>(), integral_constant<int, 3>());
+  else if (M.br == 4 && M.bc == 4) run(integral_constant<int, 4>(), integral_constant<int, 4>());
+  else if (M.br == 1 && M.bc == 3) run(integral_constant<int, 1>(), integral_constant<int, 3>());
+  else if (M.br == 3 && M.bc == 1) run(integral_constant<int, 3>(), integral_constant<int, 1>());
+  else throw Error(MGK_E_INVALID, "unsupported block shape");
 }
 
 // ---------------------------------------------------------------- hierarchy
@@ -267,7 +388,6 @@ struct DLevel {
   int nbr = 0;
   size_t n = 0;            // scalar unknowns
   void *r = nullptr, *t = nullptr, *z = nullptr, *z2 = nullptr;
-  int sA = 1, sAt = 1, sP = 1, sR = 1;
 };
 
 struct DHier {
@@ -328,10 +448,10 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
         d.M = D.upload(m.data(), m.size());
         HIPCK(hipStreamSynchronize(D.stream));
       }
-      d.sA = pick_split(H.b, d.A.avg_row);
-      d.sAt = pick_split(H.b, d.A.avg_col);
-      d.sP = pick_split(H.b, d.P.avg_row);
-      d.sR = pick_split(H.b, d.R.avg_row);
+      if (!(l == 0 && share_level0 && storage == MGK_F64 && d.A.ptr == share_level0->ptr))
+        tune_mat(D, d.A, storage, with_transpose);
+      tune_mat(D, d.P, storage, false);
+      tune_mat(D, d.R, storage, false);
     }
     d.r = D.alloc(d.n * xs);
     d.t = D.alloc(d.n * xs);
@@ -371,12 +491,12 @@ struct Cycle {
     DLevel& C = H.lv[l + 1];
     k_block_diag<B, TM, TIN, TX, AccOf<TV>>
         <<<(unsigned)((L.n + WG - 1) / WG), WG, 0, st>>>(L.nbr, trans, (const TM*)L.M, r, z);
-    residual_s<B, B, TV, TX, TIN>(st, L.A, trans, trans ? L.sAt : L.sA, r, z, t);
-    spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.sR, t, (TX*)C.r, 1.0, 0.0);
+    residual_s<B, B, TV, TX, TIN>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, r, z, t);
+    spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.R.tile, t, (TX*)C.r, 1.0, 0.0);
     TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
     run<TX, TX>(st, H, l + 1, (const TX*)C.r, zc, trans);
-    spmv_s<B, B, TV, TX, TX>(st, L.P, false, L.sP, zc, z, 1.0, 1.0);
-    smooth_s<B, TV, TX, TIN, TOUT, TM>(st, L.A, trans, trans ? L.sAt : L.sA, (const TM*)L.M, r,
+    spmv_s<B, B, TV, TX, TX>(st, L.P, false, L.P.tile, zc, z, 1.0, 1.0);
+    smooth_s<B, TV, TX, TIN, TOUT, TM>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, (const TM*)L.M, r,
                                        z, zout);
   }
 };
@@ -418,7 +538,6 @@ struct mgk_solver {
   size_t n = 0;
   HBsr A_host;               // kept for the FP64 transpose pattern and export
   DMat A;                    // FP64 outer operator
-  int sA = 1, sAt = 1;
   DHier H;                   // monolithic or velocity hierarchy
   DHier Hp;                  // pressure hierarchy (Schur)
   DMat Blo, Bup;             // Schur couplings in storage precision
@@ -431,6 +550,8 @@ struct mgk_solver {
   size_t part_len = 0;
   double* hsc = nullptr;     // pinned host mirror of sc
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> tev;   // timing events around outer SpMV launches
+  size_t tev_used = 0;
   // FGMRES
   double *V = nullptr, *Z = nullptr, *h = nullptr, *hsum = nullptr, *yv = nullptr;
   double* hpin = nullptr;
@@ -439,6 +560,8 @@ struct mgk_solver {
   bool host_only = false;
   ~mgk_solver() {
     for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : tev)
       if (e) (void)hipEventDestroy(e);
     if (hsc) (void)hipHostFree(hsc);
     if (hpin) (void)hipHostFree(hpin);
@@ -451,7 +574,19 @@ static void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, in
                        const double* w1 = nullptr, const double* w2 = nullptr,
                        int* nwg = nullptr) {
   hipStream_t st = S->dev.stream;
-  const int sp = trans ? S->sAt : S->sA;
+  const bool timed = S->prm.time_spmv && S->tev_used + 2 <= S->tev.size();
+  if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
+  struct After {
+    mgk_solver* S;
+    bool on;
+    ~After() {
+      if (on) {
+        (void)hipEventRecord(S->tev[S->tev_used + 1], S->dev.stream);
+        S->tev_used += 2;
+      }
+    }
+  } after{S, timed};
+  const Tile sp = trans ? S->A.ttile : S->A.tile;
   switch (S->b) {
     case 1: spmv_s<1, 1, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
     case 3: spmv_s<3, 3, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
@@ -462,7 +597,7 @@ static void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, in
 static void outer_residual(mgk_solver* S, const double* b, const double* x, double* r,
                            bool trans) {
   hipStream_t st = S->dev.stream;
-  const int sp = trans ? S->sAt : S->sA;
+  const Tile sp = trans ? S->A.ttile : S->A.tile;
   switch (S->b) {
     case 1: residual_s<1, 1, double, double, double>(st, S->A, trans, sp, b, x, r); break;
     case 3: residual_s<3, 3, double, double, double>(st, S->A, trans, sp, b, x, r); break;
@@ -479,9 +614,9 @@ static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
      *zp = (TX*)S->zp;
   k_split<TX><<<grid_for(nn), WG, 0, st>>>(nn, r, ru, rp);
   vcycle<TX, TX>(st, S->H, ru, zu, false);
-  residual_s<1, 3, TV, TX, TX>(st, S->Blo, false, 2, rp, zu, tp);
+  residual_s<1, 3, TV, TX, TX>(st, S->Blo, false, S->Blo.tile, rp, zu, tp);
   vcycle<TX, TX>(st, S->Hp, tp, zp, false);
-  residual_s<3, 1, TV, TX, TX>(st, S->Bup, false, 1, ru, zp, tu);
+  residual_s<3, 1, TV, TX, TX>(st, S->Bup, false, S->Bup.tile, ru, zp, tu);
   vcycle<TX, TX>(st, S->H, tu, zu, false);
   k_merge<TX><<<grid_for(nn), WG, 0, st>>>(nn, zu, zp, z);
 }
@@ -745,6 +880,10 @@ static void alloc_krylov(mgk_solver* S) {
   S->part = (double*)D.alloc(sizeof(double) * S->part_len);
   HIPCK(hipHostMalloc((void**)&S->hsc, sizeof(double) * SC_COUNT, hipHostMallocDefault));
   for (auto& e : S->ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (S->prm.time_spmv) {
+    S->tev.resize(2 * (2 * (size_t)S->prm.maxiter + 64));
+    for (auto& e : S->tev) HIPCK(hipEventCreate(&e));
+  }
   if (S->prm.krylov == MGK_FGMRES) {
     S->m = std::max(1, std::min<int>(S->prm.fgmres_m, MAXM - 1));
     S->V = (double*)D.alloc(nb * (S->m + 1));
@@ -811,8 +950,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     return;
   }
   S->A = upload_mat(S->dev, H, MGK_F64, tr);
-  S->sA = pick_split(block_size, S->A.avg_row);
-  S->sAt = pick_split(block_size, S->A.avg_col);
+  tune_mat(S->dev, S->A, MGK_F64, tr);
   const SetupParams sp = setup_params(*prm, kind);
   int rc;
   if (kind == MGK_SCHUR) {
@@ -825,6 +963,8 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr);
     S->Blo = upload_mat(S->dev, parts.Blo, prm->hier, false);
     S->Bup = upload_mat(S->dev, parts.Bup, prm->hier, false);
+    tune_mat(S->dev, S->Blo, prm->hier, false);
+    tune_mat(S->dev, S->Bup, prm->hier, false);
     const size_t xs = prm->hier == MGK_F64 ? 8 : 4, nn = (size_t)S->nbr;
     S->ru = S->dev.alloc(3 * nn * xs);
     S->tu = S->dev.alloc(3 * nn * xs);
@@ -979,6 +1119,7 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
   return mgk::guard([&]() -> int {
     auto t0 = std::chrono::steady_clock::now();
     std::memset(info, 0, sizeof(*info));
+    s->tev_used = 0;
     int rc;
     if (!trans && s->prm.krylov == MGK_FGMRES) rc = mgk::fgmres(s, d_b, d_x, rtol, info);
     else rc = mgk::bicgstab(s, d_b, d_x, rtol, trans, info);
@@ -990,6 +1131,14 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     info->solve_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     info->device_bytes = s->dev.bytes;
+    double spmv_ms = 0.0;
+    for (size_t e = 0; e + 1 < s->tev_used; e += 2) {
+      float ms = 0.0f;
+      HIPCK(hipEventElapsedTime(&ms, s->tev[e], s->tev[e + 1]));
+      spmv_ms += ms;
+    }
+    info->spmv_ms = spmv_ms;
+    info->spmv_calls = (int32_t)(s->tev_used / 2);
     return rc;
   });
 }
@@ -1050,7 +1199,7 @@ int mgk_spmv(mgk_solver* s, int32_t hier, int32_t level, int32_t which, const vo
       const mgk::DMat& M = which == 1 ? L.P : (which == 2 ? L.R : L.A);
       const bool tr = which == 3;
       if (tr && !M.tptr) throw mgk::Error(MGK_E_STATE, "no transpose index");
-      const int sp = which == 1 ? L.sP : (which == 2 ? L.sR : (tr ? L.sAt : L.sA));
+      const Tile sp = which == 1 ? L.P.tile : (which == 2 ? L.R.tile : (tr ? L.A.ttile : L.A.tile));
 #define MGK_LV(BB)                                                                           \
   case BB:                                                                                   \
     if (H.storage == MGK_F64)                                                                \
