@@ -92,6 +92,24 @@ def spmv_timing(s, n_rows, torch, reps=50):
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Practical HBM ceiling: a plain device-to-device copy of nbytes (read + write)."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del x, y
+    return 2 * nbytes / t / 1e9
+
+
 def cpu_baseline(n, b_np, iters_scale, log_fn):
     """The oracle as it stands (scalar CSR FP64, OpenMP SpMV) on the host cores: setup once
     (not part of the metric), then a bounded run of 3 BiCGStab iterations, scaled to the
@@ -225,6 +243,9 @@ def main():
         for a in ("bsr_f32", "bsr_bf16", "csr_f64"):
             if a in results:
                 out[f"speedup_{a}_vs_bsr_f64"] = f64 / results[a]["solve_s"]
+    if roofline:
+        roofline["copy_ceiling_gbs"] = copy_ceiling(torch)
+        roofline["frac_of_copy_ceiling"] = roofline["achieved"] / roofline["copy_ceiling_gbs"]
     out["roofline"] = roofline
     if not args.no_cpu_baseline and os.environ.get("BENCH_NO_CPU") != "1":
         scale = results.get("bsr_f64", results[head])["iters"]

@@ -89,7 +89,10 @@ typedef struct {
   int32_t enable_transpose;/* 1: build the A^T indices for adjoint solves (default 0) */
   int32_t time_spmv;       /* 1: time every outer-operator SpMV of a solve with HIP
                               events on the solver's stream (mgk_info.spmv_ms) */
-  int32_t reserved;
+  int32_t force_tile;      /* 0: the autotuner picks each operator's kernel tile;
+                              otherwise 100*S + U (S lanes per block row, U blocks per
+                              step) for every operator.  Results are bitwise the same
+                              for every tile. */
 } mgk_params;
 
 typedef struct {

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("max_levels", C.c_int32), ("block_spai0", C.c_int32),
                 ("eps_strong", C.c_double), ("jacobi_omega", C.c_double),
                 ("keep_host", C.c_int32), ("enable_transpose", C.c_int32),
-                ("time_spmv", C.c_int32), ("reserved", C.c_int32)]
+                ("time_spmv", C.c_int32), ("force_tile", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -40,6 +40,12 @@ typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 constexpr int WG = 256;          // threads per workgroup (4 waves)
 constexpr int WAVE = 64;
 
+// Explicit fused multiply-add.  Device code is compiled without automatic
+// contraction, so every rounding step is the one written here in every kernel
+// instantiation (results do not depend on the kernel tile).
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t u) {
   return __uint_as_float(((uint32_t)u) << 16);
 }
@@ -135,20 +141,35 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
   return L;
 }
 
-// Partial sum of row r of block row i over blocks s, s+S, ...; combined over
-// the S lanes of the row (result valid in the s == 0 lane).  U blocks are
-// handled per step with every load issued before the first use, so each lane
-// keeps U independent gathers in flight (the fine-level rows are short and the
-// loop would otherwise be bound by one dependent col -> x chain per block).
-// The accumulation order is ascending k for every (U, S).
+// Row r of block row i times x, for the lane (s, r) of a group of BR*S lanes.
+//
+// Summation order, identical for every tile (S, U): block kr (kr-th stored
+// block of the row) is added, in ascending kr, to stripe kr mod NS (NS = 16,
+// or 32 for scalar rows); the NS stripes are then combined by the fixed tree
+// (q, q + NS/2), (q, q + NS/4), ..., (q, q + 1).  Lane s owns stripes
+// s + S*t, t < T = NS/S: the upper tree levels are formed inside the lane and
+// the last log2(S) levels across lanes with shuffles.  Results are therefore
+// bitwise the same whatever tile the autotuner picks.
+//
+// U blocks are handled per step with every load issued before the first use,
+// so each lane keeps U independent gathers in flight (the fine-level rows are
+// short and would otherwise be bound by one dependent col -> x chain per
+// block).  When T > U the stripe accumulators rotate by U after each step so
+// that block u of a step always lands in accumulator u.
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA>
 __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int* __restrict__ ptr,
                                           const int* __restrict__ col, const int* __restrict__ blk,
                                           const TV* __restrict__ val, const TX* __restrict__ x) {
-  TA acc = 0;
+  constexpr int NS = BR == 1 ? 32 : 16;
+  constexpr int T = NS / S;
+  static_assert(S <= NS && (U % T == 0 || T % U == 0), "tile");
+  TA acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = 0;
   if (L.active && L.i < nbr) {
     const int k0 = ptr[L.i], k1 = ptr[L.i + 1];
-    for (int kb = k0 + L.s; kb < k1; kb += S * U) {
+    int steps = 0;
+    for (int kb = k0 + L.s; kb < k1; kb += S * U, ++steps) {
       int j[U], kk[U];
       bool ok[U];
 #pragma unroll
@@ -180,14 +201,38 @@ __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int*
         }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < U; ++u) {
+        TA& a = acc[u % T];
 #pragma unroll
-        for (int c = 0; c < BC; ++c) acc += v[u][c] * xv[u][c];
+        for (int c = 0; c < BC; ++c) a = fma_(v[u][c], xv[u][c], a);
+      }
+      if constexpr (T > U) {
+        TA tmp[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) tmp[t] = acc[(t + U) % T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = tmp[t];
+      }
+    }
+    if constexpr (T > U) {
+      // undo the rotations: acc[t] now holds stripe (t + steps*U) mod T
+      for (int q = (T / U - steps % (T / U)) % (T / U); q > 0; --q) {
+        TA tmp[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) tmp[t] = acc[(t + U) % T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = tmp[t];
+      }
     }
   }
 #pragma unroll
-  for (int m = S / 2; m >= 1; m >>= 1) acc += __shfl_down(acc, BR * m, WAVE);
-  return acc;
+  for (int h = T / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int t = 0; t < h; ++t) acc[t] += acc[t + h];
+  TA a0 = acc[0];
+#pragma unroll
+  for (int m = S / 2; m >= 1; m >>= 1) a0 += __shfl_down(a0, BR * m, WAVE);
+  return a0;
 }
 
 // Deterministic workgroup sum of up to two values; thread 0 returns them.
@@ -219,47 +264,83 @@ __device__ __forceinline__ void wg_sum2(T& a, T& b) {
 // ---- sparse kernels ------------------------------------------------------------
 
 // y = alpha A x + beta y   (beta == 0: y is not read).
-// With dots != 0, also per-workgroup partials of <w1, y> and (dots == 2)
-// <y, y> for the fused Krylov products (FP64 outer operator).  Workgroup w
-// processes the contiguous row tiles [w*T/G, (w+1)*T/G) of the T tiles, so a
-// reduced grid (G < T) keeps the partial count, and the finalizing reduction,
-// small.
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TY, class TA>
 __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ ptr,
                                              const int* __restrict__ col,
                                              const int* __restrict__ blk,
                                              const TV* __restrict__ val,
                                              const TX* __restrict__ x, TY* __restrict__ y,
-                                             TA alpha, TA beta, int dots,
-                                             const double* __restrict__ w1,
-                                             const double* __restrict__ w2,
-                                             double* __restrict__ part, int ntiles) {
+                                             TA alpha, TA beta) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const int t0 = (int)(((long long)lw * ntiles) / gridDim.x);
-  const int t1 = (int)(((long long)(lw + 1) * ntiles) / gridDim.x);
-  double d1 = 0.0, d2 = 0.0;
-  for (int tile = t0; tile < t1; ++tile) {
-    const LaneInfo L = lane_info<BR, S>(tile);
-    TA acc = row_product<BR, BC, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, x);
-    if (L.active && L.s == 0 && L.i < nbr) {
+  const LaneInfo L = lane_info<BR, S>(lw);
+  TA acc = row_product<BR, BC, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, x);
+  if (L.active && L.s == 0 && L.i < nbr) {
+    const size_t row = (size_t)L.i * BR + L.r;
+    TA out = alpha * acc;
+    if (beta != TA(0)) out += beta * (TA)y[row];
+    y[row] = (TY)out;
+  }
+}
+
+// y = A x fused with the partial dot products <w1, y> and (two) <y, y> of the
+// Krylov iteration (FP64 outer operator).  Every workgroup owns the same 64
+// block rows whatever the tile: the per-row products are staged in LDS by
+// scalar row and summed by one fixed tree, so the partials (and the whole
+// solve) do not depend on the tile.
+constexpr int DOT_ROWS = 64;
+
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX>
+__global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict__ ptr,
+                                                 const int* __restrict__ col,
+                                                 const int* __restrict__ blk,
+                                                 const TV* __restrict__ val,
+                                                 const TX* __restrict__ x,
+                                                 double* __restrict__ y, int two,
+                                                 const double* __restrict__ w1,
+                                                 double* __restrict__ part) {
+  using M = RowMap<BR, S>;
+  constexpr int NR = DOT_ROWS * BR < 128 ? 64 : (DOT_ROWS * BR <= 128 ? 128 : 256);
+  static_assert(DOT_ROWS * BR <= NR, "dot staging");
+  __shared__ double sd1[NR], sd2[NR];
+  for (int t = threadIdx.x; t < NR; t += WG) {
+    sd1[t] = 0.0;
+    sd2[t] = 0.0;
+  }
+  __syncthreads();
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const int rb0 = lw * DOT_ROWS, rb1 = min(nbr, rb0 + DOT_ROWS);
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x >> 6;
+  for (int base = rb0; base < rb1; base += M::ROWS) {
+    LaneInfo L;
+    const int g = lane / M::G, w = lane - g * M::G;
+    L.active = g < M::GPW;
+    L.s = w / BR;
+    L.r = w - L.s * BR;
+    L.gbase = g * M::G;
+    L.i = base + wave * M::GPW + g;
+    const int lim = L.i < rb1 ? nbr : 0;   // rows past this workgroup's range idle
+    const double acc = row_product<BR, BC, S, U, TRANS, TV, TX, double>(L, lim, ptr, col, blk,
+                                                                        val, x);
+    if (L.active && L.s == 0 && L.i < rb1) {
       const size_t row = (size_t)L.i * BR + L.r;
-      TA out = alpha * acc;
-      if (beta != TA(0)) out += beta * (TA)y[row];
-      y[row] = (TY)out;
-      if (dots) {
-        d1 += w1[row] * (double)out;
-        if (dots == 2) d2 += (double)out * (double)out;
-      }
+      y[row] = acc;
+      const int q = (L.i - rb0) * BR + L.r;
+      sd1[q] = w1[row] * acc;
+      sd2[q] = acc * acc;
     }
   }
-  if (dots) {
-    wg_sum2(d1, d2);
-    if (threadIdx.x == 0) {
-      part[lw] = d1;
-      if (dots == 2) part[gridDim.x + lw] = d2;
+  __syncthreads();
+  for (int h = NR / 2; h >= 1; h >>= 1) {   // NR is a power of two
+    for (int t = threadIdx.x; t < h; t += WG) {
+      sd1[t] += sd1[t + h];
+      sd2[t] += sd2[t + h];
     }
+    __syncthreads();
   }
-  (void)w2;
+  if (threadIdx.x == 0) {
+    part[lw] = sd1[0];
+    if (two) part[gridDim.x + lw] = sd2[0];
+  }
 }
 
 // t = f - A z  (A may be rectangular: BR x BC blocks).
@@ -308,7 +389,7 @@ __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ 
     TA out = (TA)z[row];
 #pragma unroll
     for (int c = 0; c < BR; ++c)
-      out += (TA)(TRANS ? m[c * BR + L.r] : m[L.r * BR + c]) * rv[c];
+      out = fma_((TA)(TRANS ? m[c * BR + L.r] : m[L.r * BR + c]), rv[c], out);
     zout[row] = (TO)out;
   }
 }
@@ -326,7 +407,7 @@ __global__ __launch_bounds__(WG) void k_block_diag(int nbr, int trans, const TM*
   const TF* fi = f + i * B;
   TA acc = 0;
 #pragma unroll
-  for (int c = 0; c < B; ++c) acc += (TA)(trans ? m[c * B + r] : m[r * B + c]) * (TA)fi[c];
+  for (int c = 0; c < B; ++c) acc = fma_((TA)(trans ? m[c * B + r] : m[r * B + c]), (TA)fi[c], acc);
   z[row] = (TX)acc;
 }
 
@@ -340,7 +421,7 @@ __global__ __launch_bounds__(WG) void k_coarse_gemv(int n, const double* __restr
   const int i = blockIdx.x;
   const double* a = Cinv + (size_t)i * n;
   double s = 0.0, dummy = 0.0;
-  for (int j = threadIdx.x; j < n; j += WG) s += a[j] * (double)r[j];
+  for (int j = threadIdx.x; j < n; j += WG) s = fma_(a[j], (double)r[j], s);
   wg_sum2(s, dummy);
   if (threadIdx.x == 0) z[i] = (TO)s;
 }
@@ -393,6 +474,32 @@ enum FinOp {
   FIN_OMEGA = 3,    // ts, tt -> omega = ts / tt (0 if tt == 0)
   FIN_RHO = 4       // rr, rho1' -> rho = rho1, rho1 = rho1'
 };
+
+// First stage of a fixed-order reduction over many partials: workgroup b sums
+// partials [b*RED_CHUNK, (b+1)*RED_CHUNK) of one or two arrays of length count.
+constexpr int RED_CHUNK = 4096;
+
+__global__ __launch_bounds__(WG) void k_reduce_stage(const double* __restrict__ part, int count,
+                                                     int two, double* __restrict__ out) {
+  const int b0 = blockIdx.x * RED_CHUNK, b1 = min(count, b0 + RED_CHUNK);
+  double a[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = b0 + threadIdx.x; k < b1; k += 4 * WG) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kq = k + q * WG;
+      if (kq < b1) {
+        a[q] += part[kq];
+        if (two) c[q] += part[count + kq];
+      }
+    }
+  }
+  double sa = (a[0] + a[1]) + (a[2] + a[3]), sc = (c[0] + c[1]) + (c[2] + c[3]);
+  wg_sum2(sa, sc);
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = sa;
+    if (two) out[gridDim.x + blockIdx.x] = sc;
+  }
+}
 
 __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int count,
                                                  int two, int op, int i0, int i1,

@@ -183,11 +183,10 @@ static void tile_switch(const Tile& t, F&& launch) {
                                  std::to_string(t.u));
 }
 
-// y = alpha A x + beta y with optional fused dots (FP64 operator only).
+// y = alpha A x + beta y.
 template <int BR, int BC, class TV, class TX, class TY>
 static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TX* x,
-                   TY* y, double alpha, double beta, int dots = 0, const double* w1 = nullptr,
-                   const double* w2 = nullptr, double* part = nullptr, int* nwg_out = nullptr) {
+                   TY* y, double alpha, double beta) {
   using TA = AccOf<TV>;
   const int nrows = trans ? M.nbc : M.nbr;
   const int* p = trans ? M.tptr : M.ptr;
@@ -196,18 +195,37 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, 
   const TV* v = (const TV*)M.val;
   tile_switch<BR>(tile, [&](auto SS, auto UU) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int nt = nwg_rows<BR, S_>(nrows);
-    // fused dots: at most 2048 workgroups (one full occupancy wave of 4-wave
-    // groups on 256 CUs), each over a contiguous range of row tiles
-    const int g = dots ? std::min(nt, 2048) : nt;
-    if (nwg_out) *nwg_out = g;
+    const int g = nwg_rows<BR, S_>(nrows);
     if (trans)
-      k_spmv<BR, BC, S_, U_, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(
-          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part, nt);
+      k_spmv<BR, BC, S_, U_, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
+                                                                     (TA)alpha, (TA)beta);
     else
-      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(
-          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, dots, w1, w2, part, nt);
+      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
+                                                                      (TA)alpha, (TA)beta);
   });
+}
+
+// y = A x (FP64) with the fused partials of <w1, y> and, when two, <y, y>;
+// returns the number of partials written per dot.
+template <int BR, int BC>
+static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile,
+                      const double* x, double* y, int two, const double* w1, double* part) {
+  const int nrows = trans ? M.nbc : M.nbr;
+  const int* p = trans ? M.tptr : M.ptr;
+  const int* c = trans ? M.trow : M.col;
+  const int* b = trans ? M.tblk : nullptr;
+  const double* v = (const double*)M.val;
+  const int g = std::max(1, (nrows + DOT_ROWS - 1) / DOT_ROWS);
+  tile_switch<BR>(tile, [&](auto SS, auto UU) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+    if (trans)
+      k_spmv_dot<BR, BC, S_, U_, true, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
+                                                                         y, two, w1, part);
+    else
+      k_spmv_dot<BR, BC, S_, U_, false, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
+                                                                          y, two, w1, part);
+  });
+  return g;
 }
 
 template <int BR, int BC, class TV, class TX, class TF>
@@ -296,8 +314,32 @@ struct TuneCache {
   }
 };
 
+static thread_local int g_force_tile = 0;  // mgk_params.force_tile of the setup in progress
+
+template <int BR>
+static bool tile_known(const Tile& t) {
+  bool known = false;
+  auto probe = [&](int ss, int uu) { known |= t.s == ss && t.u == uu; };
+#define MGK_PROBE(SS, UU) probe(SS, UU);
+  if (BR == 1) {
+    MGK_TILES_1(MGK_PROBE)
+  } else {
+    MGK_TILES_B(MGK_PROBE)
+  }
+#undef MGK_PROBE
+  return known;
+}
+
 template <int BR, int BC, class TV, class TX>
 static Tile autotune(Device& D, const DMat& M, bool trans) {
+  if (g_force_tile) {
+    const Tile t{g_force_tile / 100, g_force_tile % 100};
+    if (!tile_known<BR>(t))
+      throw Error(MGK_E_INVALID, "force_tile " + std::to_string(g_force_tile) +
+                                     " is not a kernel tile for block rows of " +
+                                     std::to_string(BR));
+    return t;
+  }
   const int nrows = trans ? M.nbc : M.nbr, ncols = trans ? M.nbr : M.nbc;
   if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4} : Tile{1, 4};
   char key[200];
@@ -308,18 +350,7 @@ static Tile autotune(Device& D, const DMat& M, bool trans) {
     std::lock_guard<std::mutex> g(C.mu);
     C.load();
     auto it = C.m.find(key);
-    if (it != C.m.end()) {
-      bool known = false;
-      auto probe = [&](int ss, int uu) { known |= it->second.s == ss && it->second.u == uu; };
-#define MGK_PROBE(SS, UU) probe(SS, UU);
-      if (BR == 1) {
-        MGK_TILES_1(MGK_PROBE)
-      } else {
-        MGK_TILES_B(MGK_PROBE)
-      }
-#undef MGK_PROBE
-      if (known) return it->second;
-    }
+    if (it != C.m.end() && tile_known<BR>(it->second)) return it->second;
   }
   std::vector<Tile> cands;
   if (BR == 1) cands = {{1, 8}, {2, 4}, {4, 4}, {8, 4}, {16, 2}, {32, 2}};
@@ -547,6 +578,7 @@ struct mgk_solver {
          *sh = nullptr, *t = nullptr;
   double* sc = nullptr;      // device scalars
   double* part = nullptr;    // reduction partials
+  double* part2 = nullptr;   // second-stage partials
   size_t part_len = 0;
   double* hsc = nullptr;     // pinned host mirror of sc
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -571,26 +603,30 @@ struct mgk_solver {
 namespace mgk {
 
 static void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots = 0,
-                       const double* w1 = nullptr, const double* w2 = nullptr,
-                       int* nwg = nullptr) {
+                       const double* w1 = nullptr, int* nwg = nullptr) {
   hipStream_t st = S->dev.stream;
   const bool timed = S->prm.time_spmv && S->tev_used + 2 <= S->tev.size();
   if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
-  struct After {
-    mgk_solver* S;
-    bool on;
-    ~After() {
-      if (on) {
-        (void)hipEventRecord(S->tev[S->tev_used + 1], S->dev.stream);
-        S->tev_used += 2;
-      }
-    }
-  } after{S, timed};
   const Tile sp = trans ? S->A.ttile : S->A.tile;
+  int g = 0;
   switch (S->b) {
-    case 1: spmv_s<1, 1, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
-    case 3: spmv_s<3, 3, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
-    case 4: spmv_s<4, 4, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0, dots, w1, w2, S->part, nwg); break;
+    case 1:
+      if (dots) g = spmv_dot_s<1, 1>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part);
+      else spmv_s<1, 1, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0);
+      break;
+    case 3:
+      if (dots) g = spmv_dot_s<3, 3>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part);
+      else spmv_s<3, 3, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0);
+      break;
+    case 4:
+      if (dots) g = spmv_dot_s<4, 4>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part);
+      else spmv_s<4, 4, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0);
+      break;
+  }
+  if (nwg) *nwg = g;
+  if (timed) {
+    HIPCK(hipEventRecord(S->tev[S->tev_used + 1], st));
+    S->tev_used += 2;
   }
 }
 
@@ -638,7 +674,14 @@ static int red_grid(size_t n) { return grid_for(n); }
 static int maxiter_of(const mgk_solver* S) { return S->prm.maxiter; }
 
 static void finalize(mgk_solver* S, int count, int two, int op, int i0 = 0, int i1 = 0) {
-  k_finalize<<<1, WG, 0, S->dev.stream>>>(S->part, count, two, op, i0, i1, S->sc);
+  const double* src = S->part;
+  if (count > RED_CHUNK) {
+    const int nb = (count + RED_CHUNK - 1) / RED_CHUNK;
+    k_reduce_stage<<<nb, WG, 0, S->dev.stream>>>(S->part, count, two, S->part2);
+    src = S->part2;
+    count = nb;
+  }
+  k_finalize<<<1, WG, 0, S->dev.stream>>>(src, count, two, op, i0, i1, S->sc);
 }
 
 // Copy the device scalars to pinned memory and mark the point with event e.
@@ -704,7 +747,7 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
         k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p);
         precond(S, S->p, S->ph, trans);
         int nw = 0;
-        outer_spmv(S, S->ph, S->v, trans, 1, S->rh, nullptr, &nw);
+        outer_spmv(S, S->ph, S->v, trans, 1, S->rh, &nw);
         finalize(S, nw, 0, FIN_ALPHA);
       }
       pending_v = false;
@@ -714,7 +757,7 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
       // speculative: shat = M s; t = A shat (harmless if we stop after s)
       precond(S, S->s, S->sh, trans);
       int nw = 0;
-      outer_spmv(S, S->sh, S->t, trans, 2, S->s, nullptr, &nw);  // partials (s,t), (t,t)
+      outer_spmv(S, S->sh, S->t, trans, 2, S->s, &nw);  // partials (s,t), (t,t)
       finalize(S, nw, 1, FIN_OMEGA);
       wait(S, 0);
       if (S->hsc[SC_SS] <= tol2) break;  // x already holds x + alpha phat
@@ -726,7 +769,7 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
         k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p);
         precond(S, S->p, S->ph, trans);
         int nw2 = 0;
-        outer_spmv(S, S->ph, S->v, trans, 1, S->rh, nullptr, &nw2);
+        outer_spmv(S, S->ph, S->v, trans, 1, S->rh, &nw2);
         finalize(S, nw2, 0, FIN_ALPHA);
         pending_v = true;
       }
@@ -875,9 +918,10 @@ static void alloc_krylov(mgk_solver* S) {
   S->sc = (double*)D.alloc(sizeof(double) * SC_COUNT);
   // partials: two dots per workgroup of the finest SpMV, or MAXM dots per
   // reduction workgroup
-  const size_t rows16 = (size_t)S->nbr / 16 + 64;
-  S->part_len = std::max<size_t>(2 * rows16 * 4, (size_t)MAXM * 1024) + 1024;
+  // (at least 4 block rows per workgroup, two dots)
+  S->part_len = std::max<size_t>((size_t)S->nbr / 2 + 4096, (size_t)MAXM * 1024 + 1024);
   S->part = (double*)D.alloc(sizeof(double) * S->part_len);
+  S->part2 = (double*)D.alloc(sizeof(double) * (2 * (S->part_len / RED_CHUNK + 2)));
   HIPCK(hipHostMalloc((void**)&S->hsc, sizeof(double) * SC_COUNT, hipHostMallocDefault));
   for (auto& e : S->ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   if (S->prm.time_spmv) {
@@ -913,6 +957,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   if (A->n_brows < 1 || !A->rowptr || (!A->col && A->rowptr[A->n_brows] > 0))
     throw Error(MGK_E_INVALID, "empty or null matrix arrays");
   S->prm = *prm;
+  g_force_tile = prm->force_tile;
   S->kind = kind;
   S->b = block_size;
   S->nbr = A->n_brows;

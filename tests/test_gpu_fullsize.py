@@ -1,0 +1,133 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+96^3 monolithic (mixed FP32 hierarchy, BiCGStab), 64^3 Schur pressure correction (BF16
+hierarchy, FGMRES(30)), 48^3 adjoint gradient.  The residual of every GPU solution is
+evaluated with the oracle's own FP64 SpMV; solutions are compared with the oracle's FP64
+solve; the gradient with the oracle's gradient over all cells and with central finite
+differences on 20 seeded cells.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import stokes_synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(300)]
+
+import paper_2006_06052_amd as mgk  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def solver(ptr, col, val, **kw):
+    return mgk.Solver(ptr, col, val, 4, kw.pop("kind", mgk.AMG_SPAI0),
+                      stream=torch.cuda.current_stream(), **kw)
+
+
+def test_cube96_mixed_precision_vs_oracle():
+    n = 96
+    say("cube96: assembling")
+    ptr, col, val = mgk.stokes_bsr(n)
+    b = S.c2_rhs(n)
+    s = solver(ptr, col, val, hier=mgk.F32)
+    dx = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    say("cube96 gpu", info)
+    x = dx.cpu().numpy()
+    A = oracle.stokes_matrix(n)
+    res = np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b)
+    assert info["status"] == 0 and res <= 1e-8, res
+    say("cube96: oracle solve")
+    xo, oi = oracle.Solver(A, 4).solve(b, 1e-11)
+    say("cube96 oracle", oi)
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_cube64_schur_bf16_vs_oracle():
+    n = 64
+    th = S.theta_field(n, 1.0, 3)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    A = oracle.stokes_matrix(n, th)
+    b = oracle.spmv(A, S.mms_solution(n))
+    s = solver(ptr, col, val, kind=mgk.SCHUR, hier=mgk.BF16, krylov=mgk.FGMRES)
+    dx = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    say("cube64 schur gpu", info)
+    x = dx.cpu().numpy()
+    res = np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b)
+    assert info["status"] == 0 and res <= 1e-8, res
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES)
+    xo, oi = so.solve(b, 1e-11)
+    say("cube64 schur oracle", oi)
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_cube48_adjoint_gradient():
+    n = 48
+    th = S.theta_field(n, 0.5, 5)
+    thr = S.theta_field(n, 0.5, 50)
+    b = S.mms_rhs(n)
+    # target from the reference viscosity
+    pr, cr, vr = mgk.stokes_bsr(n, thr)
+    s_ref = solver(pr, cr, vr, hier=mgk.F64)
+    dxt = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    s_ref.solve(dev(b), dxt, 1e-12)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    s = solver(ptr, col, val, hier=mgk.F32, enable_transpose=1)
+    dx = torch.zeros_like(dxt)
+    s.solve(dev(b), dx, 1e-10)
+    dlam = torch.zeros_like(dx)
+    info = s.solve_transposed(dx - dxt, dlam, 1e-10)
+    say("adjoint", info)
+    g = torch.empty((n - 1) ** 3, dtype=torch.float64, device=DEV)
+    mgk.theta_grad(n, dlam, dx, g)
+    g = g.cpu().numpy()
+    # oracle gradient over all cells (FP64 forward and adjoint at rtol 1e-12)
+    A = oracle.stokes_matrix(n, th)
+    so = oracle.Solver(A, 4)
+    xo, _ = so.solve(b, 1e-12)
+    xto, _ = oracle.Solver(oracle.stokes_matrix(n, thr), 4).solve(b, 1e-12)
+    lo, _ = so.solve(xo - xto, 1e-12, transposed=True)
+    go = oracle.theta_gradient(n, lo, xo)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    say("gradient vs oracle", rel)
+    assert rel <= 1e-6
+    # central differences (step 1e-6) on 20 seeded cells.  x(theta +- d) is obtained from the
+    # base solution by one defect-correction solve, A(theta +- d) c = b - A(theta +- d) x,
+    # x(theta +- d) = x + c, with an FP64 hierarchy: the correction is small, so a relative
+    # tolerance of 1e-10 on it gives x(theta +- d) to about 1e-16 of ||x||.
+    cells = S.fd_cells(n, 20, 51)
+    xb = dx.clone()
+
+    def correction(t):
+        p_, c_, v_ = mgk.stokes_bsr(n, t)
+        sf = solver(p_, c_, v_, hier=mgk.F64)
+        ax = torch.empty_like(xb)
+        sf.spmv(xb, ax)
+        r = dev(b) - ax
+        c = torch.zeros_like(xb)
+        inf = sf.solve(r, c, 1e-10)
+        assert inf["status"] == 0, inf
+        return c
+
+    # (L(t+) - L(t-)) / 2d with L = ||x - x_t||^2 / 2, written as
+    # (x+ - x-) . (x+ + x- - 2 x_t) / (4 d) so that the difference is not lost to cancellation
+    fd = []
+    for e in cells:
+        d = np.zeros_like(th)
+        d[e] = 1e-6
+        cp, cm = correction(th + d), correction(th - d)
+        fd.append(float(torch.dot(cp - cm, cp + cm + 2.0 * (xb - dxt))) / 4e-6)
+    fd = np.array(fd)
+    relfd = np.linalg.norm(g[cells] - fd) / np.linalg.norm(fd)
+    say("gradient vs central FD", relfd)
+    assert relfd <= 1e-6

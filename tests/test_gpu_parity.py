@@ -263,3 +263,27 @@ def test_edge_cases():
         s2.solve_transposed(bx, x, 1e-8)   # set up without transpose indices
     with pytest.raises(TypeError):
         s2.solve(bx.float(), x, 1e-8)
+
+
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_results_independent_of_kernel_tile(storage):
+    """Every engine tile sums in the same fixed order, so SpMV and whole solves are bitwise
+    identical whatever tile the autotuner (or force_tile) selects."""
+    n = 14
+    th, bsr, A = problem(n, 0.5, 8)
+    b = dev(S.mms_rhs(n))
+    x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
+    outs = []
+    for tile in (0, 108, 204, 404, 804, 1602):
+        say("tile", storage, tile)
+        s = gpu_solver(bsr, hier=storage, coarse_enough=200, force_tile=tile)
+        y = torch.empty_like(b)
+        s.spmv(x0, y)
+        x = torch.zeros_like(b)
+        info = s.solve(b, x, 1e-8)
+        outs.append((y.cpu().numpy(), x.cpu().numpy(), info["iters"]))
+    for y, x, it in outs[1:]:
+        assert np.array_equal(y, outs[0][0])
+        assert np.array_equal(x, outs[0][1]) and it == outs[0][2]
+    with pytest.raises(mgk.MgkError):
+        gpu_solver(bsr, hier=storage, force_tile=303)
