@@ -141,7 +141,10 @@ def main():
     ap.add_argument("--arms", default="bsr_f32,bsr_f64,bsr_bf16,csr_f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--spmv-only", action="store_true",
-                    help="only the FP64 BSR SpMV loop (for counter collection)")
+                    help="only the FP64 BSR SpMV loop")
+    ap.add_argument("--counters", action="store_true",
+                    help="one FP32-hierarchy solve, then three 1 GiB device copies (a short "
+                         "program for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
@@ -182,6 +185,20 @@ def main():
         log(f"spmv: {t * 1e6:.1f} us, {spmv_bytes / t / 1e9:.0f} GB/s")
         return
 
+    if args.counters:
+        s, _ = make("bsr_f32")
+        dx = torch.zeros_like(db)
+        info = s.solve(db, dx, 1e-8)
+        torch.cuda.synchronize()
+        log(f"counters: solve {info['iters']} iterations")
+        x = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("counters: 3 copies of 1 GiB done")
+        return
+
     arms = [a for a in args.arms.split(",") if a]
     head = arms[0]
     results = {}
@@ -210,8 +227,8 @@ def main():
             ach = spmv_bytes / (sp_ms * 1e-3 / sp_calls) / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "mgk::k_spmv<4, 4, S, U, false, double, double, double, "
-                                  "double> (FP64 4x4 BSR outer operator)",
+                        "kernel": "mgk::k_spmv_dot<4, 4, S, U, false, double, double> "
+                                  "(FP64 4x4 BSR outer operator, fused Krylov dots)",
                         "bytes_per_launch": spmv_bytes,
                         "avg_launch_us": sp_ms * 1e3 / sp_calls, "launches": sp_calls,
                         "isolated_loop_us": t_iso * 1e6,
@@ -220,7 +237,7 @@ def main():
         del s
         torch.cuda.empty_cache()
 
-    tpath = os.path.join(ROOT, "profiles", "spmv_bsr4_f64_cube96_traffic.json")
+    tpath = os.path.join(ROOT, "profiles", "spmv_bsr4_f64_cube96_traffic.json")  # rocprofv3 counters
     if roofline and os.path.exists(tpath):
         with open(tpath) as f:
             tr = json.load(f)
