@@ -240,6 +240,20 @@ class Solver:
         """x (in: initial guess, out: solution); returns the info record."""
         return self._solve(lib().mgk_solve, b, x, rtol)
 
+    def solve_multi(self, B, X, rtol: float = 1e-8) -> list:
+        """K <= 32 right-hand sides together: B, X are [n, K] (right-hand sides fastest);
+        X holds the initial guesses.  Returns one info record per column."""
+        import torch
+        if B.dim() != 2 or B.shape[0] != self.n or X.shape != B.shape:
+            raise ValueError("B and X must both be [n, K]")
+        K = B.shape[1]
+        infos = (Info * K)()
+        rc = lib().mgk_solve_multi(self._h, K, _dev_ptr(B, torch.float64),
+                                   _dev_ptr(X, torch.float64), rtol, infos)
+        if rc < 0:
+            _err(rc)
+        return [i.as_dict() for i in infos]
+
     def solve_transposed(self, g, lam, rtol: float = 1e-8) -> dict:
         return self._solve(lib().mgk_solve_transposed, g, lam, rtol)
 

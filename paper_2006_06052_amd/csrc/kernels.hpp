@@ -363,7 +363,7 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
 // Post-smoothing: zout = z + M (f - A z), M block diagonal (M^T when TRANS).
 template <int BR, int S, int U, bool TRANS, class TV, class TX, class TF, class TO, class TM,
           class TA>
-__global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
+static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
                                                const int* __restrict__ col,
                                                const int* __restrict__ blk,
                                                const TV* __restrict__ val,
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(WG) void k_coarse_gemv(int n, const double* __restr
   for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < (size_t)(n); i += (size_t)gridDim.x * WG)
 
 // part[blk] = <a,b>, part[grid + blk] = <c,d> (second dot optional).
-__global__ __launch_bounds__(WG) void k_dot2(size_t n, const double* __restrict__ a,
+static __global__ __launch_bounds__(WG) void k_dot2(size_t n, const double* __restrict__ a,
                                              const double* __restrict__ b,
                                              const double* __restrict__ c,
                                              const double* __restrict__ d,
@@ -479,7 +479,7 @@ enum FinOp {
 // partials [b*RED_CHUNK, (b+1)*RED_CHUNK) of one or two arrays of length count.
 constexpr int RED_CHUNK = 4096;
 
-__global__ __launch_bounds__(WG) void k_reduce_stage(const double* __restrict__ part, int count,
+static __global__ __launch_bounds__(WG) void k_reduce_stage(const double* __restrict__ part, int count,
                                                      int two, double* __restrict__ out) {
   const int b0 = blockIdx.x * RED_CHUNK, b1 = min(count, b0 + RED_CHUNK);
   double a[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(WG) void k_reduce_stage(const double* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int count,
+static __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int count,
                                                  int two, int op, int i0, int i1,
                                                  double* __restrict__ sc) {
   double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part
 }
 
 // p = r + beta (p - omega v), beta = (rho1 / rho) (alpha / omega).
-__global__ __launch_bounds__(WG) void k_bicg_p(size_t n, const double* __restrict__ sc,
+static __global__ __launch_bounds__(WG) void k_bicg_p(size_t n, const double* __restrict__ sc,
                                                const double* __restrict__ r,
                                                const double* __restrict__ v,
                                                double* __restrict__ p) {
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(WG) void k_bicg_p(size_t n, const double* __restric
 }
 
 // s = r - alpha v; x += alpha phat; partials of ||s||^2.
-__global__ __launch_bounds__(WG) void k_bicg_s(size_t n, const double* __restrict__ sc,
+static __global__ __launch_bounds__(WG) void k_bicg_s(size_t n, const double* __restrict__ sc,
                                                const double* __restrict__ r,
                                                const double* __restrict__ v,
                                                const double* __restrict__ ph,
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(WG) void k_bicg_s(size_t n, const double* __restric
 }
 
 // x += omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
-__global__ __launch_bounds__(WG) void k_bicg_xr(size_t n, const double* __restrict__ sc,
+static __global__ __launch_bounds__(WG) void k_bicg_xr(size_t n, const double* __restrict__ sc,
                                                 const double* __restrict__ s,
                                                 const double* __restrict__ t,
                                                 const double* __restrict__ sh,
@@ -590,24 +590,24 @@ __global__ __launch_bounds__(WG) void k_bicg_xr(size_t n, const double* __restri
 }
 
 // y = a * x (a read from sc[ia] inverted when inv) or y = x.
-__global__ __launch_bounds__(WG) void k_scale(size_t n, const double* __restrict__ sc, int ia,
+static __global__ __launch_bounds__(WG) void k_scale(size_t n, const double* __restrict__ sc, int ia,
                                               int sqrt_inv, const double* __restrict__ x,
                                               double* __restrict__ y) {
   const double a = sqrt_inv ? 1.0 / sqrt(sc[ia]) : sc[ia];
   GRID_STRIDE(i, n) y[i] = a * x[i];
 }
 
-__global__ __launch_bounds__(WG) void k_scal(size_t n, double a, const double* __restrict__ x,
+static __global__ __launch_bounds__(WG) void k_scal(size_t n, double a, const double* __restrict__ x,
                                               double* __restrict__ y) {
   GRID_STRIDE(i, n) y[i] = a * x[i];
 }
 
-__global__ __launch_bounds__(WG) void k_copy(size_t n, const double* __restrict__ x,
+static __global__ __launch_bounds__(WG) void k_copy(size_t n, const double* __restrict__ x,
                                              double* __restrict__ y) {
   GRID_STRIDE(i, n) y[i] = x[i];
 }
 
-__global__ __launch_bounds__(WG) void k_fill(size_t n, double v, double* __restrict__ y) {
+static __global__ __launch_bounds__(WG) void k_fill(size_t n, double v, double* __restrict__ y) {
   GRID_STRIDE(i, n) y[i] = v;
 }
 
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(WG) void k_fill(size_t n, double v, double* __restr
 constexpr int MAXM = 32;
 
 // part[q * grid + blk] = <V_q, w> for q < m (V_q = V + q * ld).
-__global__ __launch_bounds__(WG) void k_multidot(size_t n, int m, const double* __restrict__ V,
+static __global__ __launch_bounds__(WG) void k_multidot(size_t n, int m, const double* __restrict__ V,
                                                  size_t ld, const double* __restrict__ w,
                                                  double* __restrict__ part) {
   double acc[MAXM];
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(WG) void k_multidot(size_t n, int m, const double* 
 }
 
 // h[q] = sum of the partials of dot q (count each); h2 accumulates into hsum.
-__global__ __launch_bounds__(WG) void k_multifin(const double* __restrict__ part, int count,
+static __global__ __launch_bounds__(WG) void k_multifin(const double* __restrict__ part, int count,
                                                  int m, double* __restrict__ h,
                                                  double* __restrict__ hsum, int add) {
   for (int q = 0; q < m; ++q) {
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(WG) void k_multifin(const double* __restrict__ part
 }
 
 // w -= V h (m vectors), optionally partials of ||w||^2.
-__global__ __launch_bounds__(WG) void k_multiaxpy(size_t n, int m, const double* __restrict__ V,
+static __global__ __launch_bounds__(WG) void k_multiaxpy(size_t n, int m, const double* __restrict__ V,
                                                   size_t ld, const double* __restrict__ h,
                                                   double* __restrict__ w,
                                                   double* __restrict__ part) {
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(WG) void k_multiaxpy(size_t n, int m, const double*
 }
 
 // x += sum_q y_q Z_q (y on the device).
-__global__ __launch_bounds__(WG) void k_update_x(size_t n, int m, const double* __restrict__ Z,
+static __global__ __launch_bounds__(WG) void k_update_x(size_t n, int m, const double* __restrict__ Z,
                                                  size_t ld, const double* __restrict__ y,
                                                  double* __restrict__ x) {
   GRID_STRIDE(i, n) {
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(WG) void k_bsr_grad(int nbr, const int* __restrict_
 }
 
 // Per-cell viscosity gradient of the finite-difference Stokes operator.
-__global__ __launch_bounds__(WG) void k_theta_grad(int n, const double* __restrict__ lam,
+static __global__ __launch_bounds__(WG) void k_theta_grad(int n, const double* __restrict__ lam,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ g) {
   const int nc = n - 1;

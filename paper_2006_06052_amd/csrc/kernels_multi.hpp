@@ -1,0 +1,411 @@
+// gfx950 kernels for K <= 32 right-hand sides solved together.
+//
+// Vectors are [n][K] row-major (the K right-hand sides of one scalar row are
+// contiguous).  A group of 32 lanes owns one block row; lane k < K computes
+// every scalar row of that block row for right-hand side k, so each stored
+// block is fetched once per group (the 32 lanes read the same addresses, which
+// the address unit broadcasts) and the x block is read as b coalesced
+// K-element rows.  A workgroup of 256 lanes covers 8 block rows.
+//
+// The products are HBM-bound (about 2 flop per byte of matrix per right-hand
+// side), so vector FMA is used, not MFMA.  Each output sums its blocks in
+// ascending order with explicit FMAs.
+#pragma once
+#include "kernels.hpp"
+
+namespace mgk {
+
+constexpr int KL = 32;                 // lanes per block-row group (max right-hand sides)
+constexpr int MROWS = WG / KL;         // block rows per workgroup
+
+template <int B, class TV, class TA>
+__device__ __forceinline__ void load_block(const TV* __restrict__ p, TA* out) {
+  if constexpr (sizeof(TV) == 2) {
+    const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
+#pragma unroll
+    for (int e = 0; e < B * B; ++e) out[e] = (TA)bf16_to_f32(q[e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < B * B; ++e) out[e] = (TA)p[e];
+  }
+}
+
+// acc[r] = sum over blocks (i, j) of sum_c A_ij[r][c] X[j*BC + c][k]  (r < BR).
+template <int BR, int BC, class TV, class TX, class TA>
+__device__ __forceinline__ void block_row_multi(int i, int k, int K, const int* __restrict__ ptr,
+                                                const int* __restrict__ col,
+                                                const TV* __restrict__ val,
+                                                const TX* __restrict__ X, TA* acc) {
+#pragma unroll
+  for (int r = 0; r < BR; ++r) acc[r] = 0;
+  const int k0 = ptr[i], k1 = ptr[i + 1];
+  for (int kb = k0; kb < k1; ++kb) {
+    const int j = col[kb];
+    TA a[BR * BC];
+    if constexpr (BR == BC) {
+      load_block<BR, TV, TA>(val + (size_t)kb * BR * BC, a);
+    } else {
+#pragma unroll
+      for (int e = 0; e < BR * BC; ++e) {
+        if constexpr (sizeof(TV) == 2)
+          a[e] = (TA)bf16_to_f32(reinterpret_cast<const uint16_t*>(val)[(size_t)kb * BR * BC + e]);
+        else
+          a[e] = (TA)val[(size_t)kb * BR * BC + e];
+      }
+    }
+    TA xv[BC];
+#pragma unroll
+    for (int c = 0; c < BC; ++c) xv[c] = (TA)X[((size_t)j * BC + c) * K + k];
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int c = 0; c < BC; ++c) acc[r] = fma_(a[r * BC + c], xv[c], acc[r]);
+  }
+}
+
+// Y = alpha A X + beta Y.
+template <int BR, int BC, class TV, class TX, class TY, class TA>
+__global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restrict__ ptr,
+                                             const int* __restrict__ col,
+                                             const TV* __restrict__ val,
+                                             const TX* __restrict__ X, TY* __restrict__ Y,
+                                             TA alpha, TA beta) {
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
+  if (i >= nbr || k >= K) return;
+  TA acc[BR];
+  block_row_multi<BR, BC, TV, TX, TA>(i, k, K, ptr, col, val, X, acc);
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    const size_t e = ((size_t)i * BR + r) * K + k;
+    TA out = alpha * acc[r];
+    if (beta != TA(0)) out = fma_(beta, (TA)Y[e], out);
+    Y[e] = (TY)out;
+  }
+}
+
+// Y = A X (FP64) with per-column partials of <W1_k, Y_k> and (two) <Y_k, Y_k>:
+// part[w * KL + k] and part[(G + w) * KL + k] for workgroup w of G.
+template <int B>
+__global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __restrict__ ptr,
+                                                 const int* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ X,
+                                                 double* __restrict__ Y, int two,
+                                                 const double* __restrict__ W1,
+                                                 double* __restrict__ part) {
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = lw * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
+  double d1 = 0.0, d2 = 0.0;
+  if (i < nbr && k < K) {
+    double acc[B];
+    block_row_multi<B, B, double, double, double>(i, k, K, ptr, col, val, X, acc);
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const size_t e = ((size_t)i * B + r) * K + k;
+      Y[e] = acc[r];
+      d1 = fma_(W1[e], acc[r], d1);
+      d2 = fma_(acc[r], acc[r], d2);
+    }
+  }
+  __shared__ double sa[WG], sb[WG];
+  sa[threadIdx.x] = d1;
+  sb[threadIdx.x] = d2;
+  __syncthreads();
+  if (threadIdx.x < KL) {
+    double x = 0.0, y = 0.0;
+    for (int q = 0; q < MROWS; ++q) {
+      x += sa[q * KL + threadIdx.x];
+      y += sb[q * KL + threadIdx.x];
+    }
+    part[(size_t)lw * KL + threadIdx.x] = x;
+    if (two) part[(size_t)(gridDim.x + lw) * KL + threadIdx.x] = y;
+  }
+}
+
+// First reduction stage for per-column partials: workgroup b sums partial rows
+// [b*1024, (b+1)*1024) of one or two arrays of `count` rows (32 lanes per column,
+// 8 row slots, fixed order).
+constexpr int MRED_CHUNK = 1024;
+
+static __global__ __launch_bounds__(WG) void k_reduce_stage_m(const double* __restrict__ part, int count,
+                                                       int two, double* __restrict__ out) {
+  const int k = threadIdx.x % KL, q0 = threadIdx.x / KL;
+  const int b0 = blockIdx.x * MRED_CHUNK, b1 = min(count, b0 + MRED_CHUNK);
+  double a = 0.0, c = 0.0;
+  for (int q = b0 + q0; q < b1; q += MROWS) {
+    a += part[(size_t)q * KL + k];
+    if (two) c += part[(size_t)(count + q) * KL + k];
+  }
+  __shared__ double sa[WG], sb[WG];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x < KL) {
+    double x = 0.0, y = 0.0;
+    for (int q = 0; q < MROWS; ++q) {
+      x += sa[q * KL + threadIdx.x];
+      y += sb[q * KL + threadIdx.x];
+    }
+    out[(size_t)blockIdx.x * KL + threadIdx.x] = x;
+    if (two) out[(size_t)(gridDim.x + blockIdx.x) * KL + threadIdx.x] = y;
+  }
+}
+
+// T = F - A Z.
+template <int BR, int BC, class TV, class TX, class TF, class TA>
+__global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __restrict__ ptr,
+                                                   const int* __restrict__ col,
+                                                   const TV* __restrict__ val,
+                                                   const TF* __restrict__ F,
+                                                   const TX* __restrict__ Z,
+                                                   TX* __restrict__ T) {
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
+  if (i >= nbr || k >= K) return;
+  TA acc[BR];
+  block_row_multi<BR, BC, TV, TX, TA>(i, k, K, ptr, col, val, Z, acc);
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    const size_t e = ((size_t)i * BR + r) * K + k;
+    T[e] = (TX)((TA)F[e] - acc[r]);
+  }
+}
+
+// Zout = Z + M (F - A Z), M block diagonal.
+template <int B, class TV, class TX, class TF, class TO, class TM, class TA>
+__global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __restrict__ ptr,
+                                                 const int* __restrict__ col,
+                                                 const TV* __restrict__ val,
+                                                 const TM* __restrict__ M,
+                                                 const TF* __restrict__ F,
+                                                 const TX* __restrict__ Z,
+                                                 TO* __restrict__ Zout) {
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
+  if (i >= nbr || k >= K) return;
+  TA acc[B];
+  block_row_multi<B, B, TV, TX, TA>(i, k, K, ptr, col, val, Z, acc);
+  TA res[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) res[r] = (TA)F[((size_t)i * B + r) * K + k] - acc[r];
+  const TM* m = M + (size_t)i * B * B;
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    const size_t e = ((size_t)i * B + r) * K + k;
+    TA out = (TA)Z[e];
+#pragma unroll
+    for (int c = 0; c < B; ++c) out = fma_((TA)m[r * B + c], res[c], out);
+    Zout[e] = (TO)out;
+  }
+}
+
+// Z = M F.
+template <int B, class TM, class TF, class TX, class TA>
+__global__ __launch_bounds__(WG) void k_block_diag_m(int nbr, int K, const TM* __restrict__ M,
+                                                     const TF* __restrict__ F,
+                                                     TX* __restrict__ Z) {
+  const int i = blockIdx.x * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
+  if (i >= nbr || k >= K) return;
+  const TM* m = M + (size_t)i * B * B;
+  TA f[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) f[c] = (TA)F[((size_t)i * B + c) * K + k];
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    TA acc = 0;
+#pragma unroll
+    for (int c = 0; c < B; ++c) acc = fma_((TA)m[r * B + c], f[c], acc);
+    Z[((size_t)i * B + r) * K + k] = (TX)acc;
+  }
+}
+
+// Z = Cinv R for the dense FP64 coarsest inverse (n x n), R and Z [n][K]:
+// 8 rows of Z per workgroup, lane k per right-hand side, j ascending.
+template <class TI, class TO>
+__global__ __launch_bounds__(WG) void k_coarse_gemm(int n, int K, const double* __restrict__ Cinv,
+                                                    const TI* __restrict__ R,
+                                                    TO* __restrict__ Z) {
+  const int i = blockIdx.x * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
+  if (i >= n || k >= K) return;
+  const double* a = Cinv + (size_t)i * n;
+  double acc = 0.0;
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    const double a0 = a[j], a1 = a[j + 1], a2 = a[j + 2], a3 = a[j + 3];
+    const double r0 = (double)R[(size_t)j * K + k], r1 = (double)R[(size_t)(j + 1) * K + k];
+    const double r2 = (double)R[(size_t)(j + 2) * K + k], r3 = (double)R[(size_t)(j + 3) * K + k];
+    acc = fma_(a0, r0, acc);
+    acc = fma_(a1, r1, acc);
+    acc = fma_(a2, r2, acc);
+    acc = fma_(a3, r3, acc);
+  }
+  for (; j < n; ++j) acc = fma_(a[j], (double)R[(size_t)j * K + k], acc);
+  Z[(size_t)i * K + k] = (TO)acc;
+}
+
+// ---- per-column Krylov kernels (FP64) ----------------------------------------
+//
+// Per-column scalars live in scm[idx * KL + k].  A thread handles column
+// k = tid % 32 of rows tid / 32, tid / 32 + 8, ... of its grid-stride range; the
+// per-column partials of a workgroup are combined over its 8 row slots in LDS
+// in a fixed order.
+
+enum ScM { SM_RHO = 0, SM_RHO1, SM_ALPHA, SM_OMEGA, SM_RV, SM_SS, SM_TS, SM_TT, SM_RR, SM_NB,
+           SM_COUNT };
+
+#define MROW_STRIDE(row, n) \
+  for (size_t row = (size_t)blockIdx.x * MROWS + threadIdx.x / KL; row < (size_t)(n); \
+       row += (size_t)gridDim.x * MROWS)
+
+__device__ __forceinline__ void col_sum2(double a, double b, int two, double* __restrict__ part,
+                                         int slot, int nslots) {
+  __shared__ double sa[WG], sb[WG];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x < KL) {
+    double x = 0.0, y = 0.0;
+    for (int q = 0; q < MROWS; ++q) {
+      x += sa[q * KL + threadIdx.x];
+      y += sb[q * KL + threadIdx.x];
+    }
+    part[(size_t)slot * KL + threadIdx.x] = x;
+    if (two) part[(size_t)(nslots + slot) * KL + threadIdx.x] = y;
+  }
+}
+
+// Per-column <A_k, B_k> and (optionally) <C_k, D_k> partials.
+static __global__ __launch_bounds__(WG) void k_dot_m(size_t n, int K, const double* __restrict__ A,
+                                              const double* __restrict__ Bv,
+                                              const double* __restrict__ C,
+                                              const double* __restrict__ D,
+                                              double* __restrict__ part) {
+  const int k = threadIdx.x % KL;
+  double s1 = 0.0, s2 = 0.0;
+  if (k < K) {
+    MROW_STRIDE(row, n) {
+      const size_t e = row * K + k;
+      s1 = fma_(A[e], Bv[e], s1);
+      if (C) s2 = fma_(C[e], D[e], s2);
+    }
+  }
+  col_sum2(s1, s2, C != nullptr, part, blockIdx.x, gridDim.x);
+}
+
+enum FinM { FINM_STORE1 = 0, FINM_STORE2, FINM_ALPHA, FINM_OMEGA, FINM_RHO };
+
+static __global__ __launch_bounds__(WG) void k_finalize_m(const double* __restrict__ part, int count,
+                                                   int two, int op, int i0, int i1, int K,
+                                                   const int* __restrict__ active,
+                                                   double* __restrict__ scm) {
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < count; ++q) {
+    a += part[(size_t)q * KL + k];
+    if (two) b += part[(size_t)(count + q) * KL + k];
+  }
+  if (!active[k] && op != FINM_STORE1 && op != FINM_STORE2) return;
+  double* s = scm;
+  switch (op) {
+    case FINM_STORE1: s[i0 * KL + k] = a; break;
+    case FINM_STORE2: s[i0 * KL + k] = a; s[i1 * KL + k] = b; break;
+    case FINM_ALPHA: s[SM_RV * KL + k] = a; s[SM_ALPHA * KL + k] = s[SM_RHO1 * KL + k] / a; break;
+    case FINM_OMEGA:
+      s[SM_TS * KL + k] = a;
+      s[SM_TT * KL + k] = b;
+      s[SM_OMEGA * KL + k] = b != 0.0 ? a / b : 0.0;
+      break;
+    case FINM_RHO:
+      s[SM_RR * KL + k] = a;
+      s[SM_RHO * KL + k] = s[SM_RHO1 * KL + k];
+      s[SM_RHO1 * KL + k] = b;
+      break;
+  }
+}
+
+// p = r + beta (p - omega v) for active columns.
+static __global__ __launch_bounds__(WG) void k_bicg_p_m(size_t n, int K, const int* __restrict__ active,
+                                                 const double* __restrict__ scm,
+                                                 const double* __restrict__ r,
+                                                 const double* __restrict__ v,
+                                                 double* __restrict__ p) {
+  const int k = threadIdx.x % KL;
+  if (k >= K || !active[k]) return;
+  const double beta = (scm[SM_RHO1 * KL + k] / scm[SM_RHO * KL + k]) *
+                      (scm[SM_ALPHA * KL + k] / scm[SM_OMEGA * KL + k]);
+  const double om = scm[SM_OMEGA * KL + k];
+  MROW_STRIDE(row, n) {
+    const size_t e = row * K + k;
+    p[e] = r[e] + beta * (p[e] - om * v[e]);
+  }
+}
+
+// s = r - alpha v; x += alpha phat (active columns); partials of ||s||^2.
+static __global__ __launch_bounds__(WG) void k_bicg_s_m(size_t n, int K, const int* __restrict__ active,
+                                                 const double* __restrict__ scm,
+                                                 const double* __restrict__ r,
+                                                 const double* __restrict__ v,
+                                                 const double* __restrict__ ph,
+                                                 double* __restrict__ s, double* __restrict__ x,
+                                                 double* __restrict__ part) {
+  const int k = threadIdx.x % KL;
+  double ss = 0.0;
+  if (k < K && active[k]) {
+    const double al = scm[SM_ALPHA * KL + k];
+    MROW_STRIDE(row, n) {
+      const size_t e = row * K + k;
+      const double si = r[e] - al * v[e];
+      s[e] = si;
+      x[e] += al * ph[e];
+      ss = fma_(si, si, ss);
+    }
+  }
+  col_sum2(ss, 0.0, 0, part, blockIdx.x, gridDim.x);
+}
+
+// x += omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
+static __global__ __launch_bounds__(WG) void k_bicg_xr_m(size_t n, int K, const int* __restrict__ active,
+                                                  const double* __restrict__ scm,
+                                                  const double* __restrict__ s,
+                                                  const double* __restrict__ t,
+                                                  const double* __restrict__ sh,
+                                                  const double* __restrict__ rh,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ part) {
+  const int k = threadIdx.x % KL;
+  double rr = 0.0, rho = 0.0;
+  if (k < K && active[k]) {
+    const double om = scm[SM_OMEGA * KL + k];
+    MROW_STRIDE(row, n) {
+      const size_t e = row * K + k;
+      x[e] += om * sh[e];
+      const double ri = s[e] - om * t[e];
+      r[e] = ri;
+      rr = fma_(ri, ri, rr);
+      rho = fma_(rh[e], ri, rho);
+    }
+  }
+  col_sum2(rr, rho, 1, part, blockIdx.x, gridDim.x);
+}
+
+// Restart the columns flagged in mask: rhat = r, p = v = 0 (scalars set by the host).
+static __global__ __launch_bounds__(WG) void k_restart_m(size_t n, int K, const int* __restrict__ mask,
+                                                  const double* __restrict__ r,
+                                                  double* __restrict__ rh, double* __restrict__ p,
+                                                  double* __restrict__ v) {
+  const int k = threadIdx.x % KL;
+  if (k >= K || !mask[k]) return;
+  MROW_STRIDE(row, n) {
+    const size_t e = row * K + k;
+    rh[e] = r[e];
+    p[e] = 0.0;
+    v[e] = 0.0;
+  }
+}
+
+}  // namespace mgk

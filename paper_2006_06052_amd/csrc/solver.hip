@@ -1,274 +1,9 @@
-// Solve-phase orchestration and the C ABI of libmgk.
-//
-// Setup runs on the host in FP64 (host.hpp) and is then moved to the device
-// once (Section 2.3: setup with built-in structures, then transfer to the
-// backend).  The solve phase composes the kernels of kernels.hpp:
-//   V(1,1) cycle per level: z = M r; t = r - A z; r_c = R t; recurse;
-//     z += P z_c; z_out = z + M (r - A z); coarsest level: dense FP64 inverse;
-//   BiCGStab (right preconditioned) with every scalar kept on the device and
-//     convergence read back through pinned memory while the next stage is
-//     already queued, so the host never drains the stream inside an
-//     iteration;
-//   flexible GMRES(m) with classical Gram-Schmidt plus one reorthogonalization
-//     (multi-dot kernels) and host Givens rotations;
-//   the Schur pressure correction: one velocity cycle, the pressure cycle on
-//     r_p - B_lo z_u, and a second velocity cycle on r_u - B_up z_p (Section 4,
-//     eqs. SchurP and SchurU).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <chrono>
-#include <cmath>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <stdexcept>
-#include <string>
-#include <vector>
-
-#include "../../include/mgk.h"
-#include "host.hpp"
-#include "kernels.hpp"
+// Solve-phase orchestration and the C ABI of libmgk: tile autotuner, upload of
+// the hierarchy, BiCGStab, FGMRES, the Schur apply, setup and entry points.
+// Shared declarations are in internal.hpp; multi-RHS solves are in multi.hip.
+#include "internal.hpp"
 
 namespace mgk {
-
-thread_local std::string g_err;
-
-struct Error : std::runtime_error {
-  int code;
-  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
-
-#define HIPCK(x)                                                                      \
-  do {                                                                                \
-    hipError_t e_ = (x);                                                              \
-    if (e_ != hipSuccess)                                                             \
-      throw Error(MGK_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));         \
-  } while (0)
-
-static inline int grid_for(size_t n) {
-  size_t g = (n + WG - 1) / WG;
-  return (int)std::max<size_t>(1, std::min<size_t>(g, 1024));
-}
-
-// ---------------------------------------------------------------- memory
-
-struct Device {
-  std::vector<void*> owned;
-  int64_t bytes = 0;
-  hipStream_t stream = nullptr;
-  void* alloc(size_t n) {
-    void* p = nullptr;
-    if (n == 0) n = 16;
-    n = (n + 255) & ~(size_t)255;
-    if (hipMalloc(&p, n) != hipSuccess) throw Error(MGK_E_NOMEM, "hipMalloc failed");
-    owned.push_back(p);
-    bytes += (int64_t)n;
-    return p;
-  }
-  template <class T>
-  T* upload(const T* h, size_t count) {
-    T* d = (T*)alloc(sizeof(T) * count);
-    if (count) HIPCK(hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, stream));
-    return d;
-  }
-  ~Device() {
-    for (void* p : owned) (void)hipFree(p);
-  }
-};
-
-static uint16_t f32_to_bf16(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
-}
-
-struct Tile {
-  int s = 1, u = 4;
-};
-
-// Device block matrix in a storage precision, with optional column index
-// (CSC over blocks) for products with the transpose.
-struct DMat {
-  int br = 1, bc = 1, nbr = 0, nbc = 0;
-  int64_t nnzb = 0;
-  int storage = MGK_F64;
-  int *ptr = nullptr, *col = nullptr;
-  void* val = nullptr;
-  int *tptr = nullptr, *trow = nullptr, *tblk = nullptr;
-  double avg_row = 0.0, avg_col = 0.0;
-  Tile tile, ttile;          // engine tiles for products with A and with A^T
-};
-
-static DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index) {
-  DMat M;
-  M.br = A.br;
-  M.bc = A.bc;
-  M.nbr = A.nbr;
-  M.nbc = A.nbc;
-  M.nnzb = A.nnzb();
-  M.storage = storage;
-  M.ptr = D.upload(A.ptr.data(), A.ptr.size());
-  M.col = D.upload(A.col.data(), A.col.size());
-  const size_t nv = A.val.size();
-  if (storage == MGK_F64) {
-    M.val = D.upload(A.val.data(), nv);
-  } else if (storage == MGK_F32) {
-    std::vector<float> v(nv);
-    for (size_t i = 0; i < nv; ++i) v[i] = (float)A.val[i];
-    M.val = D.upload(v.data(), nv);
-  } else {
-    std::vector<uint16_t> v(nv);
-    for (size_t i = 0; i < nv; ++i) v[i] = f32_to_bf16((float)A.val[i]);
-    M.val = D.upload(v.data(), nv);
-  }
-  M.avg_row = A.nbr ? (double)M.nnzb / A.nbr : 0.0;
-  if (transpose_index) {
-    std::vector<int> tp(A.nbc + 1, 0), tr(M.nnzb), tb(M.nnzb);
-    for (int64_t k = 0; k < M.nnzb; ++k) tp[A.col[k] + 1]++;
-    for (int j = 0; j < A.nbc; ++j) tp[j + 1] += tp[j];
-    std::vector<int> fill(tp.begin(), tp.end() - 1);
-    for (int i = 0; i < A.nbr; ++i)
-      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-        const int d = fill[A.col[k]]++;
-        tr[d] = i;
-        tb[d] = (int)k;
-      }
-    M.tptr = D.upload(tp.data(), tp.size());
-    M.trow = D.upload(tr.data(), tr.size());
-    M.tblk = D.upload(tb.data(), tb.size());
-    M.avg_col = A.nbc ? (double)M.nnzb / A.nbc : 0.0;
-  }
-  // the host vectors must outlive the async copies
-  HIPCK(hipStreamSynchronize(D.stream));
-  return M;
-}
-
-// ---------------------------------------------------------------- sparse launch
-
-template <int BR, int S>
-static int nwg_rows(int nbr) {
-  return std::max(1, (nbr + RowMap<BR, S>::ROWS - 1) / RowMap<BR, S>::ROWS);
-}
-
-template <class TV>
-using AccOf = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
-
-// Tile of the block-row engine: S lanes split a block row, U blocks per step.
-// Candidates below: few lanes and deep unrolling for the short fine-level rows,
-// many lanes for the long rows of coarse Galerkin levels and restrictions.
-#define MGK_TILES_B(CASE) \
-  CASE(1, 4) CASE(1, 8) CASE(2, 4) CASE(2, 8) CASE(4, 4) CASE(8, 4) CASE(16, 2)
-#define MGK_TILES_1(CASE) CASE(1, 8) CASE(2, 4) CASE(4, 4) CASE(8, 4) CASE(16, 2) CASE(32, 2)
-
-template <int BR, class F>
-static void tile_switch(const Tile& t, F&& launch) {
-#define MGK_TCASE(SS, UU)                                   \
-  if (t.s == SS && t.u == UU) {                             \
-    launch(std::integral_constant<int, SS>(), std::integral_constant<int, UU>()); \
-    return;                                                 \
-  }
-  if constexpr (BR == 1) {
-    MGK_TILES_1(MGK_TCASE)
-  } else {
-    MGK_TILES_B(MGK_TCASE)
-  }
-#undef MGK_TCASE
-  throw Error(MGK_E_INVALID, "no kernel for tile s=" + std::to_string(t.s) + " u=" +
-                                 std::to_string(t.u));
-}
-
-// y = alpha A x + beta y.
-template <int BR, int BC, class TV, class TX, class TY>
-static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TX* x,
-                   TY* y, double alpha, double beta) {
-  using TA = AccOf<TV>;
-  const int nrows = trans ? M.nbc : M.nbr;
-  const int* p = trans ? M.tptr : M.ptr;
-  const int* c = trans ? M.trow : M.col;
-  const int* b = trans ? M.tblk : nullptr;
-  const TV* v = (const TV*)M.val;
-  tile_switch<BR>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int g = nwg_rows<BR, S_>(nrows);
-    if (trans)
-      k_spmv<BR, BC, S_, U_, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
-                                                                     (TA)alpha, (TA)beta);
-    else
-      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
-                                                                      (TA)alpha, (TA)beta);
-  });
-}
-
-// y = A x (FP64) with the fused partials of <w1, y> and, when two, <y, y>;
-// returns the number of partials written per dot.
-template <int BR, int BC>
-static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile,
-                      const double* x, double* y, int two, const double* w1, double* part) {
-  const int nrows = trans ? M.nbc : M.nbr;
-  const int* p = trans ? M.tptr : M.ptr;
-  const int* c = trans ? M.trow : M.col;
-  const int* b = trans ? M.tblk : nullptr;
-  const double* v = (const double*)M.val;
-  const int g = std::max(1, (nrows + DOT_ROWS - 1) / DOT_ROWS);
-  tile_switch<BR>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    if (trans)
-      k_spmv_dot<BR, BC, S_, U_, true, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
-                                                                         y, two, w1, part);
-    else
-      k_spmv_dot<BR, BC, S_, U_, false, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
-                                                                          y, two, w1, part);
-  });
-  return g;
-}
-
-template <int BR, int BC, class TV, class TX, class TF>
-static void residual_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TF* f,
-                       const TX* z, TX* t) {
-  using TA = AccOf<TV>;
-  const int nrows = trans ? M.nbc : M.nbr;
-  const int* p = trans ? M.tptr : M.ptr;
-  const int* c = trans ? M.trow : M.col;
-  const int* b = trans ? M.tblk : nullptr;
-  const TV* v = (const TV*)M.val;
-  tile_switch<BR>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int g = nwg_rows<BR, S_>(nrows);
-    if (trans)
-      k_residual<BR, BC, S_, U_, true, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
-                                                                          z, t);
-    else
-      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
-                                                                           z, t);
-  });
-}
-
-template <int B, class TV, class TX, class TF, class TO, class TM>
-static void smooth_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TM* Mb,
-                     const TF* f, const TX* z, TO* zout) {
-  using TA = AccOf<TV>;
-  const int nrows = M.nbr;
-  const int* p = trans ? M.tptr : M.ptr;
-  const int* c = trans ? M.trow : M.col;
-  const int* b = trans ? M.tblk : nullptr;
-  const TV* v = (const TV*)M.val;
-  tile_switch<B>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int g = nwg_rows<B, S_>(nrows);
-    if (trans)
-      k_smooth<B, S_, U_, true, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, Mb,
-                                                                           f, z, zout);
-    else
-      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,
-                                                                            Mb, f, z, zout);
-  });
-}
 
 // ---------------------------------------------------------------- tile autotuner
 
@@ -411,27 +146,6 @@ static void tune_mat(Device& D, DMat& M, int storage, bool with_trans) {
   else throw Error(MGK_E_INVALID, "unsupported block shape");
 }
 
-// ---------------------------------------------------------------- hierarchy
-
-struct DLevel {
-  DMat A, P, R;
-  void* M = nullptr;       // smoother blocks: FP64 (F64 hierarchy) or FP32
-  int nbr = 0;
-  size_t n = 0;            // scalar unknowns
-  void *r = nullptr, *t = nullptr, *z = nullptr, *z2 = nullptr;
-};
-
-struct DHier {
-  int b = 1, storage = MGK_F64;
-  bool trans_ready = false;
-  std::vector<DLevel> lv;
-  int nc = 0;
-  double *cinv = nullptr, *cinvT = nullptr;
-  HHierarchy host;         // kept only when requested
-  bool keep_host = false;
-  std::vector<mgk_level_desc> desc;
-};
-
 static void fill_desc(const HHierarchy& H, std::vector<mgk_level_desc>& desc) {
   desc.resize(H.levels.size());
   for (size_t l = 0; l < H.levels.size(); ++l) {
@@ -502,103 +216,7 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
   HIPCK(hipStreamSynchronize(D.stream));
 }
 
-// One V(1,1) cycle on level l.  r: TIN at level 0 (else TX in lv[l].r);
-// output: TOUT at level 0 (else TX).  Returns nothing; the output of a level
-// l > 0 lands in lv[l].z2 (or lv[l].z on the coarsest level).
-template <int B, class TV, class TX>
-struct Cycle {
-  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
-
-  template <class TIN, class TOUT>
-  static void run(hipStream_t st, DHier& H, int l, const TIN* r, TOUT* zout, bool trans) {
-    DLevel& L = H.lv[l];
-    const int nl = (int)H.lv.size();
-    if (l == nl - 1) {
-      k_coarse_gemv<TIN, TOUT><<<H.nc, WG, 0, st>>>(H.nc, trans ? H.cinvT : H.cinv, r, zout);
-      return;
-    }
-    TX* z = (TX*)L.z;
-    TX* t = (TX*)L.t;
-    DLevel& C = H.lv[l + 1];
-    k_block_diag<B, TM, TIN, TX, AccOf<TV>>
-        <<<(unsigned)((L.n + WG - 1) / WG), WG, 0, st>>>(L.nbr, trans, (const TM*)L.M, r, z);
-    residual_s<B, B, TV, TX, TIN>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, r, z, t);
-    spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.R.tile, t, (TX*)C.r, 1.0, 0.0);
-    TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
-    run<TX, TX>(st, H, l + 1, (const TX*)C.r, zc, trans);
-    spmv_s<B, B, TV, TX, TX>(st, L.P, false, L.P.tile, zc, z, 1.0, 1.0);
-    smooth_s<B, TV, TX, TIN, TOUT, TM>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, (const TM*)L.M, r,
-                                       z, zout);
-  }
-};
-
-// Dispatch on (block size, storage) for vectors of type TIN/TOUT at the
-// hierarchy boundary.
-template <class TIN, class TOUT>
-static void vcycle(hipStream_t st, DHier& H, const TIN* r, TOUT* z, bool trans) {
-#define MGK_VC(BB)                                                                   \
-  case BB:                                                                           \
-    if (H.storage == MGK_F64)                                                        \
-      Cycle<BB, double, double>::run<TIN, TOUT>(st, H, 0, r, z, trans);              \
-    else if (H.storage == MGK_F32)                                                   \
-      Cycle<BB, float, float>::run<TIN, TOUT>(st, H, 0, r, z, trans);                \
-    else                                                                             \
-      Cycle<BB, bf16, float>::run<TIN, TOUT>(st, H, 0, r, z, trans);                 \
-    break;
-  switch (H.b) {
-    MGK_VC(1)
-    MGK_VC(3)
-    MGK_VC(4)
-    default: throw Error(MGK_E_INVALID, "unsupported block size");
-  }
-#undef MGK_VC
-}
-
 }  // namespace mgk
-
-// ---------------------------------------------------------------- solver object
-
-using namespace mgk;
-
-struct mgk_solver {
-  Device dev;
-  mgk_params prm;
-  int kind = MGK_AMG_SPAI0;
-  int b = 4;
-  int nbr = 0;
-  size_t n = 0;
-  HBsr A_host;               // kept for the FP64 transpose pattern and export
-  DMat A;                    // FP64 outer operator
-  DHier H;                   // monolithic or velocity hierarchy
-  DHier Hp;                  // pressure hierarchy (Schur)
-  DMat Blo, Bup;             // Schur couplings in storage precision
-  void *ru = nullptr, *rp = nullptr, *tu = nullptr, *tp = nullptr, *zu = nullptr, *zp = nullptr;
-  // Krylov workspace (FP64)
-  double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *ph = nullptr, *s = nullptr,
-         *sh = nullptr, *t = nullptr;
-  double* sc = nullptr;      // device scalars
-  double* part = nullptr;    // reduction partials
-  double* part2 = nullptr;   // second-stage partials
-  size_t part_len = 0;
-  double* hsc = nullptr;     // pinned host mirror of sc
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<hipEvent_t> tev;   // timing events around outer SpMV launches
-  size_t tev_used = 0;
-  // FGMRES
-  double *V = nullptr, *Z = nullptr, *h = nullptr, *hsum = nullptr, *yv = nullptr;
-  double* hpin = nullptr;
-  int m = 0;
-  double setup_ms = 0.0;
-  bool host_only = false;
-  ~mgk_solver() {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-    for (auto& e : tev)
-      if (e) (void)hipEventDestroy(e);
-    if (hsc) (void)hipHostFree(hsc);
-    if (hpin) (void)hipHostFree(hpin);
-  }
-};
 
 namespace mgk {
 
@@ -657,7 +275,7 @@ static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
   k_merge<TX><<<grid_for(nn), WG, 0, st>>>(nn, zu, zp, z);
 }
 
-static void precond(mgk_solver* S, const double* r, double* z, bool trans) {
+void precond(mgk_solver* S, const double* r, double* z, bool trans) {
   if (S->kind == MGK_SCHUR) {
     if (trans) throw Error(MGK_E_STATE, "transposed Schur preconditioner is not available");
     if (S->H.storage == MGK_F64) schur_apply_t<double, double>(S, r, z);
@@ -1037,32 +655,12 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-static int fail(const Error& e) {
-  g_err = e.what();
-  return e.code;
-}
 
 }  // namespace mgk
 
 // ---------------------------------------------------------------- C ABI
 
-namespace mgk {
-// Run an entry point body; no exception crosses the C ABI.
-template <class F>
-static int guard(F&& f) {
-  try {
-    return f();
-  } catch (const Error& e) {
-    return fail(e);
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return MGK_E_NOMEM;
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return MGK_E_INVALID;
-  }
-}
-}  // namespace mgk
+
 
 extern "C" {
 
@@ -1344,12 +942,6 @@ int mgk_bsr_grad(mgk_solver* s, const double* d_lambda, const double* d_x, doubl
   });
 }
 
-int mgk_solve_multi(mgk_solver* s, int32_t nrhs, const double* d_B, double* d_X, double rtol,
-                    mgk_info* infos) {
-  (void)s; (void)nrhs; (void)d_B; (void)d_X; (void)rtol; (void)infos;
-  mgk::g_err = "mgk_solve_multi: not available in this build";
-  return MGK_E_STATE;
-}
 
 int mgk_batch_setup(int32_t nsys, const mgk_bsr* const* A, int32_t block_size,
                     mgk_precond_kind kind, const mgk_params* prm, void* hip_stream,

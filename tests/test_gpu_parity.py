@@ -287,3 +287,39 @@ def test_results_independent_of_kernel_tile(storage):
         assert np.array_equal(x, outs[0][1]) and it == outs[0][2]
     with pytest.raises(mgk.MgkError):
         gpu_solver(bsr, hier=storage, force_tile=303)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_multi_rhs_lockstep(storage):
+    """K right-hand sides in one lockstep solve: every column meets the tolerance (oracle
+    SpMV), agrees with the oracle's solve of that column, and a zero column stays zero."""
+    n = 14
+    th, bsr, A = problem(n, 0.5, 21)
+    K = 9
+    Bm = S.body_forces(n, K, 4)
+    Bm[:, 3] = 0.0                        # a zero right-hand side
+    Bm[:, 5] = S.mms_rhs(n)               # a manufactured one
+    s = gpu_solver(bsr, hier=storage)
+    dB = dev(Bm)
+    dX = torch.zeros_like(dB)
+    infos = s.solve_multi(dB, dX, 1e-8)
+    say("multi", storage, [i["iters"] for i in infos])
+    X = dX.cpu().numpy()
+    assert not np.any(X[:, 3]) and infos[3]["iters"] == 0
+    so = oracle.Solver(A, 4)
+    for k in range(K):
+        if k == 3:
+            continue
+        assert infos[k]["status"] == 0
+        b = Bm[:, k]
+        res = np.linalg.norm(b - oracle.spmv(A, X[:, k])) / np.linalg.norm(b)
+        assert res <= 1e-8, (k, res)
+        xo, _ = so.solve(b, 1e-12)
+        assert np.linalg.norm(X[:, k] - xo) <= 1e-6 * np.linalg.norm(xo), k
+    # a column of the lockstep solve equals the same system solved alone (tolerance level)
+    x1 = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    s.solve(dev(np.ascontiguousarray(Bm[:, 5])), x1, 1e-8)
+    assert np.linalg.norm(x1.cpu().numpy() - X[:, 5]) <= 1e-6 * np.linalg.norm(X[:, 5])
+    with pytest.raises(mgk.MgkError):
+        s.solve_multi(torch.zeros((A.shape[0], 33), dtype=torch.float64, device=DEV),
+                      torch.zeros((A.shape[0], 33), dtype=torch.float64, device=DEV))
