@@ -306,3 +306,55 @@ class Solver:
         if rc:
             _err(rc)
         return ptr, col[:nnz], val[:nnz * b * cb].reshape(nnz, b, cb), agg[:nb]
+
+
+class BatchSolver:
+    """Several independent systems of uneven size behind one solver: every stage of the
+    lockstep BiCGStab solve is one launch over all systems (mgk_batch_setup/solve)."""
+
+    def __init__(self, systems, block: int, kind: int = AMG_SPAI0, stream=None, **params):
+        L = lib()
+        self._keep = []
+        structs = []
+        self.sizes = []
+        for ptr, col, val in systems:
+            ptr = np.ascontiguousarray(ptr, np.int32)
+            col = np.ascontiguousarray(col, np.int32)
+            val = np.ascontiguousarray(val, np.float64).reshape(-1)
+            self._keep += [ptr, col, val]
+            structs.append(_Bsr(ptr.size - 1, block, _np_ptr(ptr).value, _np_ptr(col).value,
+                                _np_ptr(val).value))
+            self.sizes.append((ptr.size - 1) * block)
+        self._structs = (_Bsr * len(structs))(*structs)
+        ptrs = (C.c_void_p * len(structs))(*[C.addressof(self._structs[i])
+                                               for i in range(len(structs))])
+        self._ptrs = ptrs
+        self.params = default_params(**params)
+        h = C.c_void_p()
+        rc = L.mgk_batch_setup(len(structs), C.cast(ptrs, C.c_void_p), block, kind,
+                               C.byref(self.params), _stream_handle(stream), C.byref(h))
+        if rc:
+            _err(rc)
+        self._h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.mgk_destroy(self._h)
+            self._h = C.c_void_p()
+
+    __del__ = close
+
+    def solve(self, bs, xs, rtol: float = 1e-8) -> list:
+        import torch
+        n = len(self.sizes)
+        if len(bs) != n or len(xs) != n:
+            raise ValueError("one right-hand side and one solution vector per system")
+        bp = (C.c_void_p * n)(*[_dev_ptr(b, torch.float64, m).value for b, m in zip(bs, self.sizes)])
+        xp = (C.c_void_p * n)(*[_dev_ptr(x, torch.float64, m).value for x, m in zip(xs, self.sizes)])
+        infos = (Info * n)()
+        rc = lib().mgk_batch_solve(self._h, C.cast(bp, C.c_void_p), C.cast(xp, C.c_void_p),
+                                   rtol, infos)
+        if rc < 0:
+            _err(rc)
+        return [i.as_dict() for i in infos]

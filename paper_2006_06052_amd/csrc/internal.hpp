@@ -351,6 +351,8 @@ static void vcycle(hipStream_t st, DHier& H, const TIN* r, TOUT* z, bool trans) 
 
 struct MultiWork;
 void multi_free(MultiWork* w);
+struct BatchWork;
+void batch_free(BatchWork* w);
 
 inline int fail(const Error& e) {
   g_err = e.what();
@@ -411,8 +413,10 @@ struct mgk_solver {
   double setup_ms = 0.0;
   bool host_only = false;
   MultiWork* multi = nullptr;      // multi-RHS workspace, created by the first mgk_solve_multi
+  BatchWork* batch = nullptr;      // set for solvers made by mgk_batch_setup
   ~mgk_solver() {
     if (multi) mgk::multi_free(multi);
+    if (batch) mgk::batch_free(batch);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : tev)

@@ -751,6 +751,10 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     mgk::g_err = "solve: null argument or non-positive rtol";
     return MGK_E_INVALID;
   }
+  if (s->batch) {
+    mgk::g_err = "a batch solver only answers mgk_batch_solve";
+    return MGK_E_STATE;
+  }
   if (s->host_only) {
     mgk::g_err = "solve: solver was set up with mgk_setup_host (no device data)";
     return MGK_E_STATE;
@@ -800,6 +804,10 @@ int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t tra
     mgk::g_err = "precond_apply: null argument";
     return MGK_E_INVALID;
   }
+  if (s->batch) {
+    mgk::g_err = "a batch solver only answers mgk_batch_solve";
+    return MGK_E_STATE;
+  }
   if (s->host_only) {
     mgk::g_err = "precond_apply: solver has no device data";
     return MGK_E_STATE;
@@ -821,6 +829,10 @@ int mgk_spmv(mgk_solver* s, int32_t hier, int32_t level, int32_t which, const vo
   if (!s || !d_x || !d_y || which < 0 || which > 3) {
     mgk::g_err = "spmv: bad argument";
     return MGK_E_INVALID;
+  }
+  if (s->batch) {
+    mgk::g_err = "a batch solver only answers mgk_batch_solve";
+    return MGK_E_STATE;
   }
   if (s->host_only) {
     mgk::g_err = "spmv: solver has no device data";
@@ -924,7 +936,7 @@ int mgk_theta_grad(int32_t n, const double* d_lambda, const double* d_x, double*
 }
 
 int mgk_bsr_grad(mgk_solver* s, const double* d_lambda, const double* d_x, double* d_gval) {
-  if (!s || !d_lambda || !d_x || !d_gval || s->host_only) {
+  if (!s || !d_lambda || !d_x || !d_gval || s->host_only || s->batch) {
     mgk::g_err = "bsr_grad: bad argument or solver without device data";
     return MGK_E_INVALID;
   }
@@ -942,22 +954,6 @@ int mgk_bsr_grad(mgk_solver* s, const double* d_lambda, const double* d_x, doubl
   });
 }
 
-
-int mgk_batch_setup(int32_t nsys, const mgk_bsr* const* A, int32_t block_size,
-                    mgk_precond_kind kind, const mgk_params* prm, void* hip_stream,
-                    mgk_solver** out) {
-  (void)nsys; (void)A; (void)block_size; (void)kind; (void)prm; (void)hip_stream;
-  if (out) *out = nullptr;
-  mgk::g_err = "mgk_batch_setup: not available in this build";
-  return MGK_E_STATE;
-}
-
-int mgk_batch_solve(mgk_solver* s, const double* const* d_b, double* const* d_x, double rtol,
-                    mgk_info* infos) {
-  (void)s; (void)d_b; (void)d_x; (void)rtol; (void)infos;
-  mgk::g_err = "mgk_batch_solve: not available in this build";
-  return MGK_E_STATE;
-}
 
 int mgk_setup_host(const mgk_bsr* A, int32_t block_size, mgk_precond_kind kind,
                    const mgk_params* prm, mgk_solver** out) {

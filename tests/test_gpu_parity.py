@@ -323,3 +323,30 @@ def test_multi_rhs_lockstep(storage):
     with pytest.raises(mgk.MgkError):
         s.solve_multi(torch.zeros((A.shape[0], 33), dtype=torch.float64, device=DEV),
                       torch.zeros((A.shape[0], 33), dtype=torch.float64, device=DEV))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_uneven_systems(storage):
+    """Uneven systems in one batch: each meets 1e-8 (oracle SpMV), agrees with its own
+    oracle solve, and with the same system solved alone on the GPU (to the tolerance: the
+    batched dot products use a different, fixed, reduction partition)."""
+    ns = [10, 13, 16, 12]
+    probs = [problem(n, 0.5, 40 + k) for k, n in enumerate(ns)]
+    bs = [dev(oracle.spmv(A, S.mms_solution(n))) for n, (_, _, A) in zip(ns, probs)]
+    bsol = mgk.BatchSolver([p[1] for p in probs], 4, mgk.AMG_SPAI0,
+                           stream=torch.cuda.current_stream(), hier=storage, coarse_enough=300)
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = bsol.solve(bs, xs, 1e-8)
+    say("batch", storage, [i["iters"] for i in infos])
+    for k, (n, (th, bsr, A)) in enumerate(zip(ns, probs)):
+        b = bs[k].cpu().numpy()
+        x = xs[k].cpu().numpy()
+        assert infos[k]["status"] == 0
+        assert np.linalg.norm(b - oracle.spmv(A, x)) <= 1e-8 * np.linalg.norm(b)
+        xo, _ = oracle.Solver(A, 4, coarse_enough=300).solve(b, 1e-12)
+        assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+        s1 = gpu_solver(bsr, hier=storage, coarse_enough=300)
+        x1 = torch.zeros_like(bs[k])
+        i1 = s1.solve(bs[k], x1, 1e-8)
+        assert abs(i1["iters"] - infos[k]["iters"]) <= max(2, infos[k]["iters"] // 10)
+        assert torch.linalg.norm(x1 - xs[k]) <= 1e-6 * torch.linalg.norm(x1), k
