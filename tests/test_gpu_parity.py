@@ -350,3 +350,35 @@ def test_batch_uneven_systems(storage):
         i1 = s1.solve(bs[k], x1, 1e-8)
         assert abs(i1["iters"] - infos[k]["iters"]) <= max(2, infos[k]["iters"] // 10)
         assert torch.linalg.norm(x1 - xs[k]) <= 1e-6 * torch.linalg.norm(x1), k
+
+
+def test_autograd_functions():
+    """torch.autograd through the solve: d/dtheta against the oracle gradient formula on the
+    oracle's own solves, d/db = lambda, and the block-value gradient -lambda x^T."""
+    from paper_2006_06052_amd.autograd import bsr_solve, stokes_solve
+    n = 10
+    th = S.theta_field(n, 0.5, 60)
+    thr = S.theta_field(n, 0.5, 61)
+    b = S.mms_rhs(n)
+    A, Ar = oracle.stokes_matrix(n, th), oracle.stokes_matrix(n, thr)
+    xt, _ = oracle.Solver(Ar, 4, coarse_enough=300).solve(b, 1e-13)
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    db = dev(b).requires_grad_(True)
+    x = stokes_solve(theta, db, n, hier=mgk.F32, coarse_enough=300)
+    loss = 0.5 * torch.sum((x - dev(xt)) ** 2)
+    loss.backward()
+    so = oracle.Solver(A, 4, coarse_enough=300)
+    xo, _ = so.solve(b, 1e-13)
+    lo, _ = so.solve(xo - xt, 1e-13, transposed=True)
+    go = oracle.theta_gradient(n, lo, xo)
+    g = theta.grad.numpy()
+    assert np.linalg.norm(g - go) <= 1e-6 * np.linalg.norm(go)
+    assert np.linalg.norm(db.grad.cpu().numpy() - lo) <= 1e-6 * np.linalg.norm(lo)
+    # gradient with respect to the stored block values
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    vals = torch.tensor(val, dtype=torch.float64, requires_grad=True)
+    x2 = bsr_solve(ptr, col, vals, dev(b), 4, hier=mgk.F32, coarse_enough=300)
+    (0.5 * torch.sum((x2 - dev(xt)) ** 2)).backward()
+    rows = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    ref = -lo.reshape(-1, 4)[rows][:, :, None] * xo.reshape(-1, 4)[col][:, None, :]
+    assert np.linalg.norm(vals.grad.numpy() - ref) <= 1e-6 * np.linalg.norm(ref)
