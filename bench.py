@@ -110,6 +110,183 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     return 2 * nbytes / t / 1e9
 
 
+def _median_solve(fn, torch, steps=3, warmup=1):
+    """Median wall time of fn() (which returns an info record or list of them), each call
+    bracketed by device synchronizations."""
+    import numpy as np
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times)), out
+
+
+def secondary_workloads(mgk, S, torch, log_fn, which):
+    """The other solve shapes of the method, timed the same way (solution buffers reset
+    inside each timed call, hierarchy resident, setup outside):
+
+    schur64  - 64^3, theta = exp(N(0,1)) per cell (seed 3), b = A(theta) x*; pressure-correction
+               Schur preconditioner (velocity and pressure-Schur AMG, BF16 hierarchies) under
+               FGMRES(30), against the FP64-hierarchy run of the same solve;
+    multi64  - 64^3 with 32 body-force right-hand sides (seed 4) in one lockstep BiCGStab,
+               against 4 single-RHS solves of columns 0..3 scaled to 32;
+    batch8   - 8 systems of 24^3 ... 64^3 nodes, theta_k = exp(N(0, 0.25)) (seed 40+k),
+               b_k = A_k x*, in one batched solve, against the 8 systems solved one by one;
+    adjoint48 - 48^3, theta seed 5, target from theta seed 50: forward solve, adjoint solve
+               with the transposed V-cycle, and the per-cell viscosity gradient.
+    All hierarchies are FP32 unless stated; rtol 1e-8 (adjoint workload 1e-10)."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def solver(ptr, col, val, kind=mgk.AMG_SPAI0, **kw):
+        return mgk.Solver(ptr, col, val, 4, kind, stream=stream, **kw)
+
+    def a_times(s, x):
+        y = torch.empty_like(x)
+        s.spmv(x, y)
+        return y
+
+    if "schur64" in which:
+        n = 64
+        ptr, col, val = mgk.stokes_bsr(n, S.theta_field(n, 1.0, 3))
+        xs = torch.from_numpy(S.mms_solution(n)).cuda()
+        r = {}
+        for tag, hier in (("bf16", mgk.BF16), ("f64", mgk.F64)):
+            t0 = time.perf_counter()
+            s = solver(ptr, col, val, mgk.SCHUR, hier=hier, krylov=mgk.FGMRES)
+            t_setup = time.perf_counter() - t0
+            b = a_times(s, xs)
+            x = torch.zeros_like(b)
+
+            def run():
+                x.zero_()
+                return s.solve(b, x, 1e-8)
+            t, info = _median_solve(run, torch)
+            r[tag] = {"solve_s": t, "iters": info["iters"], "restarts": info["restarts"],
+                      "rel_resid": info["rel_resid"], "status": info["status"],
+                      "setup_s": t_setup}
+            log_fn(f"schur64 {tag}: {t:.3f}s, {info['iters']} iterations")
+            del s
+        r["speedup_bf16_vs_f64"] = r["f64"]["solve_s"] / r["bf16"]["solve_s"]
+        out["schur64_fgmres"] = r
+
+    if "multi64" in which:
+        n, K = 64, 32
+        ptr, col, val = mgk.stokes_bsr(n)
+        B = torch.from_numpy(np.ascontiguousarray(S.body_forces(n, K, 4))).cuda()
+        s = solver(ptr, col, val, hier=mgk.F32)
+        X = torch.zeros_like(B)
+
+        def run():
+            X.zero_()
+            return s.solve_multi(B, X, 1e-8)
+        t, infos = _median_solve(run, torch)
+        cols = [B[:, k].contiguous() for k in range(4)]
+        xc = torch.zeros_like(cols[0])
+
+        def run1():
+            its = []
+            for c in cols:
+                xc.zero_()
+                its.append(s.solve(c, xc, 1e-8)["iters"])
+            return its
+        t1, its1 = _median_solve(run1, torch)
+        seq = t1 / len(cols) * K
+        out["multi64_32rhs"] = {"solve_s": t, "rhs": K,
+                                "iters": [i["iters"] for i in infos],
+                                "all_converged": all(i["status"] == 0 for i in infos),
+                                "single_rhs_s_x32": seq, "speedup_vs_single": seq / t,
+                                "single_iters": its1}
+        log_fn(f"multi64: {t:.3f}s for {K} RHS, single-RHS x32 {seq:.3f}s")
+        del s
+
+    if "batch8" in which:
+        ns = [24, 32, 40, 48, 48, 56, 64, 64]
+        systems, bs, seq_t, seq_it = [], [], 0.0, []
+        for k, n in enumerate(ns):
+            p_, c_, v_ = mgk.stokes_bsr(n, S.theta_field(n, 0.5, 40 + k))
+            systems.append((p_, c_, v_))
+            s = solver(p_, c_, v_, hier=mgk.F32)
+            b = a_times(s, torch.from_numpy(S.mms_solution(n)).cuda())
+            bs.append(b)
+            x = torch.zeros_like(b)
+
+            def run1():
+                x.zero_()
+                return s.solve(b, x, 1e-8)
+            t1, i1 = _median_solve(run1, torch)
+            seq_t += t1
+            seq_it.append(i1["iters"])
+            del s
+        t0 = time.perf_counter()
+        bsol = mgk.BatchSolver(systems, 4, mgk.AMG_SPAI0, stream=stream, hier=mgk.F32)
+        t_setup = time.perf_counter() - t0
+        xs = [torch.zeros_like(b) for b in bs]
+
+        def run():
+            for x in xs:
+                x.zero_()
+            return bsol.solve(bs, xs, 1e-8)
+        t, infos = _median_solve(run, torch)
+        out["batch8_uneven"] = {"solve_s": t, "nodes_per_side": ns,
+                                "iters": [i["iters"] for i in infos],
+                                "all_converged": all(i["status"] == 0 for i in infos),
+                                "setup_s": t_setup, "one_by_one_s": seq_t,
+                                "one_by_one_iters": seq_it, "speedup_vs_one_by_one": seq_t / t}
+        log_fn(f"batch8: {t:.3f}s, one by one {seq_t:.3f}s")
+        del bsol
+
+    if "adjoint48" in which:
+        n = 48
+        bnp = S.mms_rhs(n)
+        b = torch.from_numpy(bnp).cuda()
+        pr, cr, vr = mgk.stokes_bsr(n, S.theta_field(n, 0.5, 50))
+        sr = solver(pr, cr, vr, hier=mgk.F32)
+        xt = torch.zeros_like(b)
+        sr.solve(b, xt, 1e-10)
+        del sr
+        ptr, col, val = mgk.stokes_bsr(n, S.theta_field(n, 0.5, 5))
+        t0 = time.perf_counter()
+        s = solver(ptr, col, val, hier=mgk.F32, enable_transpose=1)
+        t_setup = time.perf_counter() - t0
+        x = torch.zeros_like(b)
+        lam = torch.zeros_like(b)
+        g = torch.empty((n - 1) ** 3, dtype=torch.float64, device="cuda")
+        rec = {}
+
+        def run():
+            x.zero_()
+            lam.zero_()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            fi = s.solve(b, x, 1e-10)
+            e[1].record()
+            ai = s.solve_transposed(x - xt, lam, 1e-10)
+            mgk.theta_grad(n, lam, x, g, stream=stream)
+            e[2].record()
+            e[2].synchronize()
+            rec.update(forward_s=e[0].elapsed_time(e[1]) * 1e-3,
+                       adjoint_grad_s=e[1].elapsed_time(e[2]) * 1e-3)
+            return fi, ai
+        t, (fi, ai) = _median_solve(run, torch)
+        out["adjoint48_gradient"] = {"solve_s": t, "forward_iters": fi["iters"],
+                                     "adjoint_iters": ai["iters"],
+                                     "converged": fi["status"] == 0 and ai["status"] == 0,
+                                     "setup_s": t_setup, **rec}
+        log_fn(f"adjoint48: {t:.3f}s (forward {fi['iters']} it, adjoint {ai['iters']} it)")
+        del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, b_np, iters_scale, log_fn):
     """The oracle as it stands (scalar CSR FP64, OpenMP SpMV) on the host cores: setup once
     (not part of the metric), then a bounded run of 3 BiCGStab iterations, scaled to the
@@ -140,6 +317,8 @@ def main():
     ap.add_argument("--n", type=int, default=96)
     ap.add_argument("--arms", default="bsr_f32,bsr_f64,bsr_bf16,csr_f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--secondary", default="schur64,multi64,batch8,adjoint48",
+                    help="other solve shapes timed after the headline (empty: none)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the FP64 BSR SpMV loop")
     ap.add_argument("--counters", action="store_true",
@@ -264,6 +443,9 @@ def main():
         roofline["copy_ceiling_gbs"] = copy_ceiling(torch)
         roofline["frac_of_copy_ceiling"] = roofline["achieved"] / roofline["copy_ceiling_gbs"]
     out["roofline"] = roofline
+    which = [w for w in args.secondary.split(",") if w]
+    if which:
+        out["secondary"] = secondary_workloads(mgk, S, torch, log, which)
     if not args.no_cpu_baseline and os.environ.get("BENCH_NO_CPU") != "1":
         scale = results.get("bsr_f64", results[head])["iters"]
         out["cpu_baseline"] = cpu_baseline(n, b, scale, log)
