@@ -90,9 +90,12 @@ typedef struct {
   int32_t time_spmv;       /* 1: time every outer-operator SpMV of a solve with HIP
                               events on the solver's stream (mgk_info.spmv_ms) */
   int32_t force_tile;      /* 0: the autotuner picks each operator's kernel tile;
-                              otherwise 100*S + U (S lanes per block row, U blocks per
-                              step) for every operator.  Results are bitwise the same
-                              for every tile. */
+                              otherwise 10000*RPL + 100*S + U (S lanes per block row, U
+                              blocks per step, RPL scalar rows per lane) for every
+                              operator.  RPL 2 or 4 exists for BF16 4x4 blocks only; other
+                              operators then take (S, U) if that tile exists for them, else
+                              the autotuner's tile.  An unknown tile is MGK_E_INVALID.
+                              Results are bitwise the same for every tile. */
 } mgk_params;
 
 typedef struct {

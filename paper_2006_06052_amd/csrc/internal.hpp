@@ -94,7 +94,7 @@ inline uint16_t f32_to_bf16(float f) {
 }
 
 struct Tile {
-  int s = 1, u = 4;
+  int s = 1, u = 4, rpl = 1;
 };
 
 // Device block matrix in a storage precision, with optional column index
@@ -156,9 +156,9 @@ inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_ind
 
 // ---------------------------------------------------------------- sparse launch
 
-template <int BR, int S>
+template <int BR, int S, int RPL = 1>
 static int nwg_rows(int nbr) {
-  return std::max(1, (nbr + RowMap<BR, S>::ROWS - 1) / RowMap<BR, S>::ROWS);
+  return std::max(1, (nbr + RowMap<BR, S, RPL>::ROWS - 1) / RowMap<BR, S, RPL>::ROWS);
 }
 
 template <class TV>
@@ -168,8 +168,19 @@ using AccOf = typename std::conditional<std::is_same<TV, double>::value, double,
 // Candidates below: few lanes and deep unrolling for the short fine-level rows,
 // many lanes for the long rows of coarse Galerkin levels and restrictions.
 #define MGK_TILES_B(CASE) \
-  CASE(1, 4) CASE(1, 8) CASE(2, 4) CASE(2, 8) CASE(4, 4) CASE(8, 4) CASE(16, 2)
+  CASE(1, 4) CASE(1, 8) CASE(2, 2) CASE(2, 4) CASE(2, 8) CASE(4, 2) CASE(4, 4) CASE(8, 4) CASE(16, 2)
 #define MGK_TILES_1(CASE) CASE(1, 8) CASE(2, 4) CASE(4, 4) CASE(8, 4) CASE(16, 2) CASE(32, 2)
+// Wide-lane tiles (S, U, RPL) for BF16 4x4 blocks: a lane owns RPL adjacent rows
+// of a block and reads them with 16-byte loads (a single BF16 block row is 8 bytes).
+#define MGK_TILES_W(CASE) \
+  CASE(2, 4, 2) CASE(4, 2, 2) CASE(4, 4, 2) CASE(8, 2, 2) CASE(16, 2, 2) CASE(4, 2, 4) \
+  CASE(8, 1, 4) CASE(16, 1, 4)
+
+// Products that may use the wide-lane tiles.
+template <int BR, int BC, class TV>
+constexpr bool wide_ok() {
+  return BR == 4 && BC == 4 && sizeof(TV) == 2;
+}
 
 template <int BR, class F>
 static void tile_switch(const Tile& t, F&& launch) {
@@ -188,6 +199,27 @@ static void tile_switch(const Tile& t, F&& launch) {
                                  std::to_string(t.u));
 }
 
+// Tile dispatch including the wide-lane tiles (when WIDE): launch(S, U, RPL).
+template <int BR, bool WIDE, class F>
+static void tile_switch_r(const Tile& t, F&& launch) {
+  if (t.rpl == 1) {
+    tile_switch<BR>(t, [&](auto SS, auto UU) { launch(SS, UU, std::integral_constant<int, 1>()); });
+    return;
+  }
+  if constexpr (WIDE) {
+#define MGK_WCASE(SS, UU, RR)                                                              \
+  if (t.s == SS && t.u == UU && t.rpl == RR) {                                             \
+    launch(std::integral_constant<int, SS>(), std::integral_constant<int, UU>(),            \
+           std::integral_constant<int, RR>());                                              \
+    return;                                                                                 \
+  }
+    MGK_TILES_W(MGK_WCASE)
+#undef MGK_WCASE
+  }
+  throw Error(MGK_E_INVALID, "no kernel for tile s=" + std::to_string(t.s) + " u=" +
+                                 std::to_string(t.u) + " rpl=" + std::to_string(t.rpl));
+}
+
 // y = alpha A x + beta y.
 template <int BR, int BC, class TV, class TX, class TY>
 static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, const TX* x,
@@ -198,15 +230,20 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, 
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const TV* v = (const TV*)M.val;
-  tile_switch<BR>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int g = nwg_rows<BR, S_>(nrows);
-    if (trans)
+  if (trans) {
+    tile_switch<BR>(tile, [&](auto SS, auto UU) {
+      constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+      const int g = nwg_rows<BR, S_>(nrows);
       k_spmv<BR, BC, S_, U_, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
                                                                      (TA)alpha, (TA)beta);
-    else
-      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
-                                                                      (TA)alpha, (TA)beta);
+    });
+    return;
+  }
+  tile_switch_r<BR, wide_ok<BR, BC, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
+    const int g = nwg_rows<BR, S_, R_>(nrows);
+    k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
+                                                                        (TA)alpha, (TA)beta);
   });
 }
 
@@ -242,15 +279,20 @@ static void residual_s(hipStream_t st, const DMat& M, bool trans, const Tile& ti
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const TV* v = (const TV*)M.val;
-  tile_switch<BR>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int g = nwg_rows<BR, S_>(nrows);
-    if (trans)
+  if (trans) {
+    tile_switch<BR>(tile, [&](auto SS, auto UU) {
+      constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+      const int g = nwg_rows<BR, S_>(nrows);
       k_residual<BR, BC, S_, U_, true, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
                                                                           z, t);
-    else
-      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
-                                                                           z, t);
+    });
+    return;
+  }
+  tile_switch_r<BR, wide_ok<BR, BC, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
+    const int g = nwg_rows<BR, S_, R_>(nrows);
+    k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
+                                                                             f, z, t);
   });
 }
 
@@ -263,15 +305,20 @@ static void smooth_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const TV* v = (const TV*)M.val;
-  tile_switch<B>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    const int g = nwg_rows<B, S_>(nrows);
-    if (trans)
+  if (trans) {
+    tile_switch<B>(tile, [&](auto SS, auto UU) {
+      constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+      const int g = nwg_rows<B, S_>(nrows);
       k_smooth<B, S_, U_, true, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, Mb,
                                                                            f, z, zout);
-    else
-      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v,
-                                                                            Mb, f, z, zout);
+    });
+    return;
+  }
+  tile_switch_r<B, wide_ok<B, B, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
+    const int g = nwg_rows<B, S_, R_>(nrows);
+    k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
+                                                                              Mb, f, z, zout);
   });
 }
 

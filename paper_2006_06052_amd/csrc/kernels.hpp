@@ -36,6 +36,7 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 256;          // threads per workgroup (4 waves)
 constexpr int WAVE = 64;
@@ -52,7 +53,8 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t u) {
 
 // ---- value loads -----------------------------------------------------------
 
-// Row r of a stored block: BC consecutive values, streamed (non-temporal).
+// BC consecutive values of a stored block (one block row, or several adjacent
+// block rows for the wide BF16 lanes), streamed (non-temporal).
 template <int BC, class TV, class TA>
 __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
   if constexpr (sizeof(TV) == 8 && BC == 4) {
@@ -62,6 +64,20 @@ __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
   } else if constexpr (sizeof(TV) == 4 && BC == 4) {
     const f4v a = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
     out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  } else if constexpr (sizeof(TV) == 2 && BC % 8 == 0) {
+    // several consecutive block rows: 16-byte loads of eight values each
+#pragma unroll
+    for (int q = 0; q < BC / 8; ++q) {
+      const u4v a = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p) + q);
+      out[8 * q + 0] = __uint_as_float(a.x << 16);
+      out[8 * q + 1] = __uint_as_float(a.x & 0xffff0000u);
+      out[8 * q + 2] = __uint_as_float(a.y << 16);
+      out[8 * q + 3] = __uint_as_float(a.y & 0xffff0000u);
+      out[8 * q + 4] = __uint_as_float(a.z << 16);
+      out[8 * q + 5] = __uint_as_float(a.z & 0xffff0000u);
+      out[8 * q + 6] = __uint_as_float(a.w << 16);
+      out[8 * q + 7] = __uint_as_float(a.w & 0xffff0000u);
+    }
   } else if constexpr (sizeof(TV) == 2 && BC == 4) {
     const u2v a = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
     out[0] = __uint_as_float(a.x << 16);
@@ -113,35 +129,40 @@ __device__ __forceinline__ int xcd_remap(int w, int nwg) {
 
 // ---- block-row engine --------------------------------------------------------
 
-template <int BR, int S>
+// RPL: scalar rows of the block row owned by one lane (1, or 2 / 4 for the
+// BF16 square blocks, whose single block row is only 8 bytes wide).
+template <int BR, int S, int RPL = 1>
 struct RowMap {
-  static constexpr int G = BR * S;              // lanes per block row
+  static_assert(BR % RPL == 0, "rows per lane");
+  static constexpr int LB = BR / RPL;           // lanes per block
+  static constexpr int G = LB * S;              // lanes per block row
   static constexpr int GPW = WAVE / G;          // block rows per wave
   static constexpr int ROWS = GPW * (WG / WAVE);// block rows per workgroup
 };
 
 struct LaneInfo {
   int i;        // block row (may be >= nbr for idle groups)
-  int r, s;     // scalar row inside the block, split index
+  int r, s;     // first scalar row inside the block (RPL rows r, r+1, ...), split index
   int gbase;    // first lane of this group inside the wave
   bool active;  // lane belongs to a group
 };
 
-template <int BR, int S>
+template <int BR, int S, int RPL = 1>
 __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
-  using M = RowMap<BR, S>;
+  using M = RowMap<BR, S, RPL>;
   LaneInfo L;
   const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x >> 6;
   const int g = lane / M::G, w = lane - g * M::G;
   L.active = g < M::GPW;
-  L.s = w / BR;
-  L.r = w - L.s * BR;
+  L.s = w / M::LB;
+  L.r = (w - L.s * M::LB) * RPL;
   L.gbase = g * M::G;
   L.i = (logical_wg * (WG / WAVE) + wave) * M::GPW + g;
   return L;
 }
 
-// Row r of block row i times x, for the lane (s, r) of a group of BR*S lanes.
+// Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
+// (BR/RPL)*S lanes.
 //
 // Summation order, identical for every tile (S, U): block kr (kr-th stored
 // block of the row) is added, in ascending kr, to stripe kr mod NS (NS = 16,
@@ -156,16 +177,23 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
 // short and would otherwise be bound by one dependent col -> x chain per
 // block).  When T > U the stripe accumulators rotate by U after each step so
 // that block u of a step always lands in accumulator u.
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA>
-__device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int* __restrict__ ptr,
-                                          const int* __restrict__ col, const int* __restrict__ blk,
-                                          const TV* __restrict__ val, const TX* __restrict__ x) {
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA, int RPL>
+__device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
+                                              const int* __restrict__ ptr,
+                                              const int* __restrict__ col,
+                                              const int* __restrict__ blk,
+                                              const TV* __restrict__ val,
+                                              const TX* __restrict__ x, TA (&out)[RPL]) {
   constexpr int NS = BR == 1 ? 32 : 16;
   constexpr int T = NS / S;
+  constexpr int LB = BR / RPL;
   static_assert(S <= NS && (U % T == 0 || T % U == 0), "tile");
-  TA acc[T];
+  static_assert(!TRANS || RPL == 1, "transposed products read block columns, one row per lane");
+  TA acc[RPL][T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) acc[t] = 0;
+  for (int q = 0; q < RPL; ++q)
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[q][t] = 0;
   if (L.active && L.i < nbr) {
     const int k0 = ptr[L.i], k1 = ptr[L.i + 1];
     int steps = 0;
@@ -179,13 +207,13 @@ __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int*
         j[u] = ok[u] ? __builtin_nontemporal_load(col + k) : 0;
         kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
       }
-      TA v[U][BC], xv[U][BC];
+      TA v[U][RPL * BC], xv[U][BC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (ok[u]) {
           load_x<BC, TX, TA>(x + (size_t)j[u] * BC, xv[u]);
           if constexpr (!TRANS) {
-            load_vals<BC, TV, TA>(val + (size_t)kk[u] * (BR * BC) + L.r * BC, v[u]);
+            load_vals<RPL * BC, TV, TA>(val + (size_t)kk[u] * (BR * BC) + L.r * BC, v[u]);
           } else {
             // Block kk of A (BC x BR) read by columns: (A^T)[r][c] = A_kk[c][r].
             const TV* b = val + (size_t)kk[u] * (BR * BC);
@@ -194,45 +222,63 @@ __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int*
           }
         } else {
 #pragma unroll
-          for (int c = 0; c < BC; ++c) {
-            v[u][c] = 0;
-            xv[u][c] = 0;
-          }
+          for (int c = 0; c < RPL * BC; ++c) v[u][c] = 0;
+#pragma unroll
+          for (int c = 0; c < BC; ++c) xv[u][c] = 0;
         }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        TA& a = acc[u % T];
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int c = 0; c < BC; ++c) a = fma_(v[u][c], xv[u][c], a);
-      }
+        for (int q = 0; q < RPL; ++q) {
+          TA& a = acc[q][u % T];
+#pragma unroll
+          for (int c = 0; c < BC; ++c) a = fma_(v[u][q * BC + c], xv[u][c], a);
+        }
       if constexpr (T > U) {
-        TA tmp[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) tmp[t] = acc[(t + U) % T];
+        for (int q = 0; q < RPL; ++q) {
+          TA tmp[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) acc[t] = tmp[t];
+          for (int t = 0; t < T; ++t) tmp[t] = acc[q][(t + U) % T];
+#pragma unroll
+          for (int t = 0; t < T; ++t) acc[q][t] = tmp[t];
+        }
       }
     }
     if constexpr (T > U) {
-      // undo the rotations: acc[t] now holds stripe (t + steps*U) mod T
-      for (int q = (T / U - steps % (T / U)) % (T / U); q > 0; --q) {
-        TA tmp[T];
+      // undo the rotations: acc[.][t] now holds stripe (t + steps*U) mod T
+      for (int n = (T / U - steps % (T / U)) % (T / U); n > 0; --n)
 #pragma unroll
-        for (int t = 0; t < T; ++t) tmp[t] = acc[(t + U) % T];
+        for (int q = 0; q < RPL; ++q) {
+          TA tmp[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) acc[t] = tmp[t];
-      }
+          for (int t = 0; t < T; ++t) tmp[t] = acc[q][(t + U) % T];
+#pragma unroll
+          for (int t = 0; t < T; ++t) acc[q][t] = tmp[t];
+        }
     }
   }
 #pragma unroll
-  for (int h = T / 2; h >= 1; h >>= 1)
+  for (int q = 0; q < RPL; ++q) {
 #pragma unroll
-    for (int t = 0; t < h; ++t) acc[t] += acc[t + h];
-  TA a0 = acc[0];
+    for (int h = T / 2; h >= 1; h >>= 1)
 #pragma unroll
-  for (int m = S / 2; m >= 1; m >>= 1) a0 += __shfl_down(a0, BR * m, WAVE);
-  return a0;
+      for (int t = 0; t < h; ++t) acc[q][t] += acc[q][t + h];
+    TA a0 = acc[q][0];
+#pragma unroll
+    for (int m = S / 2; m >= 1; m >>= 1) a0 += __shfl_down(a0, LB * m, WAVE);
+    out[q] = a0;
+  }
+}
+
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA>
+__device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int* __restrict__ ptr,
+                                          const int* __restrict__ col, const int* __restrict__ blk,
+                                          const TV* __restrict__ val, const TX* __restrict__ x) {
+  TA out[1];
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, 1>(L, nbr, ptr, col, blk, val, x, out);
+  return out[0];
 }
 
 // Deterministic workgroup sum of up to two values; thread 0 returns them.
@@ -264,7 +310,8 @@ __device__ __forceinline__ void wg_sum2(T& a, T& b) {
 // ---- sparse kernels ------------------------------------------------------------
 
 // y = alpha A x + beta y   (beta == 0: y is not read).
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TY, class TA>
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TY, class TA,
+          int RPL = 1>
 __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ ptr,
                                              const int* __restrict__ col,
                                              const int* __restrict__ blk,
@@ -272,13 +319,17 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
                                              const TX* __restrict__ x, TY* __restrict__ y,
                                              TA alpha, TA beta) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const LaneInfo L = lane_info<BR, S>(lw);
-  TA acc = row_product<BR, BC, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, x);
+  const LaneInfo L = lane_info<BR, S, RPL>(lw);
+  TA acc[RPL];
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, x, acc);
   if (L.active && L.s == 0 && L.i < nbr) {
-    const size_t row = (size_t)L.i * BR + L.r;
-    TA out = alpha * acc;
-    if (beta != TA(0)) out += beta * (TA)y[row];
-    y[row] = (TY)out;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const size_t row = (size_t)L.i * BR + L.r + q;
+      TA out = alpha * acc[q];
+      if (beta != TA(0)) out += beta * (TA)y[row];
+      y[row] = (TY)out;
+    }
   }
 }
 
@@ -344,7 +395,8 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
 }
 
 // t = f - A z  (A may be rectangular: BR x BC blocks).
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TF, class TA>
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TF, class TA,
+          int RPL = 1>
 __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const int* __restrict__ blk,
@@ -352,17 +404,21 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
                                                  const TF* __restrict__ f,
                                                  const TX* __restrict__ z, TX* __restrict__ t) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const LaneInfo L = lane_info<BR, S>(lw);
-  TA acc = row_product<BR, BC, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
+  const LaneInfo L = lane_info<BR, S, RPL>(lw);
+  TA acc[RPL];
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
   if (L.active && L.s == 0 && L.i < nbr) {
-    const size_t row = (size_t)L.i * BR + L.r;
-    t[row] = (TX)((TA)f[row] - acc);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const size_t row = (size_t)L.i * BR + L.r + q;
+      t[row] = (TX)((TA)f[row] - acc[q]);
+    }
   }
 }
 
 // Post-smoothing: zout = z + M (f - A z), M block diagonal (M^T when TRANS).
 template <int BR, int S, int U, bool TRANS, class TV, class TX, class TF, class TO, class TM,
-          class TA>
+          class TA, int RPL = 1>
 static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
                                                const int* __restrict__ col,
                                                const int* __restrict__ blk,
@@ -371,26 +427,33 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
                                                const TF* __restrict__ f,
                                                const TX* __restrict__ z, TO* __restrict__ zout) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const LaneInfo L = lane_info<BR, S>(lw);
-  TA acc = row_product<BR, BR, S, U, TRANS, TV, TX, TA>(L, nbr, ptr, col, blk, val, z);
+  const LaneInfo L = lane_info<BR, S, RPL>(lw);
+  TA acc[RPL];
+  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
   const bool own = L.active && L.i < nbr;
-  TA res = 0;
-  if (own && L.s == 0) {
-    const size_t row = (size_t)L.i * BR + L.r;
-    res = (TA)f[row] - acc;
+  TA res[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    res[q] = 0;
+    if (own && L.s == 0) res[q] = (TA)f[(size_t)L.i * BR + L.r + q] - acc[q];
   }
-  // Gather the BR residuals of the block row from the s == 0 lanes.
+  // Gather the BR residuals of the block row from the s == 0 lanes (row c is
+  // entry c % RPL of lane c / RPL of the group).
   TA rv[BR];
 #pragma unroll
-  for (int c = 0; c < BR; ++c) rv[c] = __shfl(res, L.gbase + c, WAVE);
+  for (int c = 0; c < BR; ++c) rv[c] = __shfl(res[c % RPL], L.gbase + c / RPL, WAVE);
   if (own && L.s == 0) {
-    const size_t row = (size_t)L.i * BR + L.r;
     const TM* m = M + (size_t)L.i * BR * BR;
-    TA out = (TA)z[row];
 #pragma unroll
-    for (int c = 0; c < BR; ++c)
-      out = fma_((TA)(TRANS ? m[c * BR + L.r] : m[L.r * BR + c]), rv[c], out);
-    zout[row] = (TO)out;
+    for (int q = 0; q < RPL; ++q) {
+      const int r = L.r + q;
+      const size_t row = (size_t)L.i * BR + r;
+      TA out = (TA)z[row];
+#pragma unroll
+      for (int c = 0; c < BR; ++c)
+        out = fma_((TA)(TRANS ? m[c * BR + r] : m[r * BR + c]), rv[c], out);
+      zout[row] = (TO)out;
+    }
   }
 }
 

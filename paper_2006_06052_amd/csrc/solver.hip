@@ -27,11 +27,13 @@ struct TuneCache {
     FILE* f = fopen(path, "r");
     if (!f) return;
     char key[256];
-    int s, u;
-    // one entry per line: "key": [s, u],
+    int s, u, r;
+    // one entry per line: "key": [s, u, rpl],
     char line[512];
-    while (fgets(line, sizeof line, f))
-      if (sscanf(line, " \"%255[^\"]\": [%d, %d]", key, &s, &u) == 3) m[key] = Tile{s, u};
+    while (fgets(line, sizeof line, f)) {
+      const int got = sscanf(line, " \"%255[^\"]\": [%d, %d, %d]", key, &s, &u, &r);
+      if (got >= 3) m[key] = Tile{s, u, got == 4 ? r : 1};
+    }
     fclose(f);
   }
   void save() {
@@ -42,8 +44,8 @@ struct TuneCache {
     fprintf(f, "{\n");
     size_t i = 0;
     for (auto& kv : m)
-      fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.s, kv.second.u,
-              ++i < m.size() ? "," : "");
+      fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.s, kv.second.u,
+              kv.second.rpl, ++i < m.size() ? "," : "");
     fprintf(f, "}\n");
     fclose(f);
   }
@@ -51,32 +53,46 @@ struct TuneCache {
 
 static thread_local int g_force_tile = 0;  // mgk_params.force_tile of the setup in progress
 
+// Whether a kernel exists for tile t on block rows of BR (wide: the product may
+// use the wide-lane BF16 tiles).
 template <int BR>
-static bool tile_known(const Tile& t) {
+static bool tile_known(const Tile& t, bool wide) {
   bool known = false;
-  auto probe = [&](int ss, int uu) { known |= t.s == ss && t.u == uu; };
-#define MGK_PROBE(SS, UU) probe(SS, UU);
+  auto probe = [&](int ss, int uu, int rr) {
+    known |= t.s == ss && t.u == uu && t.rpl == rr;
+  };
+#define MGK_PROBE(SS, UU) probe(SS, UU, 1);
+#define MGK_PROBE_W(SS, UU, RR) probe(SS, UU, RR);
   if (BR == 1) {
     MGK_TILES_1(MGK_PROBE)
   } else {
     MGK_TILES_B(MGK_PROBE)
+    if (wide) {
+      MGK_TILES_W(MGK_PROBE_W)
+    }
   }
 #undef MGK_PROBE
+#undef MGK_PROBE_W
   return known;
 }
 
 template <int BR, int BC, class TV, class TX>
 static Tile autotune(Device& D, const DMat& M, bool trans) {
+  const bool wide = wide_ok<BR, BC, TV>() && !trans;
   if (g_force_tile) {
-    const Tile t{g_force_tile / 100, g_force_tile % 100};
-    if (!tile_known<BR>(t))
+    // 10000*RPL + 100*S + U.  A wide tile (RPL > 1) applies to the products that have
+    // wide kernels; the others take (S, U) when that tile exists for them, else the
+    // autotuner's choice.  Any other unknown tile is an error.
+    const int rpl = g_force_tile / 10000;
+    const Tile t{(g_force_tile / 100) % 100, g_force_tile % 100, wide && rpl > 1 ? rpl : 1};
+    if (tile_known<BR>(t, wide)) return t;
+    if (!(rpl > 1 && !wide))
       throw Error(MGK_E_INVALID, "force_tile " + std::to_string(g_force_tile) +
                                      " is not a kernel tile for block rows of " +
                                      std::to_string(BR));
-    return t;
   }
   const int nrows = trans ? M.nbc : M.nbr, ncols = trans ? M.nbr : M.nbc;
-  if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4} : Tile{1, 4};
+  if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4, 1} : Tile{1, 4, 1};
   char key[200];
   snprintf(key, sizeof key, "b%dx%d_v%d_x%d_t%d_r%d_nnz%lld", BR, BC, (int)sizeof(TV),
            (int)sizeof(TX), (int)trans, nrows, (long long)M.nnzb);
@@ -85,11 +101,21 @@ static Tile autotune(Device& D, const DMat& M, bool trans) {
     std::lock_guard<std::mutex> g(C.mu);
     C.load();
     auto it = C.m.find(key);
-    if (it != C.m.end() && tile_known<BR>(it->second)) return it->second;
+    if (it != C.m.end() && tile_known<BR>(it->second, wide)) return it->second;
   }
   std::vector<Tile> cands;
-  if (BR == 1) cands = {{1, 8}, {2, 4}, {4, 4}, {8, 4}, {16, 2}, {32, 2}};
-  else cands = {{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 4}, {8, 4}, {16, 2}};
+#define MGK_CAND(SS, UU) cands.push_back(Tile{SS, UU, 1});
+#define MGK_CAND_W(SS, UU, RR) cands.push_back(Tile{SS, UU, RR});
+  if (BR == 1) {
+    MGK_TILES_1(MGK_CAND)
+  } else {
+    MGK_TILES_B(MGK_CAND)
+    if (wide) {
+      MGK_TILES_W(MGK_CAND_W)
+    }
+  }
+#undef MGK_CAND
+#undef MGK_CAND_W
   TX *x = nullptr, *y = nullptr;
   HIPCK(hipMalloc(&x, sizeof(TX) * (size_t)ncols * (trans ? BR : BC) + 64));
   HIPCK(hipMalloc(&y, sizeof(TX) * (size_t)nrows * (trans ? BC : BR) + 64));

@@ -274,7 +274,9 @@ def test_results_independent_of_kernel_tile(storage):
     b = dev(S.mms_rhs(n))
     x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
     outs = []
-    for tile in (0, 108, 204, 404, 804, 1602):
+    # 10000*RPL + 100*S + U; the RPL 2 / 4 tiles are the wide BF16 lanes
+    for tile in (0, 108, 202, 204, 402, 404, 804, 1602, 20204, 20402, 20404, 20802, 21602,
+                 40402, 40801, 41601):
         say("tile", storage, tile)
         s = gpu_solver(bsr, hier=storage, coarse_enough=200, force_tile=tile)
         y = torch.empty_like(b)
@@ -287,6 +289,9 @@ def test_results_independent_of_kernel_tile(storage):
         assert np.array_equal(x, outs[0][1]) and it == outs[0][2]
     with pytest.raises(mgk.MgkError):
         gpu_solver(bsr, hier=storage, force_tile=303)
+    if storage == "bf16":
+        with pytest.raises(mgk.MgkError):
+            gpu_solver(bsr, hier=storage, force_tile=30402)   # no 3-row lanes of 4x4 blocks
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
