@@ -320,15 +320,20 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
                                              TA alpha, TA beta) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
+  const bool own = L.active && L.s == 0 && L.i < nbr;
+  const size_t row0 = (size_t)L.i * BR + L.r;
+  // epilogue operands are loaded before the row product so their latency overlaps it
+  TA yv[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) yv[q] = (own && beta != TA(0)) ? (TA)y[row0 + q] : TA(0);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, x, acc);
-  if (L.active && L.s == 0 && L.i < nbr) {
+  if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const size_t row = (size_t)L.i * BR + L.r + q;
       TA out = alpha * acc[q];
-      if (beta != TA(0)) out += beta * (TA)y[row];
-      y[row] = (TY)out;
+      if (beta != TA(0)) out += beta * yv[q];
+      y[row0 + q] = (TY)out;
     }
   }
 }
@@ -370,13 +375,15 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
     L.gbase = g * M::G;
     L.i = base + wave * M::GPW + g;
     const int lim = L.i < rb1 ? nbr : 0;   // rows past this workgroup's range idle
+    const bool own = L.active && L.s == 0 && L.i < rb1;
+    const size_t row = (size_t)L.i * BR + L.r;
+    const double wv = own ? w1[row] : 0.0;   // loaded ahead of the row product
     const double acc = row_product<BR, BC, S, U, TRANS, TV, TX, double>(L, lim, ptr, col, blk,
                                                                         val, x);
-    if (L.active && L.s == 0 && L.i < rb1) {
-      const size_t row = (size_t)L.i * BR + L.r;
+    if (own) {
       y[row] = acc;
       const int q = (L.i - rb0) * BR + L.r;
-      sd1[q] = w1[row] * acc;
+      sd1[q] = wv * acc;
       sd2[q] = acc * acc;
     }
   }
@@ -405,14 +412,16 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
                                                  const TX* __restrict__ z, TX* __restrict__ t) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
+  const bool own = L.active && L.s == 0 && L.i < nbr;
+  const size_t row0 = (size_t)L.i * BR + L.r;
+  TA fv[RPL];   // loaded ahead of the row product
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) fv[q] = own ? (TA)f[row0 + q] : TA(0);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
-  if (L.active && L.s == 0 && L.i < nbr) {
+  if (own) {
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const size_t row = (size_t)L.i * BR + L.r + q;
-      t[row] = (TX)((TA)f[row] - acc[q]);
-    }
+    for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)(fv[q] - acc[q]);
   }
 }
 
@@ -428,31 +437,36 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
                                                const TX* __restrict__ z, TO* __restrict__ zout) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
-  TA acc[RPL];
-  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
-  const bool own = L.active && L.i < nbr;
-  TA res[RPL];
+  const bool own = L.active && L.s == 0 && L.i < nbr;
+  const size_t row0 = (size_t)L.i * BR + L.r;
+  // f, z and the lane's rows of M are loaded ahead of the row product
+  TA fv[RPL], zv[RPL], mv[RPL][BR];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
-    res[q] = 0;
-    if (own && L.s == 0) res[q] = (TA)f[(size_t)L.i * BR + L.r + q] - acc[q];
+    fv[q] = own ? (TA)f[row0 + q] : TA(0);
+    zv[q] = own ? (TA)z[row0 + q] : TA(0);
+    const TM* m = M + (size_t)L.i * BR * BR;
+    const int r = L.r + q;
+#pragma unroll
+    for (int c = 0; c < BR; ++c) mv[q][c] = own ? (TA)(TRANS ? m[c * BR + r] : m[r * BR + c]) : TA(0);
   }
+  TA acc[RPL];
+  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
+  TA res[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) res[q] = own ? fv[q] - acc[q] : TA(0);
   // Gather the BR residuals of the block row from the s == 0 lanes (row c is
   // entry c % RPL of lane c / RPL of the group).
   TA rv[BR];
 #pragma unroll
   for (int c = 0; c < BR; ++c) rv[c] = __shfl(res[c % RPL], L.gbase + c / RPL, WAVE);
-  if (own && L.s == 0) {
-    const TM* m = M + (size_t)L.i * BR * BR;
+  if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const int r = L.r + q;
-      const size_t row = (size_t)L.i * BR + r;
-      TA out = (TA)z[row];
+      TA out = zv[q];
 #pragma unroll
-      for (int c = 0; c < BR; ++c)
-        out = fma_((TA)(TRANS ? m[c * BR + r] : m[r * BR + c]), rv[c], out);
-      zout[row] = (TO)out;
+      for (int c = 0; c < BR; ++c) out = fma_(mv[q][c], rv[c], out);
+      zout[row0 + q] = (TO)out;
     }
   }
 }

@@ -66,12 +66,12 @@ __global__ __launch_bounds__(WG) void k_g_residual(const GItem* __restrict__ ite
     const GItem& g = items[find_item(items, nitems, w)];
     if (!active[g.sys]) continue;
     const LaneInfo L = lane_info<B, S>(w - g.tile0);
+    const bool own = L.active && L.s == 0 && L.i < g.nbr;
+    const size_t row = (size_t)L.i * B + L.r;
+    const TA fv = own ? (TA)((const TF*)g.f)[row] : TA(0);   // ahead of the row product
     TA acc = row_product<B, B, S, U, false, TV, TX, TA>(L, g.nbr, g.ptr, g.col, nullptr,
                                                         (const TV*)g.val, (const TX*)g.in);
-    if (L.active && L.s == 0 && L.i < g.nbr) {
-      const size_t row = (size_t)L.i * B + L.r;
-      ((TX*)g.out)[row] = (TX)((TA)((const TF*)g.f)[row] - acc);
-    }
+    if (own) ((TX*)g.out)[row] = (TX)(fv - acc);
   }
 }
 
@@ -84,20 +84,25 @@ __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items
     if (!active[g.sys]) continue;   // uniform per workgroup: the whole tile skips
     const LaneInfo L = lane_info<B, S>(w - g.tile0);
     const TX* z = (const TX*)g.in;
+    const bool own = L.active && L.s == 0 && L.i < g.nbr;
+    const size_t row = (size_t)L.i * B + L.r;
+    // f, z and the row of M are loaded ahead of the row product
+    const TM* m = (const TM*)g.M + (size_t)L.i * B * B;
+    const TA fv = own ? (TA)((const TF*)g.f)[row] : TA(0);
+    const TA zv = own ? (TA)z[row] : TA(0);
+    TA mv[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) mv[c] = own ? (TA)m[L.r * B + c] : TA(0);
     TA acc = row_product<B, B, S, U, false, TV, TX, TA>(L, g.nbr, g.ptr, g.col, nullptr,
                                                         (const TV*)g.val, z);
-    const bool own = L.active && L.i < g.nbr;
-    TA res = 0;
-    if (own && L.s == 0) res = (TA)((const TF*)g.f)[(size_t)L.i * B + L.r] - acc;
+    const TA res = own ? fv - acc : TA(0);
     TA rv[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) rv[c] = __shfl(res, L.gbase + c, WAVE);
-    if (own && L.s == 0) {
-      const size_t row = (size_t)L.i * B + L.r;
-      const TM* m = (const TM*)g.M + (size_t)L.i * B * B;
-      TA out = (TA)z[row];
+    if (own) {
+      TA out = zv;
 #pragma unroll
-      for (int c = 0; c < B; ++c) out = fma_((TA)m[L.r * B + c], rv[c], out);
+      for (int c = 0; c < B; ++c) out = fma_(mv[c], rv[c], out);
       ((TO*)g.out)[row] = (TO)out;
     }
   }
