@@ -23,7 +23,8 @@ SOURCES = ["csr.cpp", "stokes.cpp", "amg.cpp", "krylov.cpp", "capi.cpp"]
 
 KIND_AMG, KIND_SCHUR, KIND_IDENTITY = 0, 1, 2
 SPAI0_BLOCK, JACOBI, SPAI0_SCALAR = 0, 1, 2
-BICGSTAB, FGMRES = 0, 1
+BICGSTAB, FGMRES, IDRS = 0, 1, 2
+SMOOTHED, PLAIN = 0, 1
 
 
 def build(verbose: bool = False) -> str:
@@ -42,7 +43,10 @@ class _Params(C.Structure):
     _fields_ = [("krylov", C.c_int32), ("fgmres_m", C.c_int32), ("maxiter", C.c_int32),
                 ("max_restarts", C.c_int32), ("eps_strong", C.c_double),
                 ("coarse_enough", C.c_int32), ("max_levels", C.c_int32),
-                ("smoother", C.c_int32), ("kind", C.c_int32), ("jacobi_omega", C.c_double)]
+                ("smoother", C.c_int32), ("kind", C.c_int32), ("jacobi_omega", C.c_double),
+                ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
+                ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -76,6 +80,8 @@ def lib():
         L.orc_level_smoother.argtypes = [P, C.c_int, C.c_int, P]
         L.orc_precond.argtypes = [P, P, P, C.c_int]
         L.orc_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(_Info)]
+        L.orc_idr_shadow.argtypes = [C.c_int64, C.c_int, P]
+        L.orc_idr_shadow.restype = None
         L.orc_gather_block_row.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int64, P, P,
                                            C.c_int32]
         _lib = L
@@ -114,6 +120,13 @@ def theta_gradient(n: int, lam: np.ndarray, x: np.ndarray) -> np.ndarray:
     return g
 
 
+def idr_shadow(n: int, s: int) -> np.ndarray:
+    """The n x s IDR(s) shadow space (columns orthonormal), as an (n, s) array."""
+    out = np.zeros(n * s, np.float64)
+    lib().orc_idr_shadow(n, s, _p(out))
+    return out.reshape(s, n).T.copy()
+
+
 def gather_block_row(A: sp.csr_matrix, b: int, i: int):
     """Block columns and dense b x b blocks of node row i (the oracle's node view)."""
     ptr = np.ascontiguousarray(A.indptr, np.int64)
@@ -145,14 +158,17 @@ class Solver:
                  krylov: int = BICGSTAB, smoother: int = SPAI0_BLOCK,
                  eps_strong: float = 0.08, coarse_enough: int = 3000, max_levels: int = 20,
                  maxiter: int = 1000, fgmres_m: int = 30, max_restarts: int = 5,
-                 jacobi_omega: float = 2.0 / 3.0):
+                 jacobi_omega: float = 2.0 / 3.0, coarsening: int = SMOOTHED,
+                 schur_approx: int = 0, schur_spai0: int = 0, schur_lower: int = 0,
+                 idr_s: int = 5):
         A = sp.csr_matrix(A)
         A.sort_indices()
         self.n = A.shape[0]
         self._keep = (np.ascontiguousarray(A.indptr, np.int64),
                       np.ascontiguousarray(A.indices, np.int32), _f64(A.data))
         self.prm = _Params(krylov, fgmres_m, maxiter, max_restarts, eps_strong, coarse_enough,
-                           max_levels, smoother, kind, jacobi_omega)
+                           max_levels, smoother, kind, jacobi_omega, coarsening, schur_approx,
+                           schur_spai0, schur_lower, idr_s, 0)
         self.block = block
         L = lib()
         h = L.orc_setup(self.n, *(_p(a) for a in self._keep), block, C.byref(self.prm))

@@ -175,8 +175,9 @@ bool build_smoother(const Csr& A, int b, const AmgParams& prm, std::vector<doubl
   return true;
 }
 
-// One coarsening step: aggregates, P, R and the Galerkin operator.
-bool coarsen(Level& L, int b, double eps, Csr& Ac, const char** msg) {
+// One coarsening step: aggregates, P, R and the Galerkin operator.  With
+// smooth_p false the prolongator is the tentative one (plain aggregation).
+bool coarsen(Level& L, int b, double eps, bool smooth_p, Csr& Ac, const char** msg) {
   const Csr& A = L.A;
   const i64 nn = A.nr / b;
   Strength st = strength(A, b, eps);
@@ -197,6 +198,14 @@ bool coarsen(Level& L, int b, double eps, Csr& Ac, const char** msg) {
       }
       Pt.ptr[i * b + r + 1] = (i64)Pt.col.size();
     }
+  if (!smooth_p) {
+    L.omega = 0.0;
+    L.P = Pt;
+    L.R = transpose(L.P);
+    Csr AP = spgemm(A, L.P);
+    Ac = spgemm(L.R, AP);
+    return true;
+  }
 
   // Filtered matrix: strong blocks kept, weak blocks added to the diagonal
   // block (starting from A_ii, weak blocks in ascending column order).
@@ -296,7 +305,7 @@ bool amg_build(const Csr& A, int b, const AmgParams& prm, Hierarchy& H, const ch
     Csr Ac;
     if (!last) {
       *msg = nullptr;
-      if (!coarsen(L, b, eps, Ac, msg)) {
+      if (!coarsen(L, b, eps, prm.smooth_p, Ac, msg)) {
         if (*msg) return false;
         last = true;
         L.P = Csr();

@@ -51,6 +51,12 @@ struct orc_params {
   int32_t smoother;      // 0 block SPAI0, 1 damped Jacobi, 2 scalar SPAI0
   int32_t kind;          // 0 monolithic AMG, 1 Schur pressure correction, 2 identity
   double jacobi_omega;
+  int32_t coarsening;    // 0 smoothed aggregation, 1 plain aggregation
+  int32_t schur_approx;  // 1: diagonal-only Schur approximation
+  int32_t schur_spai0;   // 1: SPAI(0) pressure step
+  int32_t schur_lower;   // 1: lower block factorization
+  int32_t idr_s;         // shadow space dimension of IDR(s)
+  int32_t pad;
 };
 
 struct orc_info {
@@ -106,6 +112,11 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
     s->aprm.max_levels = prm->max_levels;
     s->aprm.smoother = prm->smoother;
     s->aprm.jacobi_omega = prm->jacobi_omega;
+    s->aprm.smooth_p = prm->coarsening == 0;
+    if (prm->krylov == 2 && (prm->idr_s < 1 || prm->idr_s > 32)) {
+      g_err = "oracle: IDR(s) needs 1 <= s <= 32";
+      return nullptr;
+    }
     const char* msg = nullptr;
     if (prm->kind == 0) {
       if (!amg_build(s->A, block, s->aprm, s->H, &msg)) {
@@ -117,7 +128,11 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
         g_err = "oracle: Schur needs interleaved 4-component unknowns";
         return nullptr;
       }
-      if (!schur_build(s->A, s->aprm, s->S, &msg)) {
+      SchurOptions so;
+      so.diag_approx = prm->schur_approx != 0;
+      so.spai0_p = prm->schur_spai0 != 0;
+      so.lower = prm->schur_lower != 0;
+      if (!schur_build(s->A, s->aprm, so, s->S, &msg)) {
         g_err = msg ? msg : "oracle: Schur setup failed";
         return nullptr;
       }
@@ -133,7 +148,8 @@ void orc_free(orc_solver* s) { delete s; }
 
 static const Hierarchy* pick(orc_solver* s, int which) {
   if (s->prm.kind == 0) return which == 0 ? &s->H : (which == 2 && s->have_t ? &s->Ht : nullptr);
-  if (s->prm.kind == 1) return which == 0 ? &s->S.Hu : (which == 1 ? &s->S.Hp : nullptr);
+  if (s->prm.kind == 1)
+    return which == 0 ? &s->S.Hu : (which == 1 && !s->S.Hp.levels.empty() ? &s->S.Hp : nullptr);
   return nullptr;
 }
 
@@ -227,8 +243,10 @@ int orc_solve(orc_solver* s, const double* b, double* x, double tol, int transpo
   SolveInfo si;
   if (s->prm.krylov == 0)
     bicgstab(*A, *M, b, x, tol, s->prm.maxiter, s->prm.max_restarts, si);
-  else
+  else if (s->prm.krylov == 1)
     fgmres(*A, *M, b, x, tol, s->prm.fgmres_m, s->prm.maxiter, si);
+  else
+    idrs(*A, *M, b, x, tol, s->prm.idr_s, s->prm.maxiter, s->prm.max_restarts, si);
   info->iters = si.iters;
   info->restarts = si.restarts;
   info->converged = si.converged;
@@ -237,6 +255,11 @@ int orc_solve(orc_solver* s, const double* b, double* x, double tol, int transpo
 }
 
 }  // extern "C"
+
+extern "C" void orc_idr_shadow(int64_t n, int s, double* out) {
+  const std::vector<double> P = idr_shadow(n, s);
+  std::copy(P.begin(), P.end(), out);
+}
 
 extern "C" int orc_gather_block_row(int64_t nr, const int64_t* ptr, const int32_t* col,
                                     const double* val, int b, int64_t i, int32_t* cols,

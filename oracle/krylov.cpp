@@ -162,9 +162,152 @@ void fgmres(const Csr& A, const Precond& M, const double* b, double* x,
   }
 }
 
-bool schur_build(const Csr& A, const AmgParams& prm, Schur& S, const char** msg) {
+// ---- IDR(s) -------------------------------------------------------------------
+//
+// Induced dimension reduction (Sonneveld and van Gijzen), in the variant whose
+// residual updates are kept biorthogonal to the shadow space (van Gijzen and
+// Sonneveld, ACM TOMS 38, 2011), with right preconditioning: every new search
+// direction U_k is a preconditioned vector and G_k = A U_k.  The paper uses
+// IDR(5) as its outer solver (Section 4, Table of solver variants).  The step
+// length omega of the dimension-reduction step is the minimal-residual one,
+// enlarged when the angle between t and r is small (|cos| < 0.7).
+
+static double splitmix_unit(uint64_t c) {
+  // SplitMix64 (Steele, Lea and Flood, 2014): output number c of the sequence
+  // started from state 0, top 53 bits mapped to [-1, 1).
+  uint64_t z = (c + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+std::vector<double> idr_shadow(i64 n, int s) {
+  std::vector<double> P((size_t)n * s);
+  for (int j = 0; j < s; ++j)
+    for (i64 i = 0; i < n; ++i) P[(size_t)j * n + i] = splitmix_unit((uint64_t)j * n + i);
+  for (int j = 0; j < s; ++j) {
+    double* pj = &P[(size_t)j * n];
+    for (int i = 0; i < j; ++i) {
+      const double* pi = &P[(size_t)i * n];
+      const double d = dot(n, pi, pj);
+      for (i64 q = 0; q < n; ++q) pj[q] = pj[q] - d * pi[q];
+    }
+    const double nr = nrm2(n, pj);
+    for (i64 q = 0; q < n; ++q) pj[q] = pj[q] / nr;
+  }
+  return P;
+}
+
+void idrs(const Csr& A, const Precond& K, const double* b, double* x, double tol, int s,
+          int maxiter, int max_restarts, SolveInfo& info) {
+  const i64 n = A.nr;
+  info = SolveInfo();
+  const double nb = nrm2(n, b);
+  if (nb == 0.0) {
+    for (i64 i = 0; i < n; ++i) x[i] = 0.0;
+    info.converged = 1;
+    return;
+  }
+  const std::vector<double> P = idr_shadow(n, s);
+  auto col = [n](std::vector<double>& V, int j) { return &V[(size_t)j * n]; };
+  auto pcol = [&](int j) { return &P[(size_t)j * n]; };
+  std::vector<double> r(n), v(n), vh(n), t(n), G((size_t)n * s), U((size_t)n * s);
+  std::vector<double> Mm((size_t)s * s), f(s), c(s);
+  int it = 0;
+  for (int restart = 0;; ++restart) {
+    residual(A, b, x, r.data());
+    std::fill(G.begin(), G.end(), 0.0);
+    std::fill(U.begin(), U.end(), 0.0);
+    std::fill(Mm.begin(), Mm.end(), 0.0);
+    for (int i = 0; i < s; ++i) Mm[(size_t)i * s + i] = 1.0;
+    double om = 1.0;
+    double normr = nrm2(n, r.data());
+    bool conv = normr / nb <= tol, breakdown = false;
+    while (!conv && !breakdown && it < maxiter) {
+      for (int i = 0; i < s; ++i) f[i] = dot(n, pcol(i), r.data());
+      for (int k = 0; k < s && !conv && it < maxiter; ++k) {
+        // lower triangular M(k:s, k:s) c = f(k:s)
+        for (int i = k; i < s; ++i) {
+          double a = f[i];
+          for (int j = k; j < i; ++j) a = a - Mm[(size_t)i * s + j] * c[j];
+          c[i] = a / Mm[(size_t)i * s + i];
+        }
+        for (i64 q = 0; q < n; ++q) v[q] = r[q];
+        for (int i = k; i < s; ++i)
+          for (i64 q = 0; q < n; ++q) v[q] = v[q] - c[i] * col(G, i)[q];
+        K.apply(v.data(), vh.data());
+        double* Uk = col(U, k);
+        double* Gk = col(G, k);
+        std::vector<double> un(n);
+        for (i64 q = 0; q < n; ++q) un[q] = om * vh[q];
+        for (int i = k; i < s; ++i)
+          for (i64 q = 0; q < n; ++q) un[q] = un[q] + c[i] * col(U, i)[q];
+        std::copy(un.begin(), un.end(), Uk);
+        spmv(A, Uk, Gk);
+        // make G_k orthogonal to the first k shadow vectors
+        for (int i = 0; i < k; ++i) {
+          const double alpha = dot(n, pcol(i), Gk) / Mm[(size_t)i * s + i];
+          for (i64 q = 0; q < n; ++q) {
+            Gk[q] = Gk[q] - alpha * col(G, i)[q];
+            Uk[q] = Uk[q] - alpha * col(U, i)[q];
+          }
+        }
+        for (int i = k; i < s; ++i) Mm[(size_t)i * s + k] = dot(n, pcol(i), Gk);
+        if (Mm[(size_t)k * s + k] == 0.0) {
+          breakdown = true;
+          break;
+        }
+        const double beta = f[k] / Mm[(size_t)k * s + k];
+        for (i64 q = 0; q < n; ++q) {
+          r[q] = r[q] - beta * Gk[q];
+          x[q] = x[q] + beta * Uk[q];
+        }
+        ++it;
+        normr = nrm2(n, r.data());
+        if (normr / nb <= tol) {
+          conv = true;
+          break;
+        }
+        for (int i = k + 1; i < s; ++i) f[i] = f[i] - beta * Mm[(size_t)i * s + k];
+      }
+      if (conv || breakdown || it >= maxiter) break;
+      // dimension reduction step
+      K.apply(r.data(), vh.data());
+      spmv(A, vh.data(), t.data());
+      const double tt = dot(n, t.data(), t.data()), tr = dot(n, t.data(), r.data());
+      const double rho = std::fabs(tr) / (std::sqrt(tt) * normr);
+      if (tt == 0.0 || rho == 0.0) {
+        breakdown = true;
+        break;
+      }
+      om = tr / tt;
+      if (rho < 0.7) om = om * 0.7 / rho;
+      for (i64 q = 0; q < n; ++q) {
+        r[q] = r[q] - om * t[q];
+        x[q] = x[q] + om * vh[q];
+      }
+      ++it;
+      normr = nrm2(n, r.data());
+      conv = normr / nb <= tol;
+    }
+    residual(A, b, x, r.data());
+    info.rel_resid = nrm2(n, r.data()) / nb;
+    info.iters = it;
+    info.restarts = restart;
+    if (info.rel_resid <= tol) {
+      info.converged = 1;
+      return;
+    }
+    if (restart >= max_restarts || it >= maxiter) return;
+  }
+}
+
+bool schur_build(const Csr& A, const AmgParams& prm, const SchurOptions& opt, Schur& S,
+                 const char** msg) {
   const i64 nn = A.nr / 4;
   S.nn = nn;
+  S.opt = opt;
   auto init = [](Csr& M, i64 nr, i64 nc) {
     M = Csr();
     M.nr = nr;
@@ -200,6 +343,20 @@ bool schur_build(const Csr& A, const AmgParams& prm, Schur& S, const char** msg)
   Csr W = S.Blo;
   for (i64 k = 0; k < (i64)W.val.size(); ++k) W.val[k] = W.val[k] * dinv[W.col[k]];
   Csr SP = spgemm(W, S.Bup);
+  if (opt.diag_approx) {
+    // eq. SchurApprox: only the diagonal of Blo diag(Auu)^-1 Bup is subtracted
+    Csr D;
+    init(D, nn, nn);
+    for (i64 r = 0; r < nn; ++r) {
+      for (i64 k = SP.ptr[r]; k < SP.ptr[r + 1]; ++k)
+        if (SP.col[k] == r) {
+          D.col.push_back((i32)r);
+          D.val.push_back(SP.val[k]);
+        }
+      D.ptr[r + 1] = (i64)D.col.size();
+    }
+    SP = D;
+  }
   init(S.S, nn, nn);
   for (i64 r = 0; r < nn; ++r) {
     i64 a = S.C.ptr[r], ae = S.C.ptr[r + 1], p = SP.ptr[r], pe = SP.ptr[r + 1];
@@ -219,11 +376,30 @@ bool schur_build(const Csr& A, const AmgParams& prm, Schur& S, const char** msg)
     S.S.ptr[r + 1] = (i64)S.S.col.size();
   }
   if (!amg_build(S.Auu, 3, prm, S.Hu, msg)) return false;
+  if (opt.spai0_p) {
+    // scalar SPAI(0): m_i = s_ii / sum_j s_ij^2 (the b = 1 case of the block formula)
+    S.Sm.assign(nn, 0.0);
+    for (i64 r = 0; r < nn; ++r) {
+      double d = 0.0, q = 0.0;
+      for (i64 k = S.S.ptr[r]; k < S.S.ptr[r + 1]; ++k) {
+        q = q + S.S.val[k] * S.S.val[k];
+        if (S.S.col[k] == r) d = S.S.val[k];
+      }
+      if (!(q > 0.0)) {
+        *msg = "oracle: empty Schur complement row";
+        return false;
+      }
+      S.Sm[r] = d / q;
+    }
+    return true;
+  }
   if (!amg_build(S.S, 1, prm, S.Hp, msg)) return false;
   return true;
 }
 
-// z_u = V_u(r_u); z_p = V_S(r_p - B_lo z_u); z_u = V_u(r_u - B_up z_p).
+// z_u = V_u(r_u); z_p = V_S(r_p - B_lo z_u); z_u = V_u(r_u - B_up z_p) (eqs. SchurP,
+// SchurU).  The lower factorization stops after z_p; with spai0_p the pressure step
+// is z_p = m .* (r_p - B_lo z_u).
 void schur_apply(const Schur& S, const double* r, double* z) {
   const i64 nn = S.nn;
   std::vector<double> ru(3 * nn), rp(nn), zu(3 * nn), zp(nn), tu(3 * nn), tp(nn);
@@ -234,10 +410,16 @@ void schur_apply(const Schur& S, const double* r, double* z) {
   vcycle(S.Hu, 0, ru.data(), zu.data());
   spmv(S.Blo, zu.data(), tp.data());
   for (i64 g = 0; g < nn; ++g) tp[g] = rp[g] - tp[g];
-  vcycle(S.Hp, 0, tp.data(), zp.data());
-  spmv(S.Bup, zp.data(), tu.data());
-  for (i64 q = 0; q < 3 * nn; ++q) tu[q] = ru[q] - tu[q];
-  vcycle(S.Hu, 0, tu.data(), zu.data());
+  if (S.opt.spai0_p) {
+    for (i64 g = 0; g < nn; ++g) zp[g] = S.Sm[g] * tp[g];
+  } else {
+    vcycle(S.Hp, 0, tp.data(), zp.data());
+  }
+  if (!S.opt.lower) {
+    spmv(S.Bup, zp.data(), tu.data());
+    for (i64 q = 0; q < 3 * nn; ++q) tu[q] = ru[q] - tu[q];
+    vcycle(S.Hu, 0, tu.data(), zu.data());
+  }
   for (i64 g = 0; g < nn; ++g) {
     for (int c = 0; c < 3; ++c) z[4 * g + c] = zu[3 * g + c];
     z[4 * g + 3] = zp[g];

@@ -11,6 +11,14 @@
 // gathered from the b consecutive scalar rows of that node.  Arithmetic is
 // FP64, compiled with -ffp-contract=off, and every sum runs in the ascending
 // order stated at its definition.
+//
+// Pins (tests/test_oracle_pins.py) cover every function below, including the
+// plain-aggregation prolongator (hand-derived 1D case, block invariants,
+// Galerkin product), the diagonal Schur approximation and its SPAI(0) pressure
+// step (derived from the pinned full approximation; least-squares optimality),
+// the lower block factorization (dense algebra), and IDR(s) (SplitMix64's
+// published outputs for the shadow space, the m + m/s termination bound, dense
+// LU).
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -69,6 +77,7 @@ struct AmgParams {
   int max_levels = 20;
   int smoother = SPAI0_BLOCK;
   double jacobi_omega = 2.0 / 3.0;
+  bool smooth_p = true;       // false: plain aggregation, P = P_tent
 };
 
 struct Level {
@@ -110,14 +119,29 @@ void bicgstab(const Csr& A, const Precond& M, const double* b, double* x,
               double tol, int maxiter, int max_restarts, SolveInfo& info);
 void fgmres(const Csr& A, const Precond& M, const double* b, double* x,
             double tol, int m, int maxiter, SolveInfo& info);
+// IDR(s) with biorthogonal residuals, right preconditioned; iters counts products
+// with A.  The shadow space is idr_shadow(n, s).
+void idrs(const Csr& A, const Precond& M, const double* b, double* x, double tol, int s,
+          int maxiter, int max_restarts, SolveInfo& info);
+// n x s shadow space, column-major: entry (i, j) from SplitMix64 at counter j*n + i
+// mapped to [-1, 1), columns orthonormalized by modified Gram-Schmidt.
+std::vector<double> idr_shadow(i64 n, int s);
 
 // Schur-complement pressure correction for interleaved [u,v,w,p] unknowns.
+struct SchurOptions {
+  bool diag_approx = false;   // S = C - diag(Blo diag(Auu)^-1 Bup)   (eq. SchurApprox)
+  bool spai0_p = false;       // pressure step: one SPAI(0) application instead of a V-cycle
+  bool lower = false;         // lower block factorization: no second velocity cycle
+};
 struct Schur {
-  Csr Auu, Bup, Blo, C, S;    // S = C - Blo diag(Auu)^-1 Bup
+  Csr Auu, Bup, Blo, C, S;    // S = C - Blo diag(Auu)^-1 Bup, or its diagonal-only form
   Hierarchy Hu, Hp;
+  std::vector<double> Sm;     // scalar SPAI(0) of S (spai0_p)
+  SchurOptions opt;
   i64 nn = 0;                 // nodes
 };
-bool schur_build(const Csr& A, const AmgParams& prm, Schur& S, const char** msg);
+bool schur_build(const Csr& A, const AmgParams& prm, const SchurOptions& opt, Schur& S,
+                 const char** msg);
 void schur_apply(const Schur& S, const double* r, double* z);
 
 }  // namespace orc

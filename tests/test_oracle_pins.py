@@ -246,6 +246,44 @@ def test_prolongator_1d_hand_derived():
     assert np.allclose(P[3:9].sum(axis=1), 1.0)
 
 
+def test_plain_aggregation_1d_hand_derived():
+    """Plain aggregation: P is the tentative prolongator (one unit entry per aggregated
+    node, omega 0), and for the 1D Laplacian each aggregate sums to the coarse stencil
+    (-1, 2, -1): an aggregate of m nodes has 2m - 2(m - 1) = 2 on the diagonal."""
+    s = oracle.Solver(chain(11), 1, coarse_enough=1, max_levels=2, coarsening=oracle.PLAIN)
+    L0 = s.level(0)
+    assert list(L0["agg"]) == [-1, 0, 0, 1, 1, 1, 2, 2, 2, 2, -1]
+    assert L0["omega"] == 0.0
+    P = dense(L0["P"])
+    expect = np.zeros((11, 3))
+    for i, a in enumerate(L0["agg"]):
+        if a >= 0:
+            expect[i, a] = 1.0
+    assert np.array_equal(P, expect)
+    Ac = dense(s.level(1)["A"])
+    assert np.array_equal(Ac, np.array([[2.0, -1, 0], [-1, 2, -1], [0, -1, 2]]))
+
+
+def test_plain_aggregation_3d_invariants():
+    """Block plain aggregation: every stored block of P is the identity, each aggregated
+    node has exactly one, R = P^T, and A_{l+1} = R A_l P against a dense triple product."""
+    n = 8
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 7))
+    s = oracle.Solver(A, 4, coarse_enough=40, coarsening=oracle.PLAIN)
+    assert s.nlevels() >= 3
+    for l in range(s.nlevels() - 1):
+        L, Lc = s.level(l), s.level(l + 1)
+        P, R, Al = dense(L["P"]), dense(L["R"]), dense(L["A"])
+        agg = L["agg"]
+        expect = np.zeros_like(P)
+        for i, a in enumerate(agg):
+            if a >= 0:
+                expect[4 * i:4 * i + 4, 4 * a:4 * a + 4] = np.eye(4)
+        assert np.array_equal(P, expect) and np.array_equal(R, P.T)
+        Ac = R @ Al @ P
+        assert np.abs(dense(Lc["A"]) - Ac).max() <= 1e-13 * np.abs(Al).max() * 10
+
+
 @pytest.fixture(scope="module")
 def small_hierarchy():
     n = 8
@@ -405,7 +443,7 @@ def test_single_level_is_exact():
 # ---------------------------------------------------------------- Krylov
 
 @pytest.mark.parametrize("n", [4, 5, 6])
-@pytest.mark.parametrize("krylov", [oracle.BICGSTAB, oracle.FGMRES])
+@pytest.mark.parametrize("krylov", [oracle.BICGSTAB, oracle.FGMRES, oracle.IDRS])
 def test_solver_against_dense_lu(n, krylov):
     A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, n))
     xs = S.mms_solution(n)
@@ -427,6 +465,31 @@ def test_fgmres_terminates_in_n_steps():
     x, info = s.solve(b, 1e-13)
     assert info["iters"] <= m and info["converged"]
     assert np.allclose(x, np.linalg.solve(A.toarray(), b), rtol=1e-11)
+
+
+def test_idr_shadow_space_is_splitmix64_orthonormalized():
+    """Column 0 of the shadow space is the normalized SplitMix64 sequence from state 0
+    (published first outputs below) mapped to [-1, 1); columns are orthonormal."""
+    first = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    raw = np.array([(v >> 11) * 2.0 ** -53 * 2.0 - 1.0 for v in first])
+    n, s = 50, 5
+    P = oracle.idr_shadow(n, s)
+    assert np.allclose(P[:4, 0] / P[0, 0], raw / raw[0], rtol=1e-13)
+    assert np.abs(P.T @ P - np.eye(s)).max() <= 1e-14
+
+
+@pytest.mark.parametrize("m,s", [(40, 4), (60, 2), (30, 1), (48, 6)])
+def test_idrs_terminates_within_m_plus_m_over_s(m, s):
+    """IDR(s) finds the solution of an m x m system in at most m + m/s products with A
+    (exact arithmetic); nonsymmetric test matrices with spread spectrum."""
+    rng = np.random.default_rng(3 + m + s)
+    A = np.diag(np.linspace(1, 20, m)) + 0.5 * rng.normal(size=(m, m)) / np.sqrt(m)
+    b = rng.normal(size=m)
+    so = oracle.Solver(sp.csr_matrix(A), 1, kind=oracle.KIND_IDENTITY, krylov=oracle.IDRS,
+                       idr_s=s, max_restarts=0)
+    x, info = so.solve(b, 1e-10)
+    assert info["converged"] and info["iters"] <= m + m // s
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8)
 
 
 def test_bicgstab_edge_cases():
@@ -476,6 +539,58 @@ def test_schur_apply_is_block_factorization():
     r = np.random.default_rng(6).normal(size=4 * nn)
     zp = np.linalg.solve(Sh, r[p] - Blo @ np.linalg.solve(Auu, r[u]))
     zu = np.linalg.solve(Auu, r[u] - Bup @ zp)
+    z = s.precond(r)
+    assert np.allclose(z[u], zu, rtol=1e-9, atol=1e-12)
+    assert np.allclose(z[p], zp, rtol=1e-9, atol=1e-12)
+
+
+def test_schur_diagonal_approximation_and_spai0_pressure():
+    """eq. SchurApprox: S_diag = C - diag(B_lo diag(A_uu)^-1 B_up) keeps C off the diagonal
+    and has the diagonal of the full approximation (itself pinned above).  The SPAI(0)
+    pressure step m .* r_p (lower factorization, r_u = 0) minimizes ||I - diag(m) S_diag||_F."""
+    n = 5
+    A = oracle.stokes_matrix(n, S.theta_field(n, 1.0, 9))
+    D = dense(A)
+    nn = n ** 3
+    p = 4 * np.arange(nn) + 3
+    Cc = D[np.ix_(p, p)]
+    full = dense(oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, coarse_enough=10 ** 6)
+                 .level(0, which=1)["A"])
+    sd = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, coarse_enough=10 ** 6, schur_approx=1)
+    Sd = dense(sd.level(0, which=1)["A"])
+    off = ~np.eye(nn, dtype=bool)
+    assert np.array_equal(Sd[off], Cc[off])
+    assert np.allclose(np.diag(Sd), np.diag(full), rtol=1e-15, atol=0)
+    sp0 = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, coarse_enough=10 ** 6, schur_approx=1,
+                        schur_spai0=1, schur_lower=1)
+    r = np.zeros(4 * nn)
+    r[p] = 1.0
+    z = sp0.precond(r)
+    m = z[p]
+    assert not np.any(np.delete(z, p))
+    base = np.linalg.norm(np.eye(nn) - np.diag(m) @ Sd)
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        assert np.linalg.norm(np.eye(nn) - np.diag(m + 1e-4 * rng.normal(size=nn)) @ Sd) >= base
+    # normal equations of each row's least-squares problem
+    assert np.allclose(((np.eye(nn) - np.diag(m) @ Sd) * Sd).sum(axis=1), 0, atol=1e-12)
+
+
+def test_schur_lower_is_block_lower_factorization():
+    """Lower factorization with exact inner solves: z_u = A_uu^-1 r_u,
+    z_p = S^-1 (r_p - B_lo z_u); no second velocity solve."""
+    n = 5
+    A = oracle.stokes_matrix(n, S.theta_field(n, 1.0, 9))
+    s = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, coarse_enough=10 ** 6, schur_lower=1)
+    D = dense(A)
+    nn = n ** 3
+    u = np.array([4 * g + c for g in range(nn) for c in range(3)])
+    p = 4 * np.arange(nn) + 3
+    Auu, Bup, Blo, Cc = D[np.ix_(u, u)], D[np.ix_(u, p)], D[np.ix_(p, u)], D[np.ix_(p, p)]
+    Sh = Cc - Blo @ np.diag(1 / np.diag(Auu)) @ Bup
+    r = np.random.default_rng(6).normal(size=4 * nn)
+    zu = np.linalg.solve(Auu, r[u])
+    zp = np.linalg.solve(Sh, r[p] - Blo @ zu)
     z = s.precond(r)
     assert np.allclose(z[u], zu, rtol=1e-9, atol=1e-12)
     assert np.allclose(z[p], zp, rtol=1e-9, atol=1e-12)
