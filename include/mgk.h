@@ -61,7 +61,15 @@ typedef enum { MGK_AMG_SPAI0 = 0, MGK_AMG_JACOBI = 1, MGK_SCHUR = 2 } mgk_precon
  * the outer Krylov iteration and the coarsest dense solve stay FP64. */
 typedef enum { MGK_F64 = 0, MGK_F32 = 1, MGK_BF16 = 2 } mgk_storage;
 
-typedef enum { MGK_BICGSTAB = 0, MGK_FGMRES = 1 } mgk_krylov;
+/* Outer Krylov method: BiCGStab, flexible GMRES(m), or IDR(s) with biorthogonal
+ * residual updates (the paper's outer solver, IDR(5); Section 4 and the table of
+ * solver variants), all right preconditioned with FP64 vectors and scalars. */
+typedef enum { MGK_BICGSTAB = 0, MGK_FGMRES = 1, MGK_IDRS = 2 } mgk_krylov;
+
+/* AMG coarsening: smoothed aggregation, P = (I - omega D^-1 A_F) P_tent (Section
+ * 2.1 composition listing), or plain aggregation, P = P_tent (the coarsening of the
+ * paper's Schur-complement velocity solvers, Section 4 listings V2-V4). */
+typedef enum { MGK_SMOOTHED_AGGREGATION = 0, MGK_PLAIN_AGGREGATION = 1 } mgk_coarsening;
 
 typedef struct {
   int32_t n_brows;        /* block rows (= block columns) */
@@ -96,6 +104,18 @@ typedef struct {
                               operators then take (S, U) if that tile exists for them, else
                               the autotuner's tile.  An unknown tile is MGK_E_INVALID.
                               Results are bitwise the same for every tile. */
+  int32_t coarsening;      /* mgk_coarsening, default MGK_SMOOTHED_AGGREGATION */
+  int32_t schur_approx;    /* MGK_SCHUR pressure operator: 0 (default) S = C - B_lo
+                              diag(A_uu)^-1 B_up assembled; 1 S = C - diag(B_lo
+                              diag(A_uu)^-1 B_up) (eq. SchurApprox) */
+  int32_t schur_spai0;     /* MGK_SCHUR pressure step: 0 (default) one AMG V-cycle on S;
+                              1 one application of the scalar SPAI(0) of S (the paper's
+                              pressure preconditioner, Section 4) */
+  int32_t schur_lower;     /* MGK_SCHUR factorization: 0 (default) full, eqs. SchurP and
+                              SchurU (two velocity cycles); 1 lower block factorization
+                              (one velocity cycle, the PETSc LOWER variant of Section 4) */
+  int32_t idr_s;           /* shadow space dimension of MGK_IDRS, 1..16, default 5 */
+  int32_t reserved;
 } mgk_params;
 
 typedef struct {

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libmgk.so")
 MGK_OK, MGK_NOT_CONVERGED = 0, 1
 AMG_SPAI0, AMG_JACOBI, SCHUR = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
-BICGSTAB, FGMRES = 0, 1
+BICGSTAB, FGMRES, IDRS = 0, 1, 2
+SMOOTHED_AGGREGATION, PLAIN_AGGREGATION = 0, 1
 STORAGE = {"f64": F64, "f32": F32, "bf16": BF16}
 
 
@@ -40,7 +41,10 @@ class Params(C.Structure):
                 ("max_levels", C.c_int32), ("block_spai0", C.c_int32),
                 ("eps_strong", C.c_double), ("jacobi_omega", C.c_double),
                 ("keep_host", C.c_int32), ("enable_transpose", C.c_int32),
-                ("time_spmv", C.c_int32), ("force_tile", C.c_int32)]
+                ("time_spmv", C.c_int32), ("force_tile", C.c_int32),
+                ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
+                ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HOST_SOURCES = ["setup.cpp", "ingest.cpp"]
-HIP_SOURCES = ["solver.hip", "multi.hip", "batch.hip"]
+HIP_SOURCES = ["solver.hip", "multi.hip", "batch.hip", "idrs.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              # no automatic FMA contraction: kernels write their FMAs explicitly, so
              # results do not depend on how a kernel instantiation was scheduled

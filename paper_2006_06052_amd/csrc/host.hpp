@@ -32,6 +32,7 @@ struct SetupParams {
   int max_levels = 20;
   int smoother = SM_SPAI0_BLOCK;
   double jacobi_omega = 2.0 / 3.0;
+  bool smooth_p = true;          // false: plain aggregation, P = P_tent
 };
 
 struct HLevel {
@@ -58,11 +59,14 @@ bool dense_inverse(int n, std::vector<double>& a, std::vector<double>& inv);
 
 // Interleaved [u,v,w,p] 4x4 BSR split into A_uu (3x3), B_up (3x1), B_lo (1x3)
 // and C (1x1); sub-blocks that are entirely zero are not stored.  S is the
-// pressure operator C - B_lo diag(A_uu)^-1 B_up.
+// pressure operator C - B_lo diag(A_uu)^-1 B_up, or with diag_only the
+// approximation C - diag(B_lo diag(A_uu)^-1 B_up) (eq. SchurApprox).
 struct SchurParts {
   HBsr Auu, Bup, Blo, C, S;
 };
-int schur_split(const HBsr& A, SchurParts& out, std::string& err);
+int schur_split(const HBsr& A, bool diag_only, SchurParts& out, std::string& err);
+// Scalar SPAI(0) of a 1x1-block matrix: m_i = a_ii / sum_j a_ij^2 (ascending j).
+int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err);
 
 // Ingest helpers.
 int csr_to_bsr(int32_t nrows, const int32_t* ptr, const int32_t* col, const double* val,

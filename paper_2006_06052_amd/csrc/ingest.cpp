@@ -177,7 +177,7 @@ void stokes_assemble(int n, const double* theta, int32_t* ptr, int32_t* col, dou
 // The scalar structure of the split is the set of nonzero entries: stored
 // sub-blocks that are entirely zero are dropped, and zero entries inside the
 // 1x3 and 3x1 coupling blocks take no part in the product that forms S.
-int schur_split(const HBsr& A, SchurParts& S, std::string& err) {
+int schur_split(const HBsr& A, bool diag_only, SchurParts& S, std::string& err) {
   if (A.br != 4 || A.bc != 4) {
     err = "Schur split needs 4x4 blocks with interleaved [u,v,w,p]";
     return -1;
@@ -272,6 +272,7 @@ int schur_split(const HBsr& A, SchurParts& S, std::string& err) {
         for (int64_t q = S.Bup.ptr[m]; q < S.Bup.ptr[m + 1]; ++q) {
           const int32_t jj = S.Bup.col[q];
           if (S.Bup.blk(q)[c] == 0.0) continue;
+          if (diag_only && jj != i) continue;   // only the diagonal of the product
           const double p = w * S.Bup.blk(q)[c];
           if (slot[jj] < 0) {
             slot[jj] = (int64_t)cols.size();
@@ -298,6 +299,27 @@ int schur_split(const HBsr& A, SchurParts& S, std::string& err) {
       S.S.val.push_back(e.second);
     }
     S.S.ptr[i + 1] = (int32_t)S.S.col.size();
+  }
+  return 0;
+}
+
+int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err) {
+  if (A.br != 1 || A.bc != 1) {
+    err = "scalar SPAI(0) needs 1x1 blocks";
+    return -1;
+  }
+  m.assign(A.nbr, 0.0);
+  for (int32_t i = 0; i < A.nbr; ++i) {
+    double d = 0.0, q = 0.0;
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      q = q + A.val[k] * A.val[k];
+      if (A.col[k] == i) d = A.val[k];
+    }
+    if (!(q > 0.0)) {
+      err = "scalar SPAI(0): empty row";
+      return -4;
+    }
+    m[i] = d / q;
   }
   return 0;
 }

@@ -398,6 +398,23 @@ static void vcycle(hipStream_t st, DHier& H, const TIN* r, TOUT* z, bool trans) 
 
 struct MultiWork;
 void multi_free(MultiWork* w);
+
+// IDR(s) workspace (idrs.hip).
+constexpr int IDR_MAX_S = 16;
+struct IdrWork;
+IdrWork* idr_create(mgk_solver* S);
+void idr_free(IdrWork* w);
+int idrs(mgk_solver* S, const double* b, double* x, double tol, bool trans, mgk_info* info);
+
+// Solve-phase helpers shared by the Krylov methods (solver.hip).
+void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots = 0,
+                const double* w1 = nullptr, int* nwg = nullptr);
+void outer_residual(mgk_solver* S, const double* b, const double* x, double* r, bool trans);
+// Sum `count` reduction partials (two arrays when two) into sc[i0] (, sc[i1]) with
+// finalize op `op`; sc defaults to the solver's scalar block.
+void finalize(mgk_solver* S, int count, int two, int op, int i0 = 0, int i1 = 0,
+              double* sc = nullptr);
+double norm2(mgk_solver* S, const double* a);
 struct BatchWork;
 void batch_free(BatchWork* w);
 
@@ -441,6 +458,7 @@ struct mgk_solver {
   DHier H;                   // monolithic or velocity hierarchy
   DHier Hp;                  // pressure hierarchy (Schur)
   DMat Blo, Bup;             // Schur couplings in storage precision
+  void* Sm = nullptr;        // scalar SPAI(0) of the pressure operator (schur_spai0)
   void *ru = nullptr, *rp = nullptr, *tu = nullptr, *tp = nullptr, *zu = nullptr, *zp = nullptr;
   // Krylov workspace (FP64)
   double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *ph = nullptr, *s = nullptr,
@@ -460,9 +478,11 @@ struct mgk_solver {
   double setup_ms = 0.0;
   bool host_only = false;
   MultiWork* multi = nullptr;      // multi-RHS workspace, created by the first mgk_solve_multi
+  IdrWork* idr = nullptr;          // IDR(s) workspace (krylov == MGK_IDRS)
   BatchWork* batch = nullptr;      // set for solvers made by mgk_batch_setup
   ~mgk_solver() {
     if (multi) mgk::multi_free(multi);
+    if (idr) mgk::idr_free(idr);
     if (batch) mgk::batch_free(batch);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);

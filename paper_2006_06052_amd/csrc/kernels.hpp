@@ -760,6 +760,13 @@ static __global__ __launch_bounds__(WG) void k_update_x(size_t n, int m, const d
 
 // ---- Schur split / merge --------------------------------------------------------
 
+// y = m .* x (diagonal preconditioner step).
+template <class T>
+__global__ __launch_bounds__(WG) void k_diag_mul(size_t n, const T* __restrict__ m,
+                                                 const T* __restrict__ x, T* __restrict__ y) {
+  GRID_STRIDE(i, n) y[i] = m[i] * x[i];
+}
+
 // Interleaved [u,v,w,p] FP64 -> velocity (3 per node) and pressure (1 per node).
 template <class TX>
 __global__ __launch_bounds__(WG) void k_split(size_t nn, const double* __restrict__ r,

@@ -317,6 +317,27 @@ int smoothed_prolongator(const HBsr& A, const std::vector<char>& strong,
   return 0;
 }
 
+// Tentative prolongator (plain aggregation): one identity block at (i, agg(i))
+// for every aggregated block row.
+static void tentative_prolongator(int b, int32_t n, const std::vector<int32_t>& agg,
+                                  int32_t n_agg, HLevel& L) {
+  HBsr& P = L.P;
+  P = HBsr();
+  P.br = P.bc = b;
+  P.nbr = n;
+  P.nbc = n_agg;
+  P.ptr.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    P.ptr[i + 1] = P.ptr[i];
+    if (agg[i] < 0) continue;
+    P.col.push_back(agg[i]);
+    for (int r = 0; r < b; ++r)
+      for (int c = 0; c < b; ++c) P.val.push_back(r == c ? 1.0 : 0.0);
+    P.ptr[i + 1] = P.ptr[i] + 1;
+  }
+  L.omega = 0.0;
+}
+
 int build_smoother(const HBsr& A, const SetupParams& prm, std::vector<double>& M,
                    std::string& err) {
   const int b = A.br, bs = b * b;
@@ -475,7 +496,9 @@ int build_hierarchy(const HBsr& A0, const SetupParams& prm, HHierarchy& H, std::
         L.agg.clear();
         L.n_agg = 0;
       } else {
-        int rc = smoothed_prolongator(L.A, strong, iso, L.agg, L.n_agg, L, err);
+        int rc = 0;
+        if (prm.smooth_p) rc = smoothed_prolongator(L.A, strong, iso, L.agg, L.n_agg, L, err);
+        else tentative_prolongator(b, L.A.nbr, L.agg, L.n_agg, L);
         if (rc) return rc;
         L.R = block_transpose(L.P);
         HBsr AP = block_spgemm(L.A, L.P);

@@ -246,8 +246,8 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
 
 namespace mgk {
 
-static void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots = 0,
-                       const double* w1 = nullptr, int* nwg = nullptr) {
+void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots,
+                const double* w1, int* nwg) {
   hipStream_t st = S->dev.stream;
   const bool timed = S->prm.time_spmv && S->tev_used + 2 <= S->tev.size();
   if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
@@ -274,8 +274,7 @@ static void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, in
   }
 }
 
-static void outer_residual(mgk_solver* S, const double* b, const double* x, double* r,
-                           bool trans) {
+void outer_residual(mgk_solver* S, const double* b, const double* x, double* r, bool trans) {
   hipStream_t st = S->dev.stream;
   const Tile sp = trans ? S->A.ttile : S->A.tile;
   switch (S->b) {
@@ -285,7 +284,9 @@ static void outer_residual(mgk_solver* S, const double* b, const double* x, doub
   }
 }
 
-// Schur apply: z = B r for interleaved FP64 vectors.
+// Schur apply: z = B r for interleaved FP64 vectors: z_u = V_u(r_u);
+// z_p = P_S(r_p - B_lo z_u) with P_S a V-cycle on S or its SPAI(0); then, for
+// the full factorization, z_u = V_u(r_u - B_up z_p) (eqs. SchurP, SchurU).
 template <class TV, class TX>
 static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
   hipStream_t st = S->dev.stream;
@@ -295,9 +296,14 @@ static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
   k_split<TX><<<grid_for(nn), WG, 0, st>>>(nn, r, ru, rp);
   vcycle<TX, TX>(st, S->H, ru, zu, false);
   residual_s<1, 3, TV, TX, TX>(st, S->Blo, false, S->Blo.tile, rp, zu, tp);
-  vcycle<TX, TX>(st, S->Hp, tp, zp, false);
-  residual_s<3, 1, TV, TX, TX>(st, S->Bup, false, S->Bup.tile, ru, zp, tu);
-  vcycle<TX, TX>(st, S->H, tu, zu, false);
+  if (S->prm.schur_spai0)
+    k_diag_mul<TX><<<grid_for(nn), WG, 0, st>>>(nn, (const TX*)S->Sm, tp, zp);
+  else
+    vcycle<TX, TX>(st, S->Hp, tp, zp, false);
+  if (!S->prm.schur_lower) {
+    residual_s<3, 1, TV, TX, TX>(st, S->Bup, false, S->Bup.tile, ru, zp, tu);
+    vcycle<TX, TX>(st, S->H, tu, zu, false);
+  }
   k_merge<TX><<<grid_for(nn), WG, 0, st>>>(nn, zu, zp, z);
 }
 
@@ -317,7 +323,8 @@ void precond(mgk_solver* S, const double* r, double* z, bool trans) {
 static int red_grid(size_t n) { return grid_for(n); }
 static int maxiter_of(const mgk_solver* S) { return S->prm.maxiter; }
 
-static void finalize(mgk_solver* S, int count, int two, int op, int i0 = 0, int i1 = 0) {
+void finalize(mgk_solver* S, int count, int two, int op, int i0, int i1, double* sc) {
+  if (!sc) sc = S->sc;
   const double* src = S->part;
   if (count > RED_CHUNK) {
     const int nb = (count + RED_CHUNK - 1) / RED_CHUNK;
@@ -325,7 +332,7 @@ static void finalize(mgk_solver* S, int count, int two, int op, int i0 = 0, int 
     src = S->part2;
     count = nb;
   }
-  k_finalize<<<1, WG, 0, S->dev.stream>>>(src, count, two, op, i0, i1, S->sc);
+  k_finalize<<<1, WG, 0, S->dev.stream>>>(src, count, two, op, i0, i1, sc);
 }
 
 // Copy the device scalars to pinned memory and mark the point with event e.
@@ -340,7 +347,7 @@ static void wait(mgk_solver* S, int e) {
   HIPCK(hipGetLastError());
 }
 
-static double norm2(mgk_solver* S, const double* a) {
+double norm2(mgk_solver* S, const double* a) {
   const size_t n = S->n;
   const int g = red_grid(n);
   k_dot2<<<g, WG, 0, S->dev.stream>>>(n, a, a, nullptr, nullptr, S->part);
@@ -545,6 +552,7 @@ static SetupParams setup_params(const mgk_params& p, int kind) {
   sp.max_levels = p.max_levels;
   sp.jacobi_omega = p.jacobi_omega;
   sp.smoother = kind == MGK_AMG_JACOBI ? SM_JACOBI : (p.block_spai0 ? SM_SPAI0_BLOCK : SM_SPAI0_SCALAR);
+  sp.smooth_p = p.coarsening == MGK_SMOOTHED_AGGREGATION;
   return sp;
 }
 
@@ -572,6 +580,7 @@ static void alloc_krylov(mgk_solver* S) {
     S->tev.resize(2 * (2 * (size_t)S->prm.maxiter + 64));
     for (auto& e : S->tev) HIPCK(hipEventCreate(&e));
   }
+  if (S->prm.krylov == MGK_IDRS) S->idr = idr_create(S);
   if (S->prm.krylov == MGK_FGMRES) {
     S->m = std::max(1, std::min<int>(S->prm.fgmres_m, MAXM - 1));
     S->V = (double*)D.alloc(nb * (S->m + 1));
@@ -594,8 +603,14 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   if (kind == MGK_SCHUR && block_size != 4)
     throw Error(MGK_E_INVALID, "MGK_SCHUR needs interleaved [u,v,w,p] (block size 4)");
   if (prm->hier < MGK_F64 || prm->hier > MGK_BF16) throw Error(MGK_E_INVALID, "unknown storage");
-  if (prm->krylov != MGK_BICGSTAB && prm->krylov != MGK_FGMRES)
+  if (prm->krylov != MGK_BICGSTAB && prm->krylov != MGK_FGMRES && prm->krylov != MGK_IDRS)
     throw Error(MGK_E_INVALID, "unknown Krylov method");
+  if (prm->krylov == MGK_IDRS && (prm->idr_s < 1 || prm->idr_s > IDR_MAX_S))
+    throw Error(MGK_E_INVALID, "IDR(s) needs 1 <= idr_s <= " + std::to_string(IDR_MAX_S));
+  if (prm->coarsening != MGK_SMOOTHED_AGGREGATION && prm->coarsening != MGK_PLAIN_AGGREGATION)
+    throw Error(MGK_E_INVALID, "unknown coarsening");
+  if ((prm->schur_approx | prm->schur_spai0 | prm->schur_lower) & ~1)
+    throw Error(MGK_E_INVALID, "schur_approx, schur_spai0 and schur_lower are 0 or 1");
   if (prm->maxiter < 1 || prm->coarse_enough < 1 || prm->max_levels < 1 || prm->fgmres_m < 1)
     throw Error(MGK_E_INVALID, "maxiter, coarse_enough, max_levels and fgmres_m must be >= 1");
   if (A->n_brows < 1 || !A->rowptr || (!A->col && A->rowptr[A->n_brows] > 0))
@@ -624,11 +639,13 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     int rc;
     if (kind == MGK_SCHUR) {
       SchurParts parts;
-      if ((rc = schur_split(H, parts, err))) throw Error(rc, err);
+      if ((rc = schur_split(H, prm->schur_approx != 0, parts, err))) throw Error(rc, err);
       if ((rc = build_hierarchy(parts.Auu, sp, S->H.host, err))) throw Error(rc, err);
-      if ((rc = build_hierarchy(parts.S, sp, S->Hp.host, err))) throw Error(rc, err);
-      S->Hp.keep_host = true;
-      describe(S->Hp);
+      if (!prm->schur_spai0) {
+        if ((rc = build_hierarchy(parts.S, sp, S->Hp.host, err))) throw Error(rc, err);
+        S->Hp.keep_host = true;
+        describe(S->Hp);
+      }
     } else {
       if ((rc = build_hierarchy(H, sp, S->H.host, err))) throw Error(rc, err);
     }
@@ -644,12 +661,24 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   int rc;
   if (kind == MGK_SCHUR) {
     SchurParts parts;
-    if ((rc = schur_split(H, parts, err))) throw Error(rc, err);
+    if ((rc = schur_split(H, prm->schur_approx != 0, parts, err))) throw Error(rc, err);
     HHierarchy hu, hp;
     if ((rc = build_hierarchy(parts.Auu, sp, hu, err))) throw Error(rc, err);
-    if ((rc = build_hierarchy(parts.S, sp, hp, err))) throw Error(rc, err);
     upload_hierarchy(S->dev, hu, prm->hier, false, S->H, nullptr);
-    upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr);
+    if (prm->schur_spai0) {
+      std::vector<double> m;
+      if ((rc = scalar_spai0(parts.S, m, err))) throw Error(rc, err);
+      if (prm->hier == MGK_F64) {
+        S->Sm = S->dev.upload(m.data(), m.size());
+      } else {
+        std::vector<float> mf(m.begin(), m.end());
+        S->Sm = S->dev.upload(mf.data(), mf.size());
+      }
+      HIPCK(hipStreamSynchronize(S->dev.stream));
+    } else {
+      if ((rc = build_hierarchy(parts.S, sp, hp, err))) throw Error(rc, err);
+      upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr);
+    }
     S->Blo = upload_mat(S->dev, parts.Blo, prm->hier, false);
     S->Bup = upload_mat(S->dev, parts.Bup, prm->hier, false);
     tune_mat(S->dev, S->Blo, prm->hier, false);
@@ -707,6 +736,8 @@ int mgk_params_default(mgk_params* p) {
   p->jacobi_omega = 2.0 / 3.0;
   p->keep_host = 0;
   p->enable_transpose = 0;
+  p->coarsening = MGK_SMOOTHED_AGGREGATION;
+  p->idr_s = 5;
   return MGK_OK;
 }
 
@@ -795,6 +826,7 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     s->tev_used = 0;
     int rc;
     if (!trans && s->prm.krylov == MGK_FGMRES) rc = mgk::fgmres(s, d_b, d_x, rtol, info);
+    else if (s->prm.krylov == MGK_IDRS) rc = mgk::idrs(s, d_b, d_x, rtol, trans, info);
     else rc = mgk::bicgstab(s, d_b, d_x, rtol, trans, info);
     HIPCK(hipStreamSynchronize(s->dev.stream));
     HIPCK(hipGetLastError());

@@ -112,6 +112,35 @@ def test_host_setup_matches_oracle_schur():
     compare_hierarchies(hs, 1, os_, 1, levels_expected=2)
 
 
+@pytest.mark.parametrize("n,sigma", [(14, None), (12, 1.0)])
+def test_host_setup_matches_oracle_plain_aggregation(n, sigma):
+    """Plain aggregation (P = P_tent): patterns, values, aggregates and omega = 0 bit-exact."""
+    th = None if sigma is None else S.theta_field(n, sigma, 33)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    hs = host_solver(ptr, col, val, 4, coarse_enough=200, coarsening=mgk.PLAIN_AGGREGATION)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4, coarse_enough=200,
+                        coarsening=oracle.PLAIN)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)
+    assert hs.level_info(0)["omega"] == 0.0
+
+
+def test_host_setup_matches_oracle_schur_diagonal_approximation():
+    """eq. SchurApprox pressure operator and the plain-aggregation velocity hierarchy of
+    the paper's Schur configuration, bit-exact; with the SPAI(0) pressure step there is
+    no pressure hierarchy."""
+    n = 14
+    th = S.theta_field(n, 1.0, 3)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    kw = dict(coarse_enough=150, schur_approx=1)
+    hs = host_solver(ptr, col, val, 4, mgk.SCHUR, coarsening=mgk.PLAIN_AGGREGATION, **kw)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4, kind=oracle.KIND_SCHUR,
+                        coarsening=oracle.PLAIN, **kw)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)
+    compare_hierarchies(hs, 1, os_, 1, levels_expected=2)
+    hs2 = host_solver(ptr, col, val, 4, mgk.SCHUR, schur_spai0=1, **kw)
+    assert hs2.nlevels(1) == 0 and hs2.nlevels(0) >= 2
+
+
 def test_host_setup_scalar_csr_arm():
     """The whole setup at block size 1 on the scalar CSR matrix (V2-style scalar arm)."""
     n = 8
@@ -151,6 +180,11 @@ def test_invalid_input_rejected_before_device_work():
     assert e.value.code == -1
     with pytest.raises(mgk.MgkError):
         host_solver(ptr, col, val, 4, maxiter=0)
+    for bad_kw in (dict(krylov=mgk.IDRS, idr_s=0), dict(krylov=mgk.IDRS, idr_s=17),
+                   dict(krylov=3), dict(coarsening=2), dict(schur_lower=2)):
+        with pytest.raises(mgk.MgkError) as e:
+            host_solver(ptr, col, val, 4, **bad_kw)
+        assert e.value.code == -1, bad_kw
     with pytest.raises(mgk.MgkError):
         mgk.stokes_bsr(2)
     with pytest.raises(mgk.MgkError):

@@ -1,0 +1,158 @@
+"""GPU parity of the solver variants: plain aggregation, IDR(s), and the Schur
+pressure-correction options (diagonal approximation of the pressure operator,
+SPAI(0) pressure step, lower factorization), against the FP64 CPU oracle.
+
+Bars as for the other parity tests: ||b - A x|| / ||b|| <= 1e-8 with the oracle's
+SpMV, and agreement with the oracle's FP64 solve (rtol 1e-12) to 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import stokes_synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2006_06052_amd as mgk  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def problem(n, sigma=None, seed=1):
+    th = None if sigma is None else S.theta_field(n, sigma, seed)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    return th, (ptr, col, val), oracle.stokes_matrix(n, th)
+
+
+def gpu_solver(bsr, kind=mgk.AMG_SPAI0, **kw):
+    return mgk.Solver(*bsr, 4, kind, stream=torch.cuda.current_stream(), **kw)
+
+
+def check_solution(A, b, x, xo, tol=1e-8, err=1e-6):
+    res = np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b)
+    e = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert res <= tol, res
+    assert e <= err, e
+    return res, e
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_plain_aggregation_solve(storage):
+    n = 16
+    th, bsr, A = problem(n, 0.5, 11)
+    b = oracle.spmv(A, S.mms_solution(n))
+    s = gpu_solver(bsr, hier=storage, coarse_enough=300, coarsening=mgk.PLAIN_AGGREGATION)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    so = oracle.Solver(A, 4, coarse_enough=300, coarsening=oracle.PLAIN)
+    xo, oi = so.solve(b, 1e-12)
+    say("plain", storage, info["iters"], oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+    if storage == "f64":
+        # same hierarchy, same method: the V-cycle agrees with the oracle's
+        r = np.random.default_rng(2).normal(size=A.shape[0])
+        dz = torch.empty_like(dx)
+        s.precond(dev(r), dz)
+        zo = so.precond(r)
+        assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("s_dim,storage", [(1, "f64"), (5, "f64"), (8, "f64"), (5, "f32"),
+                                           (5, "bf16")])
+def test_idrs_solve(s_dim, storage):
+    """IDR(s) against the oracle's IDR(s) solve (same shadow space); with the FP64
+    hierarchy the two runs are the same method and take about the same number of
+    products with A."""
+    n = 16
+    th, bsr, A = problem(n, 0.5, 12)
+    b = oracle.spmv(A, S.mms_solution(n))
+    s = gpu_solver(bsr, hier=storage, coarse_enough=300, krylov=mgk.IDRS, idr_s=s_dim)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    so = oracle.Solver(A, 4, coarse_enough=300, krylov=oracle.IDRS, idr_s=s_dim)
+    xo, oi = so.solve(b, 1e-12)
+    xo8, oi8 = so.solve(b, 1e-8)
+    say("idrs", s_dim, storage, info, oi8["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+    if storage == "f64":
+        assert abs(info["iters"] - oi8["iters"]) <= max(3, oi8["iters"] // 10)
+
+
+def test_idrs_transposed_and_edge_cases():
+    n = 10
+    th, bsr, A = problem(n, 0.5, 13)
+    s = gpu_solver(bsr, coarse_enough=200, krylov=mgk.IDRS, enable_transpose=1)
+    g = np.random.default_rng(3).normal(size=A.shape[0])
+    dl = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve_transposed(dev(g), dl, 1e-9)
+    lo, _ = oracle.Solver(A, 4, coarse_enough=200, krylov=oracle.IDRS).solve(g, 1e-12,
+                                                                                transposed=True)
+    assert info["status"] == 0
+    At = A.T.tocsr()
+    check_solution(At, g, dl.cpu().numpy(), lo, tol=1e-9)
+    # zero right-hand side, and an iteration cap
+    z = torch.zeros_like(dl)
+    x = torch.ones_like(dl)
+    info = s.solve(z, x, 1e-8)
+    assert info["status"] == 0 and info["iters"] == 0 and not torch.any(x)
+    s1 = gpu_solver(bsr, coarse_enough=200, krylov=mgk.IDRS, maxiter=3, max_restarts=0)
+    x = torch.zeros_like(dl)
+    info = s1.solve(dev(S.mms_rhs(n)), x, 1e-12)
+    assert info["status"] == mgk.MGK_NOT_CONVERGED and info["iters"] == 3
+
+
+@pytest.mark.parametrize("approx,spai0,lower", [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0),
+                                                (1, 1, 1)])
+def test_schur_variants_match_oracle(approx, spai0, lower):
+    """Schur preconditioner options: the FP64 application agrees with the oracle's, and
+    FGMRES solves reach the oracle's solution."""
+    n = 14
+    th, bsr, A = problem(n, 1.0, 3)
+    b = oracle.spmv(A, S.mms_solution(n))
+    kw = dict(schur_approx=approx, schur_spai0=spai0, schur_lower=lower, coarse_enough=200)
+    s = gpu_solver(bsr, mgk.SCHUR, krylov=mgk.FGMRES, **kw)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES, **kw)
+    r = np.random.default_rng(4).normal(size=A.shape[0])
+    dz = torch.empty(A.shape[0], dtype=torch.float64, device=DEV)
+    s.precond(dev(r), dz)
+    zo = so.precond(r)
+    assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+    dx = torch.zeros_like(dz)
+    info = s.solve(dev(b), dx, 1e-8)
+    xo, oi = so.solve(b, 1e-12)
+    say("schur variant", kw, info["iters"], oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_paper_schur_configuration_idrs(storage):
+    """The paper's Schur configuration on the GPU: IDR(5) outer solver; velocity AMG with
+    plain aggregation on the 3x3 blocks; pressure step one SPAI(0) application of the
+    diagonal approximation of the Schur complement; full factorization; FP64 or BF16
+    hierarchy values."""
+    n = 16
+    th, bsr, A = problem(n, 1.0, 14)
+    b = oracle.spmv(A, S.mms_solution(n))
+    kw = dict(schur_approx=1, schur_spai0=1, coarse_enough=300)
+    s = gpu_solver(bsr, mgk.SCHUR, krylov=mgk.IDRS, idr_s=5, hier=storage,
+                   coarsening=mgk.PLAIN_AGGREGATION, **kw)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.IDRS, idr_s=5,
+                       coarsening=oracle.PLAIN, **kw)
+    xo, oi = so.solve(b, 1e-12)
+    say("paper schur", storage, info, oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
