@@ -140,7 +140,13 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
     batch8   - 8 systems of 24^3 ... 64^3 nodes, theta_k = exp(N(0, 0.25)) (seed 40+k),
                b_k = A_k x*, in one batched solve, against the 8 systems solved one by one;
     adjoint48 - 48^3, theta seed 5, target from theta seed 50: forward solve, adjoint solve
-               with the transposed V-cycle, and the per-cell viscosity gradient.
+               with the transposed V-cycle, and the per-cell viscosity gradient;
+    idrs96   - the 96^3 headline system with IDR(5) instead of BiCGStab;
+    plain96  - the 96^3 headline system with plain-aggregation AMG (P = P_tent);
+    paper_schur64 - the 64^3 log-normal system with the paper's Schur configuration:
+               IDR(5), velocity AMG with plain aggregation, pressure step one SPAI(0)
+               application of the diagonal Schur approximation, full factorization;
+               FP64, FP32 and BF16 hierarchy values.
     All hierarchies are FP32 unless stated; rtol 1e-8 (adjoint workload 1e-10)."""
     import numpy as np
     stream = torch.cuda.current_stream()
@@ -283,6 +289,56 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
                                      "setup_s": t_setup, **rec}
         log_fn(f"adjoint48: {t:.3f}s (forward {fi['iters']} it, adjoint {ai['iters']} it)")
         del s
+    if "idrs96" in which or "plain96" in which:
+        n = 96
+        ptr, col, val = mgk.stokes_bsr(n)
+        b = torch.from_numpy(S.c2_rhs(n)).cuda()
+        arms = []
+        if "idrs96" in which:
+            arms.append(("idrs96_f32", dict(krylov=mgk.IDRS, idr_s=5)))
+        if "plain96" in which:
+            arms.append(("plain96_f32", dict(coarsening=mgk.PLAIN_AGGREGATION)))
+        for key, kw in arms:
+            t0 = time.perf_counter()
+            sv = solver(ptr, col, val, hier=mgk.F32, **kw)
+            t_setup = time.perf_counter() - t0
+            x = torch.zeros_like(b)
+
+            def run():
+                x.zero_()
+                return sv.solve(b, x, 1e-8)
+            t, info = _median_solve(run, torch)
+            out[key] = {"solve_s": t, "iters": info["iters"], "status": info["status"],
+                        "rel_resid": info["rel_resid"], "levels": info["levels"],
+                        "setup_s": t_setup}
+            log_fn(f"{key}: {t:.3f}s, {info['iters']} iterations")
+            del sv
+            torch.cuda.empty_cache()
+
+    if "paper_schur64" in which:
+        n = 64
+        ptr, col, val = mgk.stokes_bsr(n, S.theta_field(n, 1.0, 3))
+        xs = torch.from_numpy(S.mms_solution(n)).cuda()
+        r = {}
+        for tag, hier in (("f64", mgk.F64), ("f32", mgk.F32), ("bf16", mgk.BF16)):
+            t0 = time.perf_counter()
+            sv = solver(ptr, col, val, mgk.SCHUR, hier=hier, krylov=mgk.IDRS, idr_s=5,
+                        coarsening=mgk.PLAIN_AGGREGATION, schur_approx=1, schur_spai0=1)
+            t_setup = time.perf_counter() - t0
+            b = a_times(sv, xs)
+            x = torch.zeros_like(b)
+
+            def run():
+                x.zero_()
+                return sv.solve(b, x, 1e-8)
+            t, info = _median_solve(run, torch)
+            r[tag] = {"solve_s": t, "iters": info["iters"], "status": info["status"],
+                      "rel_resid": info["rel_resid"], "setup_s": t_setup}
+            log_fn(f"paper_schur64 {tag}: {t:.3f}s, {info['iters']} iterations")
+            del sv
+        r["speedup_f32_vs_f64"] = r["f64"]["solve_s"] / r["f32"]["solve_s"]
+        r["speedup_bf16_vs_f64"] = r["f64"]["solve_s"] / r["bf16"]["solve_s"]
+        out["paper_schur64_idrs"] = r
     torch.cuda.empty_cache()
     return out
 
@@ -317,7 +373,8 @@ def main():
     ap.add_argument("--n", type=int, default=96)
     ap.add_argument("--arms", default="bsr_f32,bsr_f64,bsr_bf16,csr_f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--secondary", default="schur64,multi64,batch8,adjoint48",
+    ap.add_argument("--secondary",
+                    default="schur64,multi64,batch8,adjoint48,idrs96,plain96,paper_schur64",
                     help="other solve shapes timed after the headline (empty: none)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the FP64 BSR SpMV loop")
