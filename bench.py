@@ -343,6 +343,39 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
     return out
 
 
+def seed_sweep(mgk, S, torch, n, seeds, log_fn):
+    """The three BSR hierarchy precisions on the same 96^3 operator with the right-hand
+    side noise drawn from `seeds` seeds: BiCGStab's iteration count at rtol 1e-8 moves by
+    several percent with rounding-level changes, so single-seed speedups carry that
+    spread.  One untimed and one timed solve per seed and arm."""
+    import numpy as np
+    ptr, col, val = mgk.stokes_bsr(n)
+    st = torch.cuda.current_stream()
+    res = {}
+    for arm, hier in (("bsr_f64", mgk.F64), ("bsr_f32", mgk.F32), ("bsr_bf16", mgk.BF16)):
+        s = mgk.Solver(ptr, col, val, 4, mgk.AMG_SPAI0, stream=st, hier=hier)
+        for seed in range(2, 2 + seeds):
+            b = torch.from_numpy(S.c2_rhs(n, seed=seed)).cuda()
+            x = torch.zeros_like(b)
+
+            def run():
+                x.zero_()
+                return s.solve(b, x, 1e-8)
+            t, info = _median_solve(run, torch, steps=1, warmup=1)
+            res.setdefault(arm, []).append({"seed": seed, "iters": info["iters"], "solve_s": t})
+            log_fn(f"seed sweep {arm} seed {seed}: {t:.3f}s, {info['iters']} iterations")
+        del s
+    out = {"seeds": list(range(2, 2 + seeds)), "runs": res}
+    for arm in res:
+        it = np.array([r["iters"] for r in res[arm]], float)
+        out[arm] = {"iters_mean": it.mean(), "iters_min": it.min(), "iters_max": it.max(),
+                    "solve_s_mean": float(np.mean([r["solve_s"] for r in res[arm]]))}
+    for arm in ("bsr_f32", "bsr_bf16"):
+        sp = np.array([a["solve_s"] / b["solve_s"] for a, b in zip(res["bsr_f64"], res[arm])])
+        out[f"speedup_{arm}_vs_bsr_f64"] = {"mean": sp.mean(), "min": sp.min(), "max": sp.max()}
+    return out
+
+
 def cpu_baseline(n, b_np, iters_scale, log_fn):
     """The oracle as it stands (scalar CSR FP64, OpenMP SpMV) on the host cores: setup once
     (not part of the metric), then a bounded run of 3 BiCGStab iterations, scaled to the
@@ -373,6 +406,8 @@ def main():
     ap.add_argument("--n", type=int, default=96)
     ap.add_argument("--arms", default="bsr_f32,bsr_f64,bsr_bf16,csr_f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed-sweep", type=int, default=0,
+                    help="also run the three BSR arms over this many right-hand-side seeds")
     ap.add_argument("--secondary",
                     default="schur64,multi64,batch8,adjoint48,idrs96,plain96,paper_schur64",
                     help="other solve shapes timed after the headline (empty: none)")
@@ -500,6 +535,8 @@ def main():
         roofline["copy_ceiling_gbs"] = copy_ceiling(torch)
         roofline["frac_of_copy_ceiling"] = roofline["achieved"] / roofline["copy_ceiling_gbs"]
     out["roofline"] = roofline
+    if args.seed_sweep > 0:
+        out["seed_sweep"] = seed_sweep(mgk, S, torch, n, args.seed_sweep, log)
     which = [w for w in args.secondary.split(",") if w]
     if which:
         out["secondary"] = secondary_workloads(mgk, S, torch, log, which)

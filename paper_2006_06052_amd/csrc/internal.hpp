@@ -257,7 +257,7 @@ static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& til
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const double* v = (const double*)M.val;
-  const int g = std::max(1, (nrows + DOT_ROWS - 1) / DOT_ROWS);
+  const int g = std::max(1, (nrows + dot_rows<BR>() - 1) / dot_rows<BR>());
   tile_switch<BR>(tile, [&](auto SS, auto UU) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
     if (trans)

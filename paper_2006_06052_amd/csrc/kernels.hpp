@@ -339,11 +339,16 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
 }
 
 // y = A x fused with the partial dot products <w1, y> and (two) <y, y> of the
-// Krylov iteration (FP64 outer operator).  Every workgroup owns the same 64
-// block rows whatever the tile: the per-row products are staged in LDS by
-// scalar row and summed by one fixed tree, so the partials (and the whole
-// solve) do not depend on the tile.
-constexpr int DOT_ROWS = 64;
+// Krylov iteration (FP64 outer operator).  Every workgroup owns the same
+// DOT_ROWS block rows whatever the tile: the per-row products are staged in LDS
+// by scalar row and summed by one fixed tree, so the partials (and the whole
+// solve) do not depend on the tile.  16 block rows are one pass of the
+// four-lane split (S = 4) tile that suits short 3x3 / 4x4 block rows; scalar
+// rows use 64.
+template <int BR>
+constexpr int dot_rows() {
+  return BR == 1 ? 64 : 16;
+}
 
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX>
 __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict__ ptr,
@@ -355,6 +360,7 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
                                                  const double* __restrict__ w1,
                                                  double* __restrict__ part) {
   using M = RowMap<BR, S>;
+  constexpr int DOT_ROWS = dot_rows<BR>();
   constexpr int NR = DOT_ROWS * BR < 128 ? 64 : (DOT_ROWS * BR <= 128 ? 128 : 256);
   static_assert(DOT_ROWS * BR <= NR, "dot staging");
   __shared__ double sd1[NR], sd2[NR];
