@@ -18,11 +18,16 @@
 
 namespace mgk {
 
+// Launch shapes of a grouped launch: a persistent grid of PERSIST workgroups
+// striding through the tiles, or one workgroup per tile (ONE_PER_TILE).
+constexpr int PERSIST = 2048, ONE_PER_TILE = 1 << 30;
+
 struct GStage {
   std::vector<GItem> h;
   GItem* d = nullptr;
   int total = 0;
   Tile tile;
+  int cap = PERSIST;               // workgroups per launch (tuned for row stages)
 };
 
 struct BatchWork {
@@ -80,8 +85,9 @@ static int tiles_for(int B, const Tile& t, int nbr) {
 }
 
 // Assign tile starts for a row stage with tile t and upload its items.
-static void finish_rows(BatchWork& W, GStage& g, int B, const Tile& t) {
+static void finish_rows(BatchWork& W, GStage& g, int B, const Tile& t, int cap) {
   g.tile = t;
+  g.cap = cap;
   int acc = 0;
   for (GItem& it : g.h) {
     it.tile0 = acc;
@@ -109,7 +115,7 @@ static void finish_fixed(BatchWork& W, GStage& g, int per_tile_rows) {
   HIPCK(hipStreamSynchronize(W.dev.stream));
 }
 
-static int pgrid(int total) { return std::max(1, std::min(total, 2048)); }
+static int pgrid(int total, int cap = PERSIST) { return std::max(1, std::min(total, cap)); }
 
 // ---------------------------------------------------------------- grouped launches
 
@@ -119,7 +125,7 @@ static void g_spmv(hipStream_t st, const GStage& g, const int* active, double be
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
     k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA>
-        <<<pgrid(g.total), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
+        <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
   });
 }
 
@@ -129,7 +135,7 @@ static void g_residual(hipStream_t st, const GStage& g, const int* active) {
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
     k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA>
-        <<<pgrid(g.total), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+        <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
   });
 }
 
@@ -139,7 +145,7 @@ static void g_smooth(hipStream_t st, const GStage& g, const int* active) {
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
     k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA>
-        <<<pgrid(g.total), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+        <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
   });
 }
 
@@ -147,32 +153,40 @@ static void g_smooth(hipStream_t st, const GStage& g, const int* active) {
 template <int B, class TV, class TX>
 static void tune_stage(BatchWork& W, GStage& g, int* active) {
   std::vector<Tile> cands;
-  if (B == 1) cands = {{1, 8}, {2, 4}, {4, 4}, {8, 4}, {16, 2}, {32, 2}};
-  else cands = {{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 4}, {8, 4}, {16, 2}};
+#define MGK_BCAND(SS, UU) cands.push_back(Tile{SS, UU, 1});
+  if (B == 1) {
+    MGK_TILES_1(MGK_BCAND)
+  } else {
+    MGK_TILES_B(MGK_BCAND)
+  }
+#undef MGK_BCAND
   if (g.h.empty()) return;
   // scratch outputs: the stage's own outputs are overwritten during setup only
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
   Tile best = cands[0];
+  int best_cap = PERSIST;
   float best_ms = 1e30f;
-  for (const Tile& t : cands) {
-    finish_rows(W, g, B, t);
-    g_spmv<B, TV, TX, TX>(W.dev.stream, g, active, 0.0);
-    HIPCK(hipEventRecord(e0, W.dev.stream));
-    for (int r = 0; r < 3; ++r) g_spmv<B, TV, TX, TX>(W.dev.stream, g, active, 0.0);
-    HIPCK(hipEventRecord(e1, W.dev.stream));
-    HIPCK(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    HIPCK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = t;
+  for (const Tile& t : cands)
+    for (int cap : {PERSIST, ONE_PER_TILE}) {
+      finish_rows(W, g, B, t, cap);
+      g_spmv<B, TV, TX, TX>(W.dev.stream, g, active, 0.0);
+      HIPCK(hipEventRecord(e0, W.dev.stream));
+      for (int r = 0; r < 3; ++r) g_spmv<B, TV, TX, TX>(W.dev.stream, g, active, 0.0);
+      HIPCK(hipEventRecord(e1, W.dev.stream));
+      HIPCK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+        best_cap = cap;
+      }
     }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  finish_rows(W, g, B, best);
+  finish_rows(W, g, B, best, best_cap);
 }
 
 // ---------------------------------------------------------------- grouped V-cycle
@@ -302,14 +316,14 @@ static void tune_all(BatchWork& W) {
     tune_stage<B, TV, TX>(W, W.res[0][l], W.active);
     for (int v = 0; v < 2; ++v) {
       if (v == 1 && l > 0) continue;
-      finish_rows(W, W.res[v][l], B, W.res[0][l].tile);
-      finish_rows(W, W.sm[v][l], B, W.res[0][l].tile);
+      finish_rows(W, W.res[v][l], B, W.res[0][l].tile, W.res[0][l].cap);
+      finish_rows(W, W.sm[v][l], B, W.res[0][l].tile, W.res[0][l].cap);
     }
     tune_stage<B, TV, TX>(W, W.R[l], W.active);
     tune_stage<B, TV, TX>(W, W.P[l], W.active);
   }
   for (int v = 0; v < 2; ++v) tune_stage<B, double, double>(W, W.outer_spmv[v], W.active);
-  finish_rows(W, W.outer_res, B, W.outer_spmv[0].tile);
+  finish_rows(W, W.outer_res, B, W.outer_spmv[0].tile, W.outer_spmv[0].cap);
 }
 
 static void batch_setup_impl(mgk_solver* S, int nsys, const mgk_bsr* const* A, int block_size,

@@ -35,7 +35,12 @@ __device__ __forceinline__ int find_item(const GItem* __restrict__ items, int ni
   return it;
 }
 
-#define GROUP_TILES(w, total) for (int w = blockIdx.x; w < (total); w += gridDim.x)
+// Tile walk of a grouped launch.  gridDim.x >= total: one tile per workgroup,
+// remapped so that each XCD takes one contiguous range of tiles; gridDim.x <
+// total: a persistent grid striding through the tile space.
+#define GROUP_TILES(w, total)                                                         \
+  for (int w = (int)gridDim.x >= (total) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
+       w < (total); w += (int)gridDim.x)
 
 // y = A x + beta y
 template <int BR, int BC, int S, int U, class TV, class TX, class TY, class TA>
