@@ -139,6 +139,7 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
                against 4 single-RHS solves of columns 0..3 scaled to 32;
     batch8   - 8 systems of 24^3 ... 64^3 nodes, theta_k = exp(N(0, 0.25)) (seed 40+k),
                b_k = A_k x*, in one batched solve, against the 8 systems solved one by one;
+    batch32small - 32 systems of 12^3 ... 22^3 nodes (seeds 100+k), batched vs one by one;
     adjoint48 - 48^3, theta seed 5, target from theta seed 50: forward solve, adjoint solve
                with the transposed V-cycle, and the per-cell viscosity gradient;
     idrs96   - the 96^3 headline system with IDR(5) instead of BiCGStab;
@@ -248,6 +249,43 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
                                 "setup_s": t_setup, "one_by_one_s": seq_t,
                                 "one_by_one_iters": seq_it, "speedup_vs_one_by_one": seq_t / t}
         log_fn(f"batch8: {t:.3f}s, one by one {seq_t:.3f}s")
+        del bsol
+
+    if "batch32small" in which:
+        # many small systems (12^3 .. 22^3 nodes, log-normal viscosity): the regime where a
+        # single system cannot fill the GPU and one launch per stage over all systems pays
+        ns = [12 + (k % 6) * 2 for k in range(32)]
+        systems, bs, seq_t = [], [], 0.0
+        singles = []
+        for k, n in enumerate(ns):
+            p_, c_, v_ = mgk.stokes_bsr(n, S.theta_field(n, 0.5, 100 + k))
+            systems.append((p_, c_, v_))
+            sv = solver(p_, c_, v_, hier=mgk.F32, coarse_enough=500)
+            bs.append(a_times(sv, torch.from_numpy(S.mms_solution(n)).cuda()))
+            singles.append(sv)
+        xs = [torch.zeros_like(b) for b in bs]
+
+        def run_seq():
+            its = []
+            for sv, b, x in zip(singles, bs, xs):
+                x.zero_()
+                its.append(sv.solve(b, x, 1e-8)["iters"])
+            return its
+        seq_t, seq_it = _median_solve(run_seq, torch)
+        del singles
+        bsol = mgk.BatchSolver(systems, 4, mgk.AMG_SPAI0, stream=stream, hier=mgk.F32,
+                               coarse_enough=500)
+
+        def run():
+            for x in xs:
+                x.zero_()
+            return bsol.solve(bs, xs, 1e-8)
+        t, infos = _median_solve(run, torch)
+        out["batch32_small"] = {"solve_s": t, "nodes_per_side": ns,
+                                "iters_max": max(i["iters"] for i in infos),
+                                "all_converged": all(i["status"] == 0 for i in infos),
+                                "one_by_one_s": seq_t, "speedup_vs_one_by_one": seq_t / t}
+        log_fn(f"batch32small: {t:.3f}s, one by one {seq_t:.3f}s")
         del bsol
 
     if "adjoint48" in which:
@@ -409,7 +447,8 @@ def main():
     ap.add_argument("--seed-sweep", type=int, default=0,
                     help="also run the three BSR arms over this many right-hand-side seeds")
     ap.add_argument("--secondary",
-                    default="schur64,multi64,batch8,adjoint48,idrs96,plain96,paper_schur64",
+                    default="schur64,multi64,batch8,batch32small,adjoint48,idrs96,plain96,"
+                            "paper_schur64",
                     help="other solve shapes timed after the headline (empty: none)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the FP64 BSR SpMV loop")
