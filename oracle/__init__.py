@@ -19,9 +19,9 @@ import scipy.sparse as sp
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liborc.so")
-SOURCES = ["csr.cpp", "stokes.cpp", "amg.cpp", "krylov.cpp", "capi.cpp"]
+SOURCES = ["csr.cpp", "stokes.cpp", "amg.cpp", "krylov.cpp", "ilu.cpp", "capi.cpp"]
 
-KIND_AMG, KIND_SCHUR, KIND_IDENTITY = 0, 1, 2
+KIND_AMG, KIND_SCHUR, KIND_IDENTITY, KIND_ILU = 0, 1, 2, 3
 SPAI0_BLOCK, JACOBI, SPAI0_SCALAR = 0, 1, 2
 BICGSTAB, FGMRES, IDRS = 0, 1, 2
 SMOOTHED, PLAIN = 0, 1
@@ -46,7 +46,7 @@ class _Params(C.Structure):
                 ("smoother", C.c_int32), ("kind", C.c_int32), ("jacobi_omega", C.c_double),
                 ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
-                ("pad", C.c_int32)]
+                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("pad", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -81,6 +81,8 @@ def lib():
         L.orc_precond.argtypes = [P, P, P, C.c_int]
         L.orc_solve.argtypes = [P, P, P, C.c_double, C.c_int, C.POINTER(_Info)]
         L.orc_idr_shadow.argtypes = [C.c_int64, C.c_int, P]
+        L.orc_ilu_factor.argtypes = [P, P, P, P]
+        L.orc_ilu_factor.restype = C.c_int64
         L.orc_idr_shadow.restype = None
         L.orc_gather_block_row.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int64, P, P,
                                            C.c_int32]
@@ -160,7 +162,7 @@ class Solver:
                  maxiter: int = 1000, fgmres_m: int = 30, max_restarts: int = 5,
                  jacobi_omega: float = 2.0 / 3.0, coarsening: int = SMOOTHED,
                  schur_approx: int = 0, schur_spai0: int = 0, schur_lower: int = 0,
-                 idr_s: int = 5):
+                 idr_s: int = 5, ilu_level: int = 0, ilu_sweeps: int = 2):
         A = sp.csr_matrix(A)
         A.sort_indices()
         self.n = A.shape[0]
@@ -168,7 +170,7 @@ class Solver:
                       np.ascontiguousarray(A.indices, np.int32), _f64(A.data))
         self.prm = _Params(krylov, fgmres_m, maxiter, max_restarts, eps_strong, coarse_enough,
                            max_levels, smoother, kind, jacobi_omega, coarsening, schur_approx,
-                           schur_spai0, schur_lower, idr_s, 0)
+                           schur_spai0, schur_lower, idr_s, ilu_level, ilu_sweeps, 0)
         self.block = block
         L = lib()
         h = L.orc_setup(self.n, *(_p(a) for a in self._keep), block, C.byref(self.prm))
@@ -181,6 +183,17 @@ class Solver:
         if h and _lib is not None:
             _lib.orc_free(h)
             self._h = None
+
+    def ilu_factor(self) -> sp.csr_matrix:
+        """Combined block ILU factor (L strictly lower with unit diagonal implied, U on and
+        above the diagonal) as scalar CSR."""
+        L = lib()
+        nz = L.orc_ilu_factor(self._h, None, None, None)
+        ptr = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(max(nz, 1), np.int32)
+        val = np.zeros(max(nz, 1), np.float64)
+        L.orc_ilu_factor(self._h, _p(ptr), _p(col), _p(val))
+        return sp.csr_matrix((val[:nz], col[:nz], ptr), shape=(self.n, self.n))
 
     def nlevels(self, which: int = 0) -> int:
         return lib().orc_nlevels(self._h, which)

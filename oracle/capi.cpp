@@ -21,6 +21,11 @@ struct AmgPre : Precond {
   explicit AmgPre(const Hierarchy* h) : H(h) {}
   void apply(const double* r, double* z) const override { vcycle(*H, 0, r, z); }
 };
+struct IluPre : Precond {
+  const Ilu* F;
+  explicit IluPre(const Ilu* f) : F(f) {}
+  void apply(const double* r, double* z) const override { ilu_apply(*F, r, z); }
+};
 struct SchurPre : Precond {
   const Schur* S;
   explicit SchurPre(const Schur* s) : S(s) {}
@@ -56,6 +61,8 @@ struct orc_params {
   int32_t schur_spai0;   // 1: SPAI(0) pressure step
   int32_t schur_lower;   // 1: lower block factorization
   int32_t idr_s;         // shadow space dimension of IDR(s)
+  int32_t ilu_level;     // fill level of the block ILU(k) preconditioner (kind 3)
+  int32_t ilu_sweeps;    // Jacobi sweeps per triangular factor
   int32_t pad;
 };
 
@@ -72,6 +79,7 @@ struct orc_solver {
   Hierarchy H, Ht;
   bool have_t = false;
   Schur S;
+  Ilu F;
 };
 
 const char* orc_last_error(void) { return g_err.c_str(); }
@@ -121,6 +129,15 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
     if (prm->kind == 0) {
       if (!amg_build(s->A, block, s->aprm, s->H, &msg)) {
         g_err = msg ? msg : "oracle: setup failed";
+        return nullptr;
+      }
+    } else if (prm->kind == 3) {
+      if (prm->ilu_level < 0 || prm->ilu_level > 1 || prm->ilu_sweeps < 0) {
+        g_err = "oracle: ILU(k) needs k in {0, 1} and sweeps >= 0";
+        return nullptr;
+      }
+      if (!ilu_build(s->A, block, prm->ilu_level, prm->ilu_sweeps, s->F, &msg)) {
+        g_err = msg ? msg : "oracle: ILU setup failed";
         return nullptr;
       }
     } else if (prm->kind == 1) {
@@ -222,6 +239,8 @@ int orc_precond(orc_solver* s, const double* r, double* z, int transposed) {
     vcycle(transposed ? s->Ht : s->H, 0, r, z);
   } else if (s->prm.kind == 1) {
     schur_apply(s->S, r, z);
+  } else if (s->prm.kind == 3) {
+    ilu_apply(s->F, r, z);
   } else {
     std::memcpy(z, r, sizeof(double) * s->A.nr);
   }
@@ -239,6 +258,7 @@ int orc_solve(orc_solver* s, const double* b, double* x, double tol, int transpo
   std::unique_ptr<Precond> M;
   if (s->prm.kind == 0) M.reset(new AmgPre(transposed ? &s->Ht : &s->H));
   else if (s->prm.kind == 1) M.reset(new SchurPre(&s->S));
+  else if (s->prm.kind == 3) M.reset(new IluPre(&s->F));
   else M.reset(new Identity(s->A.nr));
   SolveInfo si;
   if (s->prm.krylov == 0)
@@ -255,6 +275,28 @@ int orc_solve(orc_solver* s, const double* b, double* x, double tol, int transpo
 }
 
 }  // extern "C"
+
+// Combined ILU factor as scalar CSR (block entries expanded, zeros kept):
+// returns the number of entries, fills ptr/col/val when they are non-null.
+extern "C" int64_t orc_ilu_factor(orc_solver* s, int64_t* ptr, int32_t* col, double* val) {
+  const Ilu& F = s->F;
+  const int b = F.b;
+  int64_t nz = 0;
+  for (i64 i = 0; i < F.nn; ++i)
+    for (int r = 0; r < b; ++r) {
+      if (ptr) ptr[i * b + r] = nz;
+      for (size_t t = 0; t < F.cols[i].size(); ++t)
+        for (int c = 0; c < b; ++c) {
+          if (col) {
+            col[nz] = F.cols[i][t] * b + c;
+            val[nz] = F.vals[i][t * b * b + r * b + c];
+          }
+          ++nz;
+        }
+    }
+  if (ptr) ptr[F.nn * b] = nz;
+  return nz;
+}
 
 extern "C" void orc_idr_shadow(int64_t n, int s, double* out) {
   const std::vector<double> P = idr_shadow(n, s);

@@ -18,7 +18,9 @@
 // step (derived from the pinned full approximation; least-squares optimality),
 // the lower block factorization (dense algebra), and IDR(s) (SplitMix64's
 // published outputs for the shadow space, the m + m/s termination bound, dense
-// LU).
+// LU), and block ILU(k) (exact LU of a tridiagonal matrix, (LU)_ij = A_ij on the
+// factor's pattern, exactness of enough Jacobi sweeps, block Jacobi at zero
+// sweeps).
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -143,5 +145,20 @@ struct Schur {
 bool schur_build(const Csr& A, const AmgParams& prm, const SchurOptions& opt, Schur& S,
                  const char** msg);
 void schur_apply(const Schur& S, const double* r, double* z);
+
+// Block ILU(k) (ilu.cpp): per block row, the sorted block columns of the
+// combined factor (L strictly below the diagonal, U on and above it) and their
+// b x b blocks; Dinv holds U(i,i)^-1.  Applied with `sweeps` Jacobi iterations
+// on each triangular factor.
+struct Ilu {
+  int b = 1;
+  i64 nn = 0;
+  int sweeps = 2;
+  std::vector<std::vector<i32>> cols;
+  std::vector<std::vector<double>> vals;
+  std::vector<double> Dinv;
+};
+bool ilu_build(const Csr& A, int b, int level, int sweeps, Ilu& F, const char** msg);
+void ilu_apply(const Ilu& F, const double* r, double* z);
 
 }  // namespace orc

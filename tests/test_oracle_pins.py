@@ -492,6 +492,87 @@ def test_idrs_terminates_within_m_plus_m_over_s(m, s):
     assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8)
 
 
+# ---------------------------------------------------------------- block ILU(k)
+
+def split_lu(Fd, b):
+    nb = Fd.shape[0] // b
+    blk = np.kron(np.arange(nb), np.ones(b, int))
+    lower = blk[:, None] > blk[None, :]
+    L = np.where(lower, Fd, 0.0) + np.eye(Fd.shape[0])
+    U = np.where(~lower, Fd, 0.0)
+    return L, U
+
+
+def test_ilu0_of_tridiagonal_is_exact_lu():
+    """No fill is dropped for a tridiagonal matrix: L U = A, and with as many sweeps as
+    rows the Jacobi-iterated triangular solves are exact."""
+    m = 11
+    A = sp.csr_matrix(chain(m) + sp.diags(np.linspace(0.1, 0.6, m - 1), 1))
+    s = oracle.Solver(A, 1, kind=oracle.KIND_ILU, ilu_level=0, ilu_sweeps=m)
+    L, U = split_lu(dense(s.ilu_factor()), 1)
+    assert np.allclose(L @ U, dense(A), atol=1e-14)
+    r = np.random.default_rng(8).normal(size=m)
+    assert np.allclose(s.precond(r), np.linalg.solve(dense(A), r), rtol=1e-12)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_ilu_reproduces_a_on_its_pattern(level):
+    """The defining property of ILU: (L U)_ij = A_ij on the stored block pattern, which
+    contains A's pattern (plus level-1 fill for ILU(1)); block rows of 4x4."""
+    n = 5
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 3))
+    s = oracle.Solver(A, 4, kind=oracle.KIND_ILU, ilu_level=level, ilu_sweeps=2)
+    F = s.ilu_factor()
+    L, U = split_lu(dense(F), 4)
+    Ad = dense(A)
+    blk = np.kron(np.arange(n ** 3), np.ones(4, int))
+    # block pattern of the factor
+    Fc, Ac = F.tocoo(), A.tocoo()          # stored entries, explicit zeros included
+    Fb = sp.csr_matrix((np.ones(Fc.nnz), (blk[Fc.row], blk[Fc.col])))
+    Ab = sp.csr_matrix((np.ones(Ac.nnz), (blk[Ac.row], blk[Ac.col])))
+    Fb.data[:] = 1.0
+    Ab.data[:] = 1.0
+    assert (Ab.multiply(Fb) != Ab).nnz == 0           # A's pattern is inside the factor's
+    mask = np.kron(dense(Fb) != 0, np.ones((4, 4), bool))
+    LU = L @ U
+    assert np.abs((LU - Ad)[mask]).max() <= 1e-12 * np.abs(Ad).max()
+    if level == 1:
+        assert Fb.nnz > Ab.nnz                        # fill was kept
+        F0 = oracle.Solver(A, 4, kind=oracle.KIND_ILU, ilu_level=0).ilu_factor()
+        L0, U0 = split_lu(dense(F0), 4)
+        # the level-1 factor is the better approximation of A
+        assert np.linalg.norm(LU - Ad) < np.linalg.norm(L0 @ U0 - Ad)
+
+
+def test_ilu_sweeps_limit_and_zero_sweeps():
+    """Enough sweeps reach the exact solve with the factors; zero sweeps leave block
+    Jacobi with the pivot blocks, z = D^-1 r."""
+    n = 4
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 4))
+    r = np.random.default_rng(9).normal(size=A.shape[0])
+    many = oracle.Solver(A, 4, kind=oracle.KIND_ILU, ilu_level=1, ilu_sweeps=n ** 3)
+    L, U = split_lu(dense(many.ilu_factor()), 4)
+    assert np.allclose(many.precond(r), np.linalg.solve(U, np.linalg.solve(L, r)), rtol=1e-10)
+    zero = oracle.Solver(A, 4, kind=oracle.KIND_ILU, ilu_level=1, ilu_sweeps=0)
+    Dm = np.zeros_like(U)
+    for i in range(n ** 3):
+        Dm[4 * i:4 * i + 4, 4 * i:4 * i + 4] = U[4 * i:4 * i + 4, 4 * i:4 * i + 4]
+    assert np.allclose(zero.precond(r), np.linalg.solve(Dm, r), rtol=1e-12)
+
+
+def test_idrs_with_ilu1_reaches_dense_solution():
+    """The paper's monolithic configuration (IDR(5) with ILU(1)) on a small system."""
+    n = 6
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 5))
+    b = A @ S.mms_solution(n)
+    s = oracle.Solver(A, 4, kind=oracle.KIND_ILU, ilu_level=1, ilu_sweeps=3,
+                      krylov=oracle.IDRS, idr_s=5)
+    x, info = s.solve(b, 1e-11)
+    xd = np.linalg.solve(dense(A), b)
+    assert info["converged"]
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
 def test_bicgstab_edge_cases():
     n = 5
     A = oracle.stokes_matrix(n)
