@@ -147,7 +147,9 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
     paper_schur64 - the 64^3 log-normal system with the paper's Schur configuration:
                IDR(5), velocity AMG with plain aggregation, pressure step one SPAI(0)
                application of the diagonal Schur approximation, full factorization;
-               FP64, FP32 and BF16 hierarchy values.
+               FP64, FP32 and BF16 hierarchy values;
+    ilu48    - 48^3 manufactured-plus-noise system: IDR(5) with block ILU(1) (3 Jacobi
+               sweeps per factor; FP64 and FP32 factors) against IDR(5) with the AMG.
     All hierarchies are FP32 unless stated; rtol 1e-8 (adjoint workload 1e-10)."""
     import numpy as np
     stream = torch.cuda.current_stream()
@@ -353,6 +355,31 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
             del sv
             torch.cuda.empty_cache()
 
+    if "ilu48" in which:
+        # the paper's monolithic configuration (IDR(5) with ILU(1)) against IDR(5) with the
+        # smoothed-aggregation AMG, on the 48^3 manufactured-plus-noise system
+        n = 48
+        ptr, col, val = mgk.stokes_bsr(n)
+        b = torch.from_numpy(S.c2_rhs(n)).cuda()
+        r = {}
+        for tag, kind, kw in (("ilu1_f64", mgk.ILU, dict(ilu_level=1, ilu_sweeps=3)),
+                              ("ilu1_f32", mgk.ILU, dict(ilu_level=1, ilu_sweeps=3, hier=mgk.F32)),
+                              ("amg_f32", mgk.AMG_SPAI0, dict(hier=mgk.F32))):
+            t0 = time.perf_counter()
+            sv = solver(ptr, col, val, kind, krylov=mgk.IDRS, idr_s=5, maxiter=4000, **kw)
+            t_setup = time.perf_counter() - t0
+            x = torch.zeros_like(b)
+
+            def run():
+                x.zero_()
+                return sv.solve(b, x, 1e-8)
+            t, info = _median_solve(run, torch, steps=1, warmup=1)
+            r[tag] = {"solve_s": t, "iters": info["iters"], "status": info["status"],
+                      "setup_s": t_setup}
+            log_fn(f"ilu48 {tag}: {t:.3f}s, {info['iters']} iterations, status {info['status']}")
+            del sv
+        out["ilu48_idrs"] = r
+
     if "paper_schur64" in which:
         n = 64
         ptr, col, val = mgk.stokes_bsr(n, S.theta_field(n, 1.0, 3))
@@ -448,7 +475,7 @@ def main():
                     help="also run the three BSR arms over this many right-hand-side seeds")
     ap.add_argument("--secondary",
                     default="schur64,multi64,batch8,batch32small,adjoint48,idrs96,plain96,"
-                            "paper_schur64",
+                            "paper_schur64,ilu48",
                     help="other solve shapes timed after the headline (empty: none)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the FP64 BSR SpMV loop")

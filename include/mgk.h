@@ -52,8 +52,12 @@ typedef enum {
  *  MGK_SCHUR      Schur-complement pressure correction (Section 4, eqs.
  *                 SchurP and SchurU) for interleaved [u,v,w,p] unknowns
  *                 (block size 4): velocity AMG on the 3x3 block A_uu, scalar
- *                 pressure AMG on S = C - B_lo diag(A_uu)^-1 B_up. */
-typedef enum { MGK_AMG_SPAI0 = 0, MGK_AMG_JACOBI = 1, MGK_SCHUR = 2 } mgk_precond_kind;
+ *                 pressure AMG on S = C - B_lo diag(A_uu)^-1 B_up.
+ *  MGK_ILU        block ILU(k), k = mgk_params.ilu_level in {0, 1}, of the
+ *                 whole system (the paper's monolithic variant uses ILU(1) under
+ *                 IDR(5), Section 4), applied with mgk_params.ilu_sweeps Jacobi
+ *                 sweeps on each triangular factor. */
+typedef enum { MGK_AMG_SPAI0 = 0, MGK_AMG_JACOBI = 1, MGK_SCHUR = 2, MGK_ILU = 3 } mgk_precond_kind;
 
 /* Storage precision of the preconditioner hierarchy values (Section 4, the
  * mixed-precision variant: single-precision nested solvers under a double
@@ -115,6 +119,8 @@ typedef struct {
                               SchurU (two velocity cycles); 1 lower block factorization
                               (one velocity cycle, the PETSc LOWER variant of Section 4) */
   int32_t idr_s;           /* shadow space dimension of MGK_IDRS, 1..16, default 5 */
+  int32_t ilu_level;       /* MGK_ILU fill level k in {0, 1}, default 0 */
+  int32_t ilu_sweeps;      /* MGK_ILU Jacobi sweeps per triangular factor, 0..64, default 2 */
   int32_t reserved;
 } mgk_params;
 
@@ -220,6 +226,15 @@ int mgk_spmv(mgk_solver* s, int32_t hier, int32_t level, int32_t which, const vo
 
 /* z = B r for one preconditioner application (FP64 in and out). */
 int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t transposed);
+
+/* Block ILU factor inspection (MGK_ILU solvers set up with prm->keep_host, or
+ * with mgk_setup_host): sizes, then which 0 = L (blocks strictly below the
+ * diagonal), 1 = U (strictly above), as BSR with n_brows + 1 row pointers and
+ * row-major b x b blocks; which 2 = the n_brows pivot inverses U(i,i)^-1 in val.
+ * Arrays are caller-allocated; null arrays are skipped.  MGK_E_STATE if no
+ * factors were kept. */
+int mgk_ilu_info(mgk_solver* s, int32_t* n_brows, int64_t* l_nnzb, int64_t* u_nnzb);
+int mgk_ilu_export(mgk_solver* s, int32_t which, int32_t* rowptr, int32_t* col, double* val);
 
 /* Hierarchy inspection (host copies need prm->keep_host).  hier 0: the
  * monolithic or velocity hierarchy, 1: the pressure hierarchy (MGK_SCHUR). */

@@ -83,6 +83,8 @@ def lib():
         L.orc_idr_shadow.argtypes = [C.c_int64, C.c_int, P]
         L.orc_ilu_factor.argtypes = [P, P, P, P]
         L.orc_ilu_factor.restype = C.c_int64
+        L.orc_ilu_dinv.argtypes = [P, P]
+        L.orc_ilu_dinv.restype = None
         L.orc_idr_shadow.restype = None
         L.orc_gather_block_row.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int64, P, P,
                                            C.c_int32]
@@ -194,6 +196,12 @@ class Solver:
         val = np.zeros(max(nz, 1), np.float64)
         L.orc_ilu_factor(self._h, _p(ptr), _p(col), _p(val))
         return sp.csr_matrix((val[:nz], col[:nz], ptr), shape=(self.n, self.n))
+
+    def ilu_dinv(self) -> np.ndarray:
+        """Inverses of the ILU pivot blocks, (n / b, b, b)."""
+        out = np.zeros(self.n * self.block, np.float64)
+        lib().orc_ilu_dinv(self._h, _p(out))
+        return out.reshape(self.n // self.block, self.block, self.block)
 
     def nlevels(self, which: int = 0) -> int:
         return lib().orc_nlevels(self._h, which)

@@ -298,6 +298,10 @@ extern "C" int64_t orc_ilu_factor(orc_solver* s, int64_t* ptr, int32_t* col, dou
   return nz;
 }
 
+extern "C" void orc_ilu_dinv(orc_solver* s, double* out) {
+  std::copy(s->F.Dinv.begin(), s->F.Dinv.end(), out);
+}
+
 extern "C" void orc_idr_shadow(int64_t n, int s, double* out) {
   const std::vector<double> P = idr_shadow(n, s);
   std::copy(P.begin(), P.end(), out);

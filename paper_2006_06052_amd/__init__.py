@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgk.so")
 
 MGK_OK, MGK_NOT_CONVERGED = 0, 1
-AMG_SPAI0, AMG_JACOBI, SCHUR = 0, 1, 2
+AMG_SPAI0, AMG_JACOBI, SCHUR, ILU = 0, 1, 2, 3
 F64, F32, BF16 = 0, 1, 2
 BICGSTAB, FGMRES, IDRS = 0, 1, 2
 SMOOTHED_AGGREGATION, PLAIN_AGGREGATION = 0, 1
@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("time_spmv", C.c_int32), ("force_tile", C.c_int32),
                 ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -66,8 +66,8 @@ class LevelDesc(C.Structure):
 EXPORTS = ["mgk_params_default", "mgk_stokes_sizes", "mgk_stokes_assemble", "mgk_csr_to_bsr",
            "mgk_setup", "mgk_setup_host", "mgk_solve", "mgk_solve_transposed", "mgk_solve_multi",
            "mgk_batch_setup", "mgk_batch_solve", "mgk_spmv", "mgk_precond_apply",
-           "mgk_level_count", "mgk_level_info", "mgk_level_export", "mgk_theta_grad",
-           "mgk_bsr_grad", "mgk_destroy", "mgk_last_error"]
+           "mgk_level_count", "mgk_level_info", "mgk_level_export", "mgk_ilu_info",
+           "mgk_ilu_export", "mgk_theta_grad", "mgk_bsr_grad", "mgk_destroy", "mgk_last_error"]
 
 _lib = None
 
@@ -89,6 +89,8 @@ def lib():
     L.mgk_setup.argtypes = [C.POINTER(_Bsr), I32, I32, C.POINTER(Params), P, C.POINTER(P)]
     L.mgk_setup_host.argtypes = [C.POINTER(_Bsr), I32, I32, C.POINTER(Params), C.POINTER(P)]
     L.mgk_solve.argtypes = [P, P, P, D, C.POINTER(Info)]
+    L.mgk_ilu_info.argtypes = [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64)]
+    L.mgk_ilu_export.argtypes = [P, I32, P, P, P]
     L.mgk_solve_transposed.argtypes = [P, P, P, D, C.POINTER(Info)]
     L.mgk_solve_multi.argtypes = [P, I32, P, P, D, P]
     L.mgk_batch_setup.argtypes = [I32, P, I32, I32, C.POINTER(Params), P, C.POINTER(P)]
@@ -289,6 +291,30 @@ class Solver:
         if rc:
             _err(rc)
         return {k: getattr(d, k) for k, _ in d._fields_ if k != "pad"}
+
+    def ilu_export(self):
+        """Host FP64 block ILU factors: (L, U) as (rowptr, col, val[nnzb, b, b]) and Dinv."""
+        L = lib()
+        nb = C.c_int32()
+        ln, un = C.c_int64(), C.c_int64()
+        rc = L.mgk_ilu_info(self._h, C.byref(nb), C.byref(ln), C.byref(un))
+        if rc:
+            _err(rc)
+        b = self.block
+        out = []
+        for which, nz in ((0, ln.value), (1, un.value)):
+            ptr = np.zeros(nb.value + 1, np.int32)
+            col = np.zeros(max(nz, 1), np.int32)
+            val = np.zeros(max(nz, 1) * b * b, np.float64)
+            rc = L.mgk_ilu_export(self._h, which, _np_ptr(ptr), _np_ptr(col), _np_ptr(val))
+            if rc:
+                _err(rc)
+            out.append((ptr, col[:nz], val[:nz * b * b].reshape(nz, b, b)))
+        dinv = np.zeros(nb.value * b * b, np.float64)
+        rc = L.mgk_ilu_export(self._h, 2, None, None, _np_ptr(dinv))
+        if rc:
+            _err(rc)
+        return out[0], out[1], dinv.reshape(nb.value, b, b)
 
     def level_export(self, level: int, which: int = 0, hier: int = 0):
         """Host FP64 copy (rowptr, col, val) of A_l (0), P_l (1) or R_l (2), plus aggregates."""

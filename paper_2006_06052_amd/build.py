@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libmgk.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HOST_SOURCES = ["setup.cpp", "ingest.cpp"]
+HOST_SOURCES = ["setup.cpp", "ingest.cpp", "ilu.cpp"]
 HIP_SOURCES = ["solver.hip", "multi.hip", "batch.hip", "idrs.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              # no automatic FMA contraction: kernels write their FMAs explicitly, so

@@ -68,6 +68,14 @@ int schur_split(const HBsr& A, bool diag_only, SchurParts& out, std::string& err
 // Scalar SPAI(0) of a 1x1-block matrix: m_i = a_ii / sum_j a_ij^2 (ascending j).
 int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err);
 
+// Block ILU(k) factors (k = 0 or 1): L strictly below, U strictly above the
+// diagonal blocks, Dinv the inverses of U's diagonal blocks (ilu.cpp).
+struct IluFactors {
+  HBsr L, U;
+  std::vector<double> Dinv;
+};
+int ilu_factor(const HBsr& A, int level, IluFactors& out, std::string& err);
+
 // Ingest helpers.
 int csr_to_bsr(int32_t nrows, const int32_t* ptr, const int32_t* col, const double* val,
                int b, HBsr& out, std::string& err);

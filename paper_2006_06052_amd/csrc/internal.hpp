@@ -459,6 +459,11 @@ struct mgk_solver {
   DHier Hp;                  // pressure hierarchy (Schur)
   DMat Blo, Bup;             // Schur couplings in storage precision
   void* Sm = nullptr;        // scalar SPAI(0) of the pressure operator (schur_spai0)
+  DMat Lf, Uf;               // ILU factors (strict lower / upper), storage precision
+  void* Dinv = nullptr;      // ILU pivot inverses (FP64, or FP32 for low-precision storage)
+  void *iy = nullptr, *iy2 = nullptr, *iw = nullptr, *iz = nullptr;  // ILU sweep vectors
+  IluFactors ilu_host;       // FP64 factors kept for mgk_ilu_export (keep_host / host only)
+  bool ilu_kept = false;
   void *ru = nullptr, *rp = nullptr, *tu = nullptr, *tp = nullptr, *zu = nullptr, *zp = nullptr;
   // Krylov workspace (FP64)
   double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *ph = nullptr, *s = nullptr,

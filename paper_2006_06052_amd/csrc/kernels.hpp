@@ -766,6 +766,13 @@ static __global__ __launch_bounds__(WG) void k_update_x(size_t n, int m, const d
 
 // ---- Schur split / merge --------------------------------------------------------
 
+// out = (TO) in.
+template <class TI, class TO>
+__global__ __launch_bounds__(WG) void k_cast(size_t n, const TI* __restrict__ in,
+                                             TO* __restrict__ out) {
+  GRID_STRIDE(i, n) out[i] = (TO)in[i];
+}
+
 // y = m .* x (diagonal preconditioner step).
 template <class T>
 __global__ __launch_bounds__(WG) void k_diag_mul(size_t n, const T* __restrict__ m,

@@ -307,7 +307,55 @@ static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
   k_merge<TX><<<grid_for(nn), WG, 0, st>>>(nn, zu, zp, z);
 }
 
+// Block ILU apply with Jacobi sweeps on the factors, in the storage precision:
+// (I + L) y = r by y = r, then sweeps x y <- r - L y; (D + U) z = y by z = Dinv y,
+// then sweeps x z <- Dinv (y - U z).  The last product writes the FP64 output.
+template <int B, class TV, class TX>
+static void ilu_apply_b(mgk_solver* S, const double* r, double* z) {
+  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+  using TA = AccOf<TV>;
+  hipStream_t st = S->dev.stream;
+  const size_t n = S->n;
+  const int nbr = S->nbr, sw = S->prm.ilu_sweeps, gb = grid_for(n);
+  TX *y = (TX*)S->iy, *y2 = (TX*)S->iy2, *w = (TX*)S->iw, *zt = (TX*)S->iz;
+  const TM* Dinv = (const TM*)S->Dinv;
+  const int gd = (int)((n + WG - 1) / WG);
+  k_cast<double, TX><<<gb, WG, 0, st>>>(n, r, y);
+  for (int q = 0; q < sw; ++q) {
+    residual_s<B, B, TV, TX, double>(st, S->Lf, false, S->Lf.tile, r, y, y2);
+    std::swap(y, y2);
+  }
+  if (sw == 0) {
+    k_block_diag<B, TM, TX, double, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, y, z);
+    return;
+  }
+  k_block_diag<B, TM, TX, TX, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, y, zt);
+  for (int q = 0; q < sw; ++q) {
+    residual_s<B, B, TV, TX, TX>(st, S->Uf, false, S->Uf.tile, y, zt, w);
+    if (q + 1 == sw)
+      k_block_diag<B, TM, TX, double, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, w, z);
+    else
+      k_block_diag<B, TM, TX, TX, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, w, zt);
+  }
+}
+
+template <class TV, class TX>
+static void ilu_apply_t(mgk_solver* S, const double* r, double* z) {
+  switch (S->b) {
+    case 1: ilu_apply_b<1, TV, TX>(S, r, z); break;
+    case 3: ilu_apply_b<3, TV, TX>(S, r, z); break;
+    case 4: ilu_apply_b<4, TV, TX>(S, r, z); break;
+  }
+}
+
 void precond(mgk_solver* S, const double* r, double* z, bool trans) {
+  if (S->kind == MGK_ILU) {
+    if (trans) throw Error(MGK_E_STATE, "transposed ILU preconditioner is not available");
+    if (S->prm.hier == MGK_F64) ilu_apply_t<double, double>(S, r, z);
+    else if (S->prm.hier == MGK_F32) ilu_apply_t<float, float>(S, r, z);
+    else ilu_apply_t<bf16, float>(S, r, z);
+    return;
+  }
   if (S->kind == MGK_SCHUR) {
     if (trans) throw Error(MGK_E_STATE, "transposed Schur preconditioner is not available");
     if (S->H.storage == MGK_F64) schur_apply_t<double, double>(S, r, z);
@@ -599,7 +647,10 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   if (!A || !prm) throw Error(MGK_E_INVALID, "null matrix or params");
   if (A->block != block_size || (block_size != 1 && block_size != 3 && block_size != 4))
     throw Error(MGK_E_INVALID, "block_size must equal A->block and be 1, 3 or 4");
-  if (kind < MGK_AMG_SPAI0 || kind > MGK_SCHUR) throw Error(MGK_E_INVALID, "unknown kind");
+  if (kind < MGK_AMG_SPAI0 || kind > MGK_ILU) throw Error(MGK_E_INVALID, "unknown kind");
+  if (kind == MGK_ILU && (prm->ilu_level < 0 || prm->ilu_level > 1 || prm->ilu_sweeps < 0 ||
+                          prm->ilu_sweeps > 64))
+    throw Error(MGK_E_INVALID, "MGK_ILU needs ilu_level in {0, 1} and 0 <= ilu_sweeps <= 64");
   if (kind == MGK_SCHUR && block_size != 4)
     throw Error(MGK_E_INVALID, "MGK_SCHUR needs interleaved [u,v,w,p] (block size 4)");
   if (prm->hier < MGK_F64 || prm->hier > MGK_BF16) throw Error(MGK_E_INVALID, "unknown storage");
@@ -637,7 +688,10 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     // hierarchy only, kept on the host for inspection; no device work
     const SetupParams sp = setup_params(*prm, kind);
     int rc;
-    if (kind == MGK_SCHUR) {
+    if (kind == MGK_ILU) {
+      if ((rc = ilu_factor(H, prm->ilu_level, S->ilu_host, err))) throw Error(rc, err);
+      S->ilu_kept = true;
+    } else if (kind == MGK_SCHUR) {
       SchurParts parts;
       if ((rc = schur_split(H, prm->schur_approx != 0, parts, err))) throw Error(rc, err);
       if ((rc = build_hierarchy(parts.Auu, sp, S->H.host, err))) throw Error(rc, err);
@@ -659,7 +713,30 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   tune_mat(S->dev, S->A, MGK_F64, tr);
   const SetupParams sp = setup_params(*prm, kind);
   int rc;
-  if (kind == MGK_SCHUR) {
+  if (kind == MGK_ILU) {
+    IluFactors f;
+    if ((rc = ilu_factor(H, prm->ilu_level, f, err))) throw Error(rc, err);
+    S->Lf = upload_mat(S->dev, f.L, prm->hier, false);
+    S->Uf = upload_mat(S->dev, f.U, prm->hier, false);
+    tune_mat(S->dev, S->Lf, prm->hier, false);
+    tune_mat(S->dev, S->Uf, prm->hier, false);
+    if (prm->hier == MGK_F64) {
+      S->Dinv = S->dev.upload(f.Dinv.data(), f.Dinv.size());
+    } else {
+      std::vector<float> d(f.Dinv.begin(), f.Dinv.end());
+      S->Dinv = S->dev.upload(d.data(), d.size());
+    }
+    if (prm->keep_host) {
+      S->ilu_host = std::move(f);
+      S->ilu_kept = true;
+    }
+    const size_t xs = prm->hier == MGK_F64 ? 8 : 4;
+    S->iy = S->dev.alloc(S->n * xs);
+    S->iy2 = S->dev.alloc(S->n * xs);
+    S->iw = S->dev.alloc(S->n * xs);
+    S->iz = S->dev.alloc(S->n * xs);
+    HIPCK(hipStreamSynchronize(S->dev.stream));
+  } else if (kind == MGK_SCHUR) {
     SchurParts parts;
     if ((rc = schur_split(H, prm->schur_approx != 0, parts, err))) throw Error(rc, err);
     HHierarchy hu, hp;
@@ -738,6 +815,8 @@ int mgk_params_default(mgk_params* p) {
   p->enable_transpose = 0;
   p->coarsening = MGK_SMOOTHED_AGGREGATION;
   p->idr_s = 5;
+  p->ilu_level = 0;
+  p->ilu_sweeps = 2;
   return MGK_OK;
 }
 
@@ -816,7 +895,7 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     mgk::g_err = "solve: solver was set up with mgk_setup_host (no device data)";
     return MGK_E_STATE;
   }
-  if (trans && (s->kind == MGK_SCHUR || !s->H.trans_ready)) {
+  if (trans && (s->kind == MGK_SCHUR || s->kind == MGK_ILU || !s->H.trans_ready)) {
     mgk::g_err = "solve_transposed needs a monolithic AMG solver set up with enable_transpose";
     return MGK_E_STATE;
   }
@@ -870,7 +949,7 @@ int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t tra
     mgk::g_err = "precond_apply: solver has no device data";
     return MGK_E_STATE;
   }
-  if (transposed && (s->kind == MGK_SCHUR || !s->H.trans_ready)) {
+  if (transposed && (s->kind == MGK_SCHUR || s->kind == MGK_ILU || !s->H.trans_ready)) {
     mgk::g_err = "transposed preconditioner needs enable_transpose and a monolithic AMG";
     return MGK_E_STATE;
   }
@@ -974,6 +1053,36 @@ int mgk_level_export(mgk_solver* s, int32_t hier, int32_t level, int32_t which, 
   if (agg) {
     for (int32_t i = 0; i < L.A.nbr; ++i) agg[i] = L.agg.empty() ? -1 : L.agg[i];
   }
+  return MGK_OK;
+}
+
+int mgk_ilu_info(mgk_solver* s, int32_t* n_brows, int64_t* l_nnzb, int64_t* u_nnzb) {
+  if (!s || !n_brows || !l_nnzb || !u_nnzb) return MGK_E_INVALID;
+  if (!s->ilu_kept) {
+    mgk::g_err = "ilu_info needs an MGK_ILU solver set up with keep_host = 1 (or host only)";
+    return MGK_E_STATE;
+  }
+  *n_brows = s->ilu_host.L.nbr;
+  *l_nnzb = s->ilu_host.L.nnzb();
+  *u_nnzb = s->ilu_host.U.nnzb();
+  return MGK_OK;
+}
+
+int mgk_ilu_export(mgk_solver* s, int32_t which, int32_t* rowptr, int32_t* col, double* val) {
+  if (!s || which < 0 || which > 2) return MGK_E_INVALID;
+  if (!s->ilu_kept) {
+    mgk::g_err = "ilu_export needs an MGK_ILU solver set up with keep_host = 1 (or host only)";
+    return MGK_E_STATE;
+  }
+  const mgk::IluFactors& F = s->ilu_host;
+  if (which == 2) {
+    if (val) std::memcpy(val, F.Dinv.data(), sizeof(double) * F.Dinv.size());
+    return MGK_OK;
+  }
+  const mgk::HBsr& M = which == 0 ? F.L : F.U;
+  if (rowptr) std::memcpy(rowptr, M.ptr.data(), sizeof(int32_t) * M.ptr.size());
+  if (col) std::memcpy(col, M.col.data(), sizeof(int32_t) * M.col.size());
+  if (val) std::memcpy(val, M.val.data(), sizeof(double) * M.val.size());
   return MGK_OK;
 }
 

@@ -141,6 +141,26 @@ def test_host_setup_matches_oracle_schur_diagonal_approximation():
     assert hs2.nlevels(1) == 0 and hs2.nlevels(0) >= 2
 
 
+@pytest.mark.parametrize("n,level", [(6, 0), (9, 1), (7, 1)])
+def test_host_ilu_factors_match_oracle_bitwise(n, level):
+    """Block ILU(k) host factorization: L and U blocks and the pivot inverses bit-exact."""
+    th = S.theta_field(n, 0.5, 3 + n)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    hs = host_solver(ptr, col, val, 4, mgk.ILU, ilu_level=level)
+    (lp, lc, lv), (up, uc, uv), dinv = hs.ilu_export()
+    so = oracle.Solver(oracle.stokes_matrix(n, th), 4, kind=oracle.KIND_ILU, ilu_level=level)
+    F = so.ilu_factor()
+    optr, ocol, oval = oracle_blocks(F, 4)
+    nb = n ** 3
+    for i in range(nb):
+        oc = ocol[optr[i]:optr[i + 1]]
+        ov = oval[optr[i]:optr[i + 1]]
+        lo, up_ = oc < i, oc > i
+        assert np.array_equal(lc[lp[i]:lp[i + 1]], oc[lo]) and np.array_equal(lv[lp[i]:lp[i + 1]], ov[lo])
+        assert np.array_equal(uc[up[i]:up[i + 1]], oc[up_]) and np.array_equal(uv[up[i]:up[i + 1]], ov[up_])
+    assert np.array_equal(dinv, so.ilu_dinv())
+
+
 def test_host_setup_scalar_csr_arm():
     """The whole setup at block size 1 on the scalar CSR matrix (V2-style scalar arm)."""
     n = 8
@@ -180,6 +200,13 @@ def test_invalid_input_rejected_before_device_work():
     assert e.value.code == -1
     with pytest.raises(mgk.MgkError):
         host_solver(ptr, col, val, 4, maxiter=0)
+    with pytest.raises(mgk.MgkError):
+        host_solver(ptr, col, val, 4, mgk.ILU, ilu_level=2)
+    with pytest.raises(mgk.MgkError):
+        host_solver(ptr, col, val, 4, mgk.ILU, ilu_sweeps=-1)
+    with pytest.raises(mgk.MgkError) as e:
+        host_solver(ptr, col, val, 4).ilu_export()     # not an ILU solver
+    assert e.value.code == -5
     for bad_kw in (dict(krylov=mgk.IDRS, idr_s=0), dict(krylov=mgk.IDRS, idr_s=17),
                    dict(krylov=3), dict(coarsening=2), dict(schur_lower=2)):
         with pytest.raises(mgk.MgkError) as e:

@@ -1,6 +1,7 @@
-"""GPU parity of the solver variants: plain aggregation, IDR(s), and the Schur
+"""GPU parity of the solver variants: plain aggregation, IDR(s), the Schur
 pressure-correction options (diagonal approximation of the pressure operator,
-SPAI(0) pressure step, lower factorization), against the FP64 CPU oracle.
+SPAI(0) pressure step, lower factorization), and the block ILU(k) preconditioner
+with Jacobi-iterated triangular solves, against the FP64 CPU oracle.
 
 Bars as for the other parity tests: ||b - A x|| / ||b|| <= 1e-8 with the oracle's
 SpMV, and agreement with the oracle's FP64 solve (rtol 1e-12) to 1e-6 relative.
@@ -156,3 +157,44 @@ def test_paper_schur_configuration_idrs(storage):
     say("paper schur", storage, info, oi["iters"])
     assert info["status"] == 0
     check_solution(A, b, dx.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("level,sweeps", [(0, 2), (1, 3), (1, 0)])
+def test_ilu_application_matches_oracle(level, sweeps):
+    """Block ILU(k) with Jacobi-iterated triangular solves: the FP64 application agrees
+    with the oracle's to rounding."""
+    n = 10
+    th, bsr, A = problem(n, 0.5, 15)
+    kw = dict(ilu_level=level, ilu_sweeps=sweeps)
+    s = gpu_solver(bsr, mgk.ILU, **kw)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_ILU, **kw)
+    r = np.random.default_rng(5).normal(size=A.shape[0])
+    dz = torch.empty(A.shape[0], dtype=torch.float64, device=DEV)
+    s.precond(dev(r), dz)
+    zo = so.precond(r)
+    assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-12 * np.linalg.norm(zo)
+    with pytest.raises(mgk.MgkError):
+        s.precond(dev(r), dz, transposed=True)
+
+
+@pytest.mark.parametrize("storage,krylov", [("f64", "idrs"), ("f32", "idrs"), ("bf16", "idrs"),
+                                            ("f64", "bicgstab")])
+def test_paper_monolithic_ilu_configuration(storage, krylov):
+    """The paper's monolithic configuration, IDR(5) preconditioned with ILU(1), and
+    BiCGStab with ILU(1), on a small system (ILU alone does not scale with size)."""
+    n = 10
+    th, bsr, A = problem(n, 0.5, 16)
+    b = oracle.spmv(A, S.mms_solution(n))
+    kr = {"idrs": (mgk.IDRS, oracle.IDRS), "bicgstab": (mgk.BICGSTAB, oracle.BICGSTAB)}[krylov]
+    kw = dict(ilu_level=1, ilu_sweeps=3)
+    s = gpu_solver(bsr, mgk.ILU, hier=storage, krylov=kr[0], idr_s=5, **kw)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_ILU, krylov=kr[1], idr_s=5, **kw)
+    xo, oi = so.solve(b, 1e-12)
+    say("ilu", storage, krylov, info["iters"], oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+    B = torch.zeros((A.shape[0], 2), dtype=torch.float64, device=DEV)
+    with pytest.raises(mgk.MgkError):
+        s.solve_multi(B, torch.zeros_like(B), 1e-8)
