@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liborc.so")
 SOURCES = ["csr.cpp", "stokes.cpp", "amg.cpp", "krylov.cpp", "ilu.cpp", "capi.cpp"]
 
 KIND_AMG, KIND_SCHUR, KIND_IDENTITY, KIND_ILU = 0, 1, 2, 3
-SPAI0_BLOCK, JACOBI, SPAI0_SCALAR = 0, 1, 2
+SPAI0_BLOCK, JACOBI, SPAI0_SCALAR, ILU0 = 0, 1, 2, 3
 BICGSTAB, FGMRES, IDRS = 0, 1, 2
 SMOOTHED, PLAIN = 0, 1
 

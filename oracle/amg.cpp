@@ -320,7 +320,9 @@ bool amg_build(const Csr& A, int b, const AmgParams& prm, Hierarchy& H, const ch
       }
       return true;
     }
-    if (!build_smoother(L.A, b, prm, L.M)) {
+    if (prm.smoother == ILU0) {
+      if (!ilu_build(L.A, b, 0, prm.ilu_sweeps, L.F, msg)) return false;
+    } else if (!build_smoother(L.A, b, prm, L.M)) {
       *msg = "oracle: singular smoother block";
       return false;
     }
@@ -332,6 +334,11 @@ bool amg_build(const Csr& A, int b, const AmgParams& prm, Hierarchy& H, const ch
 
 bool amg_transpose(const Hierarchy& H, Hierarchy& Ht, const char** msg) {
   const int b = H.b;
+  for (const Level& L : H.levels)
+    if (!L.F.cols.empty()) {
+      *msg = "oracle: no transposed cycle with the ILU smoother";
+      return false;
+    }
   Ht.b = b;
   Ht.transposed = true;
   Ht.levels.resize(H.levels.size());
@@ -379,7 +386,9 @@ void vcycle(const Hierarchy& H, int l, const double* r, double* z) {
   }
   const int b = H.b;
   std::vector<double> t(n), rc(L.P.nc), zc(L.P.nc), pz(n);
-  apply_M(b, L.M, r, z, false);
+  const bool ilu = !L.F.cols.empty();
+  if (ilu) ilu_apply(L.F, r, z);   // z = ILU^-1 r
+  else apply_M(b, L.M, r, z, false);
   spmv(L.A, z, t.data());
   for (i64 i = 0; i < n; ++i) t[i] = r[i] - t[i];
   spmv(L.R, t.data(), rc.data());
@@ -388,7 +397,13 @@ void vcycle(const Hierarchy& H, int l, const double* r, double* z) {
   for (i64 i = 0; i < n; ++i) z[i] = z[i] + pz[i];
   spmv(L.A, z, t.data());
   for (i64 i = 0; i < n; ++i) t[i] = r[i] - t[i];
-  apply_M(b, L.M, t.data(), z, true);
+  if (ilu) {
+    std::vector<double> w(n);
+    ilu_apply(L.F, t.data(), w.data());
+    for (i64 i = 0; i < n; ++i) z[i] = z[i] + w[i];
+  } else {
+    apply_M(b, L.M, t.data(), z, true);
+  }
 }
 
 }  // namespace orc

@@ -53,7 +53,7 @@ struct orc_params {
   double eps_strong;
   int32_t coarse_enough;
   int32_t max_levels;
-  int32_t smoother;      // 0 block SPAI0, 1 damped Jacobi, 2 scalar SPAI0
+  int32_t smoother;      // 0 block SPAI0, 1 damped Jacobi, 2 scalar SPAI0, 3 block ILU(0)
   int32_t kind;          // 0 monolithic AMG, 1 Schur pressure correction, 2 identity
   double jacobi_omega;
   int32_t coarsening;    // 0 smoothed aggregation, 1 plain aggregation
@@ -121,6 +121,7 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
     s->aprm.smoother = prm->smoother;
     s->aprm.jacobi_omega = prm->jacobi_omega;
     s->aprm.smooth_p = prm->coarsening == 0;
+    s->aprm.ilu_sweeps = prm->ilu_sweeps;
     if (prm->krylov == 2 && (prm->idr_s < 1 || prm->idr_s > 32)) {
       g_err = "oracle: IDR(s) needs 1 <= s <= 32";
       return nullptr;

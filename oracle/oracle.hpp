@@ -71,7 +71,7 @@ void stokes_assemble(int n, const double* theta, Csr& A);
 void theta_gradient(int n, const double* lambda, const double* x, double* g);
 
 // ---- smoothed-aggregation hierarchy (amg.cpp) ----------------------------
-enum Smoother { SPAI0_BLOCK = 0, JACOBI = 1, SPAI0_SCALAR = 2 };
+enum Smoother { SPAI0_BLOCK = 0, JACOBI = 1, SPAI0_SCALAR = 2, ILU0 = 3 };
 
 struct AmgParams {
   double eps_strong = 0.08;
@@ -80,13 +80,30 @@ struct AmgParams {
   int smoother = SPAI0_BLOCK;
   double jacobi_omega = 2.0 / 3.0;
   bool smooth_p = true;       // false: plain aggregation, P = P_tent
+  int ilu_sweeps = 2;         // Jacobi sweeps per factor of the ILU0 smoother
 };
+
+// Block ILU(k) (ilu.cpp): per block row, the sorted block columns of the
+// combined factor (L strictly below the diagonal, U on and above it) and their
+// b x b blocks; Dinv holds U(i,i)^-1.  Applied with `sweeps` Jacobi iterations
+// on each triangular factor.
+struct Ilu {
+  int b = 1;
+  i64 nn = 0;
+  int sweeps = 2;
+  std::vector<std::vector<i32>> cols;
+  std::vector<std::vector<double>> vals;
+  std::vector<double> Dinv;
+};
+bool ilu_build(const Csr& A, int b, int level, int sweeps, Ilu& F, const char** msg);
+void ilu_apply(const Ilu& F, const double* r, double* z);
 
 struct Level {
   Csr A, P, R;                // P, R empty on the coarsest level
   std::vector<i32> agg;       // aggregate of each node, -1 if isolated
   std::vector<char> isolated;
   std::vector<double> M;      // smoother: one b x b block per node
+  Ilu F;                      // block ILU(0) factors when the smoother is ILU0
   double omega = 0;           // prolongator damping used to build P
   i64 n_agg = 0;
 };
@@ -146,19 +163,6 @@ bool schur_build(const Csr& A, const AmgParams& prm, const SchurOptions& opt, Sc
                  const char** msg);
 void schur_apply(const Schur& S, const double* r, double* z);
 
-// Block ILU(k) (ilu.cpp): per block row, the sorted block columns of the
-// combined factor (L strictly below the diagonal, U on and above it) and their
-// b x b blocks; Dinv holds U(i,i)^-1.  Applied with `sweeps` Jacobi iterations
-// on each triangular factor.
-struct Ilu {
-  int b = 1;
-  i64 nn = 0;
-  int sweeps = 2;
-  std::vector<std::vector<i32>> cols;
-  std::vector<std::vector<double>> vals;
-  std::vector<double> Dinv;
-};
-bool ilu_build(const Csr& A, int b, int level, int sweeps, Ilu& F, const char** msg);
-void ilu_apply(const Ilu& F, const double* r, double* z);
+
 
 }  // namespace orc

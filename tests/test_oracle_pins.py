@@ -416,6 +416,40 @@ def test_vcycle_brute_force(small_hierarchy):
         assert np.allclose(z, B @ r, rtol=1e-10, atol=1e-12 * np.abs(B @ r).max())
 
 
+def test_vcycle_with_ilu0_smoother_brute_force():
+    """V(1,1) with block ILU(0) smoothing: the dense operator of the definition with the
+    smoother S_l = the standalone ILU(0) preconditioner of A_l (pinned above), applied
+    column by column."""
+    n = 5
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 7))
+    s = oracle.Solver(A, 4, coarse_enough=40, smoother=oracle.ILU0, ilu_sweeps=2)
+    nlev = s.nlevels()
+    assert nlev >= 2
+
+    def smoother(l):
+        Al = s.level(l)["A"]
+        si = oracle.Solver(Al, 4, kind=oracle.KIND_ILU, ilu_level=0, ilu_sweeps=2)
+        m = Al.shape[0]
+        return np.column_stack([si.precond(np.eye(m)[:, j]) for j in range(m)])
+
+    def dense_cycle(l):
+        L = s.level(l)
+        Al = dense(L["A"])
+        if l == nlev - 1:
+            return np.linalg.inv(Al)
+        Sm = smoother(l)
+        P, R = dense(L["P"]), dense(L["R"])
+        I = np.eye(Al.shape[0])
+        return Sm + (I - Sm @ Al) @ Sm + (I - Sm @ Al) @ P @ dense_cycle(l + 1) @ R @ (I - Al @ Sm)
+
+    B = dense_cycle(0)
+    r = np.random.default_rng(12).normal(size=A.shape[0])
+    z = s.precond(r)
+    assert np.allclose(z, B @ r, rtol=1e-10, atol=1e-12 * np.abs(B @ r).max())
+    with pytest.raises(RuntimeError):
+        s.solve(r, 1e-8, transposed=True)
+
+
 def test_transposed_vcycle_is_adjoint(small_hierarchy):
     """<y, B x> = <B^T y, x> for the transposed-cycle preconditioner."""
     n, A, s = small_hierarchy
