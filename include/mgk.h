@@ -120,8 +120,13 @@ typedef struct {
                               (one velocity cycle, the PETSc LOWER variant of Section 4) */
   int32_t idr_s;           /* shadow space dimension of MGK_IDRS, 1..16, default 5 */
   int32_t ilu_level;       /* MGK_ILU fill level k in {0, 1}, default 0 */
-  int32_t ilu_sweeps;      /* MGK_ILU Jacobi sweeps per triangular factor, 0..64, default 2 */
-  int32_t reserved;
+  int32_t ilu_sweeps;      /* Jacobi sweeps per triangular factor for MGK_ILU and the ILU
+                              smoother, 0..64, default 2 */
+  int32_t ilu_smoother;    /* 1: every AMG level (monolithic, or the Schur velocity and
+                              pressure hierarchies) smooths with block ILU(0) instead of
+                              SPAI(0) / Jacobi: pre z = ILU^-1 r, post z += ILU^-1 (r - A z)
+                              (the paper smooths its velocity AMG with ILUT, Section 4).
+                              Not with enable_transpose, multi-RHS or batched solves. */
 } mgk_params;
 
 typedef struct {

@@ -330,8 +330,8 @@ static void batch_setup_impl(mgk_solver* S, int nsys, const mgk_bsr* const* A, i
                              int kind, const mgk_params* prm, void* stream) {
   if (nsys < 1 || nsys > 256 || !A || !prm)
     throw Error(MGK_E_INVALID, "batch: need 1..256 systems and non-null arguments");
-  if (kind == MGK_SCHUR || kind == MGK_ILU)
-    throw Error(MGK_E_INVALID, "batch: monolithic AMG kinds only");
+  if (kind == MGK_SCHUR || kind == MGK_ILU || prm->ilu_smoother)
+    throw Error(MGK_E_INVALID, "batch: monolithic AMG kinds with block-diagonal smoothers only");
   if (prm->krylov != MGK_BICGSTAB) throw Error(MGK_E_INVALID, "batch: BiCGStab only");
   BatchWork* W = new BatchWork();
   S->batch = W;

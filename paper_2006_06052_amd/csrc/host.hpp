@@ -24,6 +24,13 @@ struct HBsr {
   double* blk(int64_t k) { return val.data() + k * br * bc; }
 };
 
+// Block ILU(k) factors (k = 0 or 1): L strictly below, U strictly above the
+// diagonal blocks, Dinv the inverses of U's diagonal blocks (ilu.cpp).
+struct IluFactors {
+  HBsr L, U;
+  std::vector<double> Dinv;
+};
+
 enum SmootherKind { SM_SPAI0_BLOCK = 0, SM_JACOBI = 1, SM_SPAI0_SCALAR = 2 };
 
 struct SetupParams {
@@ -33,12 +40,15 @@ struct SetupParams {
   int smoother = SM_SPAI0_BLOCK;
   double jacobi_omega = 2.0 / 3.0;
   bool smooth_p = true;          // false: plain aggregation, P = P_tent
+  bool ilu_smoother = false;     // block ILU(0) smoothing instead of the block-diagonal smoother
+  int ilu_sweeps = 2;            // Jacobi sweeps per factor of the ILU smoother
 };
 
 struct HLevel {
   HBsr A, P, R;                  // P, R empty on the coarsest level
   std::vector<int32_t> agg;      // aggregate per block row, -1 = isolated
   std::vector<double> M;         // smoother, nbr * b * b (empty on coarsest)
+  IluFactors ilu;                // block ILU(0) smoother factors (ilu_smoother)
   double omega = 0.0;
   int32_t n_agg = 0;
 };
@@ -68,12 +78,6 @@ int schur_split(const HBsr& A, bool diag_only, SchurParts& out, std::string& err
 // Scalar SPAI(0) of a 1x1-block matrix: m_i = a_ii / sum_j a_ij^2 (ascending j).
 int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err);
 
-// Block ILU(k) factors (k = 0 or 1): L strictly below, U strictly above the
-// diagonal blocks, Dinv the inverses of U's diagonal blocks (ilu.cpp).
-struct IluFactors {
-  HBsr L, U;
-  std::vector<double> Dinv;
-};
 int ilu_factor(const HBsr& A, int level, IluFactors& out, std::string& err);
 
 // Ingest helpers.

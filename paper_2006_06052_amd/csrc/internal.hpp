@@ -327,6 +327,8 @@ static void smooth_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile
 struct DLevel {
   DMat A, P, R;
   void* M = nullptr;       // smoother blocks: FP64 (F64 hierarchy) or FP32
+  DMat Lf, Uf;             // ILU(0) smoother factors (ilu hierarchies)
+  void* Dinv = nullptr;    // ILU pivot inverses, FP64 or FP32 like M
   int nbr = 0;
   size_t n = 0;            // scalar unknowns
   void *r = nullptr, *t = nullptr, *z = nullptr, *z2 = nullptr;
@@ -335,6 +337,9 @@ struct DLevel {
 struct DHier {
   int b = 1, storage = MGK_F64;
   bool trans_ready = false;
+  bool ilu = false;        // levels smooth with block ILU(0)
+  int ilu_sweeps = 2;
+  void *sy = nullptr, *sy2 = nullptr, *sw = nullptr, *sz = nullptr;  // ILU scratch (level-0 size)
   std::vector<DLevel> lv;
   int nc = 0;
   double *cinv = nullptr, *cinvT = nullptr;
@@ -346,6 +351,37 @@ struct DHier {
 // One V(1,1) cycle on level l.  r: TIN at level 0 (else TX in lv[l].r);
 // output: TOUT at level 0 (else TX).  Returns nothing; the output of a level
 // l > 0 lands in lv[l].z2 (or lv[l].z on the coarsest level).
+// Block ILU application with Jacobi sweeps on the factors (TX vectors, FP32 or
+// FP64 accumulation): (I + L) y = r by y = r, then `sw` times y <- r - L y;
+// (D + U) z = y by z = Dinv y, then `sw` times z <- Dinv (y - U z).  y, y2, w,
+// zt are scratch vectors of n entries; the last product writes out (TOUT).
+template <int B, class TV, class TX, class TIN, class TOUT>
+static void ilu_sweeps(hipStream_t st, const DMat& Lf, const DMat& Uf, const void* Dinv, int nbr,
+                       int sw, const TIN* r, TOUT* out, TX* y, TX* y2, TX* w, TX* zt) {
+  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+  using TA = AccOf<TV>;
+  const size_t n = (size_t)nbr * B;
+  const int gd = (int)((n + WG - 1) / WG);
+  const TM* D = (const TM*)Dinv;
+  k_cast<TIN, TX><<<grid_for(n), WG, 0, st>>>(n, r, y);
+  for (int q = 0; q < sw; ++q) {
+    residual_s<B, B, TV, TX, TIN>(st, Lf, false, Lf.tile, r, y, y2);
+    std::swap(y, y2);
+  }
+  if (sw == 0) {
+    k_block_diag<B, TM, TX, TOUT, TA><<<gd, WG, 0, st>>>(nbr, 0, D, y, out);
+    return;
+  }
+  k_block_diag<B, TM, TX, TX, TA><<<gd, WG, 0, st>>>(nbr, 0, D, y, zt);
+  for (int q = 0; q < sw; ++q) {
+    residual_s<B, B, TV, TX, TX>(st, Uf, false, Uf.tile, y, zt, w);
+    if (q + 1 == sw)
+      k_block_diag<B, TM, TX, TOUT, TA><<<gd, WG, 0, st>>>(nbr, 0, D, w, out);
+    else
+      k_block_diag<B, TM, TX, TX, TA><<<gd, WG, 0, st>>>(nbr, 0, D, w, zt);
+  }
+}
+
 template <int B, class TV, class TX>
 struct Cycle {
   using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
@@ -361,15 +397,27 @@ struct Cycle {
     TX* z = (TX*)L.z;
     TX* t = (TX*)L.t;
     DLevel& C = H.lv[l + 1];
-    k_block_diag<B, TM, TIN, TX, AccOf<TV>>
-        <<<(unsigned)((L.n + WG - 1) / WG), WG, 0, st>>>(L.nbr, trans, (const TM*)L.M, r, z);
+    TX *sy = (TX*)H.sy, *sy2 = (TX*)H.sy2, *sw = (TX*)H.sw, *sz = (TX*)H.sz;
+    if (H.ilu)   // z = ILU^-1 r
+      ilu_sweeps<B, TV, TX, TIN, TX>(st, L.Lf, L.Uf, L.Dinv, L.nbr, H.ilu_sweeps, r, z, sy, sy2,
+                                     sw, sz);
+    else
+      k_block_diag<B, TM, TIN, TX, AccOf<TV>>
+          <<<(unsigned)((L.n + WG - 1) / WG), WG, 0, st>>>(L.nbr, trans, (const TM*)L.M, r, z);
     residual_s<B, B, TV, TX, TIN>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, r, z, t);
     spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.R.tile, t, (TX*)C.r, 1.0, 0.0);
     TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
     run<TX, TX>(st, H, l + 1, (const TX*)C.r, zc, trans);
     spmv_s<B, B, TV, TX, TX>(st, L.P, false, L.P.tile, zc, z, 1.0, 1.0);
-    smooth_s<B, TV, TX, TIN, TOUT, TM>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, (const TM*)L.M, r,
-                                       z, zout);
+    if (H.ilu) {   // zout = z + ILU^-1 (r - A z)
+      residual_s<B, B, TV, TX, TIN>(st, L.A, false, L.A.tile, r, z, t);
+      ilu_sweeps<B, TV, TX, TX, TX>(st, L.Lf, L.Uf, L.Dinv, L.nbr, H.ilu_sweeps, t, (TX*)L.z2,
+                                    sy, sy2, sw, sz);
+      k_add<TX, TOUT><<<grid_for(L.n), WG, 0, st>>>(L.n, z, (const TX*)L.z2, zout);
+    } else {
+      smooth_s<B, TV, TX, TIN, TOUT, TM>(st, L.A, trans, trans ? L.A.ttile : L.A.tile,
+                                         (const TM*)L.M, r, z, zout);
+    }
   }
 };
 

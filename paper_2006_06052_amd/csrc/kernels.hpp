@@ -773,6 +773,13 @@ __global__ __launch_bounds__(WG) void k_cast(size_t n, const TI* __restrict__ in
   GRID_STRIDE(i, n) out[i] = (TO)in[i];
 }
 
+// out = a + b.
+template <class T, class TO>
+__global__ __launch_bounds__(WG) void k_add(size_t n, const T* __restrict__ a,
+                                            const T* __restrict__ b, TO* __restrict__ out) {
+  GRID_STRIDE(i, n) out[i] = (TO)(a[i] + b[i]);
+}
+
 // y = m .* x (diagonal preconditioner step).
 template <class T>
 __global__ __launch_bounds__(WG) void k_diag_mul(size_t n, const T* __restrict__ m,

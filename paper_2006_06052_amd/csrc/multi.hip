@@ -367,7 +367,8 @@ extern "C" int mgk_solve_multi(mgk_solver* s, int32_t nrhs, const double* d_B, d
     mgk::g_err = "mgk_solve_multi: need 1 <= nrhs <= 32, non-null arguments, rtol > 0";
     return MGK_E_INVALID;
   }
-  if (s->host_only || s->batch || s->kind == MGK_SCHUR || s->kind == MGK_ILU) {
+  if (s->host_only || s->batch || s->kind == MGK_SCHUR || s->kind == MGK_ILU ||
+      s->prm.ilu_smoother) {
     mgk::g_err = "mgk_solve_multi: needs a monolithic AMG solver with device data";
     return MGK_E_STATE;
   }

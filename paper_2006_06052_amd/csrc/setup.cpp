@@ -503,7 +503,7 @@ int build_hierarchy(const HBsr& A0, const SetupParams& prm, HHierarchy& H, std::
         L.R = block_transpose(L.P);
         HBsr AP = block_spgemm(L.A, L.P);
         Ac = block_spgemm(L.R, AP);
-        rc = build_smoother(L.A, prm, L.M, err);
+        rc = prm.ilu_smoother ? ilu_factor(L.A, 0, L.ilu, err) : build_smoother(L.A, prm, L.M, err);
         if (rc) return rc;
       }
     }

@@ -212,12 +212,21 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
     if (!last) {
       d.P = upload_mat(D, h.P, storage, false);
       d.R = upload_mat(D, h.R, storage, false);
+      const bool ilu = !h.ilu.Dinv.empty();
+      const std::vector<double>& Mh = ilu ? h.ilu.Dinv : h.M;
       if (storage == MGK_F64) {
-        d.M = D.upload(h.M.data(), h.M.size());
+        (ilu ? d.Dinv : d.M) = D.upload(Mh.data(), Mh.size());
       } else {
-        std::vector<float> m(h.M.begin(), h.M.end());
-        d.M = D.upload(m.data(), m.size());
+        std::vector<float> m(Mh.begin(), Mh.end());
+        (ilu ? d.Dinv : d.M) = D.upload(m.data(), m.size());
         HIPCK(hipStreamSynchronize(D.stream));
+      }
+      if (ilu) {
+        out.ilu = true;
+        d.Lf = upload_mat(D, h.ilu.L, storage, false);
+        d.Uf = upload_mat(D, h.ilu.U, storage, false);
+        tune_mat(D, d.Lf, storage, false);
+        tune_mat(D, d.Uf, storage, false);
       }
       if (!(l == 0 && share_level0 && storage == MGK_F64 && d.A.ptr == share_level0->ptr))
         tune_mat(D, d.A, storage, with_transpose);
@@ -228,6 +237,13 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
     d.t = D.alloc(d.n * xs);
     d.z = D.alloc(d.n * xs);
     d.z2 = D.alloc(d.n * xs);
+  }
+  if (out.ilu) {
+    const size_t n0 = out.lv[0].n;
+    out.sy = D.alloc(n0 * xs);
+    out.sy2 = D.alloc(n0 * xs);
+    out.sw = D.alloc(n0 * xs);
+    out.sz = D.alloc(n0 * xs);
   }
   fill_desc(H, out.desc);
   out.nc = H.nc;
@@ -307,36 +323,12 @@ static void schur_apply_t(mgk_solver* S, const double* r, double* z) {
   k_merge<TX><<<grid_for(nn), WG, 0, st>>>(nn, zu, zp, z);
 }
 
-// Block ILU apply with Jacobi sweeps on the factors, in the storage precision:
-// (I + L) y = r by y = r, then sweeps x y <- r - L y; (D + U) z = y by z = Dinv y,
-// then sweeps x z <- Dinv (y - U z).  The last product writes the FP64 output.
+// Block ILU preconditioner (MGK_ILU) in the storage precision, FP64 in and out.
 template <int B, class TV, class TX>
 static void ilu_apply_b(mgk_solver* S, const double* r, double* z) {
-  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
-  using TA = AccOf<TV>;
-  hipStream_t st = S->dev.stream;
-  const size_t n = S->n;
-  const int nbr = S->nbr, sw = S->prm.ilu_sweeps, gb = grid_for(n);
-  TX *y = (TX*)S->iy, *y2 = (TX*)S->iy2, *w = (TX*)S->iw, *zt = (TX*)S->iz;
-  const TM* Dinv = (const TM*)S->Dinv;
-  const int gd = (int)((n + WG - 1) / WG);
-  k_cast<double, TX><<<gb, WG, 0, st>>>(n, r, y);
-  for (int q = 0; q < sw; ++q) {
-    residual_s<B, B, TV, TX, double>(st, S->Lf, false, S->Lf.tile, r, y, y2);
-    std::swap(y, y2);
-  }
-  if (sw == 0) {
-    k_block_diag<B, TM, TX, double, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, y, z);
-    return;
-  }
-  k_block_diag<B, TM, TX, TX, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, y, zt);
-  for (int q = 0; q < sw; ++q) {
-    residual_s<B, B, TV, TX, TX>(st, S->Uf, false, S->Uf.tile, y, zt, w);
-    if (q + 1 == sw)
-      k_block_diag<B, TM, TX, double, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, w, z);
-    else
-      k_block_diag<B, TM, TX, TX, TA><<<gd, WG, 0, st>>>(nbr, 0, Dinv, w, zt);
-  }
+  ilu_sweeps<B, TV, TX, double, double>(S->dev.stream, S->Lf, S->Uf, S->Dinv, S->nbr,
+                                        S->prm.ilu_sweeps, r, z, (TX*)S->iy, (TX*)S->iy2,
+                                        (TX*)S->iw, (TX*)S->iz);
 }
 
 template <class TV, class TX>
@@ -601,6 +593,8 @@ static SetupParams setup_params(const mgk_params& p, int kind) {
   sp.jacobi_omega = p.jacobi_omega;
   sp.smoother = kind == MGK_AMG_JACOBI ? SM_JACOBI : (p.block_spai0 ? SM_SPAI0_BLOCK : SM_SPAI0_SCALAR);
   sp.smooth_p = p.coarsening == MGK_SMOOTHED_AGGREGATION;
+  sp.ilu_smoother = p.ilu_smoother != 0;
+  sp.ilu_sweeps = p.ilu_sweeps;
   return sp;
 }
 
@@ -648,9 +642,13 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   if (A->block != block_size || (block_size != 1 && block_size != 3 && block_size != 4))
     throw Error(MGK_E_INVALID, "block_size must equal A->block and be 1, 3 or 4");
   if (kind < MGK_AMG_SPAI0 || kind > MGK_ILU) throw Error(MGK_E_INVALID, "unknown kind");
-  if (kind == MGK_ILU && (prm->ilu_level < 0 || prm->ilu_level > 1 || prm->ilu_sweeps < 0 ||
-                          prm->ilu_sweeps > 64))
-    throw Error(MGK_E_INVALID, "MGK_ILU needs ilu_level in {0, 1} and 0 <= ilu_sweeps <= 64");
+  if (kind == MGK_ILU && (prm->ilu_level < 0 || prm->ilu_level > 1))
+    throw Error(MGK_E_INVALID, "MGK_ILU needs ilu_level in {0, 1}");
+  if (prm->ilu_sweeps < 0 || prm->ilu_sweeps > 64)
+    throw Error(MGK_E_INVALID, "ilu_sweeps must be in 0..64");
+  if (prm->ilu_smoother & ~1) throw Error(MGK_E_INVALID, "ilu_smoother is 0 or 1");
+  if (prm->ilu_smoother && prm->enable_transpose)
+    throw Error(MGK_E_INVALID, "the ILU smoother has no transposed cycle (enable_transpose)");
   if (kind == MGK_SCHUR && block_size != 4)
     throw Error(MGK_E_INVALID, "MGK_SCHUR needs interleaved [u,v,w,p] (block size 4)");
   if (prm->hier < MGK_F64 || prm->hier > MGK_BF16) throw Error(MGK_E_INVALID, "unknown storage");
@@ -742,6 +740,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     HHierarchy hu, hp;
     if ((rc = build_hierarchy(parts.Auu, sp, hu, err))) throw Error(rc, err);
     upload_hierarchy(S->dev, hu, prm->hier, false, S->H, nullptr);
+    S->H.ilu_sweeps = prm->ilu_sweeps;
     if (prm->schur_spai0) {
       std::vector<double> m;
       if ((rc = scalar_spai0(parts.S, m, err))) throw Error(rc, err);
@@ -755,6 +754,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     } else {
       if ((rc = build_hierarchy(parts.S, sp, hp, err))) throw Error(rc, err);
       upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr);
+      S->Hp.ilu_sweeps = prm->ilu_sweeps;
     }
     S->Blo = upload_mat(S->dev, parts.Blo, prm->hier, false);
     S->Bup = upload_mat(S->dev, parts.Bup, prm->hier, false);
@@ -776,6 +776,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     HHierarchy hh;
     if ((rc = build_hierarchy(H, sp, hh, err))) throw Error(rc, err);
     upload_hierarchy(S->dev, hh, prm->hier, tr, S->H, &S->A);
+    S->H.ilu_sweeps = prm->ilu_sweeps;
     if (prm->keep_host) {
       S->H.host = std::move(hh);
       S->H.keep_host = true;

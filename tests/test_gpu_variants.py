@@ -198,3 +198,52 @@ def test_paper_monolithic_ilu_configuration(storage, krylov):
     B = torch.zeros((A.shape[0], 2), dtype=torch.float64, device=DEV)
     with pytest.raises(mgk.MgkError):
         s.solve_multi(B, torch.zeros_like(B), 1e-8)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_amg_with_ilu0_smoother(storage):
+    """Every AMG level smoothed with block ILU(0) (2 Jacobi sweeps per factor): the FP64
+    V-cycle agrees with the oracle's, and solves reach the oracle's solution."""
+    n = 12
+    th, bsr, A = problem(n, 0.5, 17)
+    b = oracle.spmv(A, S.mms_solution(n))
+    s = gpu_solver(bsr, hier=storage, coarse_enough=300, ilu_smoother=1, ilu_sweeps=2)
+    so = oracle.Solver(A, 4, coarse_enough=300, smoother=oracle.ILU0, ilu_sweeps=2)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    if storage == "f64":
+        r = np.random.default_rng(6).normal(size=A.shape[0])
+        s.precond(dev(r), dx)
+        zo = so.precond(r)
+        assert np.linalg.norm(dx.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+        dx.zero_()
+    info = s.solve(dev(b), dx, 1e-8)
+    xo, oi = so.solve(b, 1e-12)
+    say("ilu smoother", storage, info["iters"], oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+    with pytest.raises(mgk.MgkError):
+        gpu_solver(bsr, ilu_smoother=1, enable_transpose=1)
+    B = torch.zeros((A.shape[0], 2), dtype=torch.float64, device=DEV)
+    with pytest.raises(mgk.MgkError):
+        s.solve_multi(B, torch.zeros_like(B), 1e-8)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_paper_v2_shape_schur_ilu_smoothed(storage):
+    """The paper's Schur variant shape: IDR(5); velocity AMG with plain aggregation and
+    ILU smoothing (block ILU(0) in place of ILUT) on the 3x3 blocks; SPAI(0) pressure
+    step on the diagonal Schur approximation; FP64 or FP32 hierarchy (V3 / V4)."""
+    n = 14
+    th, bsr, A = problem(n, 1.0, 18)
+    b = oracle.spmv(A, S.mms_solution(n))
+    kw = dict(schur_approx=1, schur_spai0=1, coarse_enough=300, ilu_sweeps=2)
+    s = gpu_solver(bsr, mgk.SCHUR, krylov=mgk.IDRS, idr_s=5, hier=storage, ilu_smoother=1,
+                   coarsening=mgk.PLAIN_AGGREGATION, **kw)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    info = s.solve(dev(b), dx, 1e-8)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.IDRS, idr_s=5,
+                       smoother=oracle.ILU0, coarsening=oracle.PLAIN, **kw)
+    xo, oi = so.solve(b, 1e-12)
+    say("paper v2 shape", storage, info["iters"], oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
