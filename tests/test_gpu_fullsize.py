@@ -1,7 +1,8 @@
 """Parity at the full workload sizes, in the configuration bench.py times.
 
 96^3 monolithic (mixed FP32 hierarchy, BiCGStab), 64^3 Schur pressure correction (BF16
-hierarchy, FGMRES(30)), 48^3 adjoint gradient.  The residual of every GPU solution is
+hierarchy, FGMRES(30)), 48^3 adjoint gradient, 64^3 with 32 right-hand sides in one lockstep
+solve, and the eight 24^3 ... 64^3 systems in one batched solve.  The residual of every GPU solution is
 evaluated with the oracle's own FP64 SpMV; solutions are compared with the oracle's FP64
 solve; the gradient with the oracle's gradient over all cells and with central finite
 differences on 20 seeded cells.
@@ -131,3 +132,50 @@ def test_cube48_adjoint_gradient():
     relfd = np.linalg.norm(g[cells] - fd) / np.linalg.norm(fd)
     say("gradient vs central FD", relfd)
     assert relfd <= 1e-6
+
+
+def test_cube64_32rhs_lockstep_vs_oracle():
+    """All 32 columns meet 1e-8 (oracle SpMV); columns 0 and 17 match oracle solves."""
+    n, K = 64, 32
+    ptr, col, val = mgk.stokes_bsr(n)
+    Bm = S.body_forces(n, K, 4)
+    s = solver(ptr, col, val, hier=mgk.F32)
+    dB = dev(Bm)
+    dX = torch.zeros_like(dB)
+    infos = s.solve_multi(dB, dX, 1e-8)
+    X = dX.cpu().numpy()
+    say("multi64", [i["iters"] for i in infos])
+    A = oracle.stokes_matrix(n)
+    AX = np.column_stack([oracle.spmv(A, np.ascontiguousarray(X[:, k])) for k in range(K)])
+    res = np.linalg.norm(Bm - AX, axis=0) / np.linalg.norm(Bm, axis=0)
+    assert all(i["status"] == 0 for i in infos) and res.max() <= 1e-8, res.max()
+    so = oracle.Solver(A, 4)
+    for k in (0, 17):
+        xo, _ = so.solve(np.ascontiguousarray(Bm[:, k]), 1e-11)
+        assert np.linalg.norm(X[:, k] - xo) <= 1e-6 * np.linalg.norm(xo), k
+
+
+def test_batch_eight_systems_vs_oracle():
+    """The eight log-normal systems (24^3 ... 64^3) in one batched solve: every system meets
+    1e-8 (oracle SpMV); the 24^3 and one 64^3 system match oracle solves."""
+    ns = [24, 32, 40, 48, 48, 56, 64, 64]
+    systems, bs, As = [], [], []
+    for k, n in enumerate(ns):
+        th = S.theta_field(n, 0.5, 40 + k)
+        systems.append(mgk.stokes_bsr(n, th))
+        A = oracle.stokes_matrix(n, th)
+        As.append(A)
+        bs.append(oracle.spmv(A, S.mms_solution(n)))
+    bsol = mgk.BatchSolver(systems, 4, mgk.AMG_SPAI0, stream=torch.cuda.current_stream(),
+                           hier=mgk.F32)
+    db = [dev(b) for b in bs]
+    xs = [torch.zeros_like(b) for b in db]
+    infos = bsol.solve(db, xs, 1e-8)
+    say("batch8", [i["iters"] for i in infos])
+    for k, (A, b, x) in enumerate(zip(As, bs, xs)):
+        xk = x.cpu().numpy()
+        assert infos[k]["status"] == 0
+        assert np.linalg.norm(b - oracle.spmv(A, xk)) <= 1e-8 * np.linalg.norm(b), k
+        if k in (0, 6):
+            xo, _ = oracle.Solver(A, 4).solve(b, 1e-11)
+            assert np.linalg.norm(xk - xo) <= 1e-6 * np.linalg.norm(xo), k
