@@ -46,7 +46,8 @@ class _Params(C.Structure):
                 ("smoother", C.c_int32), ("kind", C.c_int32), ("jacobi_omega", C.c_double),
                 ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
-                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("pad", C.c_int32)]
+                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32),
+                ("schur_scalar_u", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -164,7 +165,8 @@ class Solver:
                  maxiter: int = 1000, fgmres_m: int = 30, max_restarts: int = 5,
                  jacobi_omega: float = 2.0 / 3.0, coarsening: int = SMOOTHED,
                  schur_approx: int = 0, schur_spai0: int = 0, schur_lower: int = 0,
-                 idr_s: int = 5, ilu_level: int = 0, ilu_sweeps: int = 2):
+                 idr_s: int = 5, ilu_level: int = 0, ilu_sweeps: int = 2,
+                 schur_scalar_u: int = 0):
         A = sp.csr_matrix(A)
         A.sort_indices()
         self.n = A.shape[0]
@@ -172,7 +174,8 @@ class Solver:
                       np.ascontiguousarray(A.indices, np.int32), _f64(A.data))
         self.prm = _Params(krylov, fgmres_m, maxiter, max_restarts, eps_strong, coarse_enough,
                            max_levels, smoother, kind, jacobi_omega, coarsening, schur_approx,
-                           schur_spai0, schur_lower, idr_s, ilu_level, ilu_sweeps, 0)
+                           schur_spai0, schur_lower, idr_s, ilu_level, ilu_sweeps,
+                           schur_scalar_u)
         self.block = block
         L = lib()
         h = L.orc_setup(self.n, *(_p(a) for a in self._keep), block, C.byref(self.prm))

@@ -63,7 +63,7 @@ struct orc_params {
   int32_t idr_s;         // shadow space dimension of IDR(s)
   int32_t ilu_level;     // fill level of the block ILU(k) preconditioner (kind 3)
   int32_t ilu_sweeps;    // Jacobi sweeps per triangular factor
-  int32_t pad;
+  int32_t schur_scalar_u;  // 1: Schur velocity AMG on scalar values
 };
 
 struct orc_info {
@@ -150,6 +150,7 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
       so.diag_approx = prm->schur_approx != 0;
       so.spai0_p = prm->schur_spai0 != 0;
       so.lower = prm->schur_lower != 0;
+      so.scalar_u = prm->schur_scalar_u != 0;
       if (!schur_build(s->A, s->aprm, so, s->S, &msg)) {
         g_err = msg ? msg : "oracle: Schur setup failed";
         return nullptr;

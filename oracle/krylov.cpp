@@ -375,7 +375,7 @@ bool schur_build(const Csr& A, const AmgParams& prm, const SchurOptions& opt, Sc
     }
     S.S.ptr[r + 1] = (i64)S.S.col.size();
   }
-  if (!amg_build(S.Auu, 3, prm, S.Hu, msg)) return false;
+  if (!amg_build(S.Auu, opt.scalar_u ? 1 : 3, prm, S.Hu, msg)) return false;
   if (opt.spai0_p) {
     // scalar SPAI(0): m_i = s_ii / sum_j s_ij^2 (the b = 1 case of the block formula)
     S.Sm.assign(nn, 0.0);

@@ -151,6 +151,7 @@ struct SchurOptions {
   bool diag_approx = false;   // S = C - diag(Blo diag(Auu)^-1 Bup)   (eq. SchurApprox)
   bool spai0_p = false;       // pressure step: one SPAI(0) application instead of a V-cycle
   bool lower = false;         // lower block factorization: no second velocity cycle
+  bool scalar_u = false;      // velocity AMG on scalar values instead of 3x3 blocks
 };
 struct Schur {
   Csr Auu, Bup, Blo, C, S;    // S = C - Blo diag(Auu)^-1 Bup, or its diagonal-only form

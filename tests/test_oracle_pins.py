@@ -711,6 +711,23 @@ def test_schur_lower_is_block_lower_factorization():
     assert np.allclose(z[p], zp, rtol=1e-9, atol=1e-12)
 
 
+def test_schur_scalar_and_block_velocity_amg_coincide():
+    """The finite-difference velocity block has no coupling between u, v and w, so its 3x3
+    blocks are diagonal: block strength, aggregation, prolongation and SPAI(0) reduce to the
+    scalar ones, and the velocity AMG on scalar values (the paper's V2 format) is the same
+    preconditioner as on 3x3 blocks (V3) - two independent code paths agree."""
+    n = 9
+    A = oracle.stokes_matrix(n, S.theta_field(n, 1.0, 6))
+    kw = dict(kind=oracle.KIND_SCHUR, coarse_enough=150)
+    sb = oracle.Solver(A, 4, **kw)
+    ss = oracle.Solver(A, 4, schur_scalar_u=1, **kw)
+    assert sb.level(0, 0)["block"] == 3 and ss.level(0, 0)["block"] == 1
+    assert sb.nlevels(0) == ss.nlevels(0) >= 2
+    r = np.random.default_rng(10).normal(size=A.shape[0])
+    zb, zs = sb.precond(r), ss.precond(r)
+    assert np.allclose(zb, zs, rtol=1e-12, atol=1e-14 * np.abs(zb).max())
+
+
 def test_schur_exact_complement_one_iteration():
     """If the pressure operator were the exact Schur complement C - B_lo A_uu^-1 B_up, the
     factorization would be A^-1 (eqs. SchurP/SchurU); the dense check of that identity pins
