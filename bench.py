@@ -145,7 +145,8 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
                with the transposed V-cycle, and the per-cell viscosity gradient;
     idrs96   - the 96^3 headline system with IDR(5) instead of BiCGStab;
     plain96  - the 96^3 headline system with plain-aggregation AMG (P = P_tent);
-    paper_schur64 - the 64^3 log-normal system with the paper's Schur configuration:
+    paper_schur64 - the 64^3 log-normal system with the paper's Schur configuration
+               (velocity AMG on scalar values, V2, or on 3x3 blocks, V3/V4):
                IDR(5), velocity AMG with plain aggregation, pressure step one SPAI(0)
                application of the diagonal Schur approximation, full factorization;
                FP64, FP32 and BF16 hierarchy values, and FP64 / FP32 with block ILU(0)
@@ -387,10 +388,12 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
         ptr, col, val = mgk.stokes_bsr(n, S.theta_field(n, 1.0, 3))
         xs = torch.from_numpy(S.mms_solution(n)).cuda()
         r = {}
-        for tag, hier in (("f64", mgk.F64), ("f32", mgk.F32), ("bf16", mgk.BF16)):
+        for tag, hier, su in (("scalar_f64", mgk.F64, 1), ("f64", mgk.F64, 0),
+                              ("f32", mgk.F32, 0), ("bf16", mgk.BF16, 0)):
             t0 = time.perf_counter()
             sv = solver(ptr, col, val, mgk.SCHUR, hier=hier, krylov=mgk.IDRS, idr_s=5,
-                        coarsening=mgk.PLAIN_AGGREGATION, schur_approx=1, schur_spai0=1)
+                        coarsening=mgk.PLAIN_AGGREGATION, schur_approx=1, schur_spai0=1,
+                        schur_scalar_u=su)
             t_setup = time.perf_counter() - t0
             b = a_times(sv, xs)
             x = torch.zeros_like(b)
@@ -422,6 +425,7 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
                       "rel_resid": info["rel_resid"], "setup_s": t_setup}
             log_fn(f"paper_schur64 {tag}: {t:.3f}s, {info['iters']} iterations")
             del sv
+        r["speedup_block_f64_vs_scalar_f64"] = r["scalar_f64"]["solve_s"] / r["f64"]["solve_s"]
         r["speedup_f32_vs_f64"] = r["f64"]["solve_s"] / r["f32"]["solve_s"]
         r["speedup_bf16_vs_f64"] = r["f64"]["solve_s"] / r["bf16"]["solve_s"]
         r["speedup_ilu_f32_vs_ilu_f64"] = r["ilu_f64"]["solve_s"] / r["ilu_f32"]["solve_s"]

@@ -127,6 +127,10 @@ typedef struct {
                               SPAI(0) / Jacobi: pre z = ILU^-1 r, post z += ILU^-1 (r - A z)
                               (the paper smooths its velocity AMG with ILUT, Section 4).
                               Not with enable_transpose, multi-RHS or batched solves. */
+  int32_t schur_scalar_u;  /* MGK_SCHUR: 1 builds the velocity AMG on the scalar values of
+                              A_uu (1x1 blocks, zero entries dropped) instead of 3x3 blocks -
+                              the paper's scalar (V2) versus block-valued (V3) solver */
+  int32_t reserved;
 } mgk_params;
 
 typedef struct {

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("time_spmv", C.c_int32), ("force_tile", C.c_int32),
                 ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
-                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("ilu_smoother", C.c_int32)]
+                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("ilu_smoother", C.c_int32),
+                ("schur_scalar_u", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -75,6 +75,8 @@ struct SchurParts {
   HBsr Auu, Bup, Blo, C, S;
 };
 int schur_split(const HBsr& A, bool diag_only, SchurParts& out, std::string& err);
+// Scalar (1x1-block) form of a square-block BSR matrix, zero entries dropped.
+HBsr scalar_form(const HBsr& A);
 // Scalar SPAI(0) of a 1x1-block matrix: m_i = a_ii / sum_j a_ij^2 (ascending j).
 int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err);
 

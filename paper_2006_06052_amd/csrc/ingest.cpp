@@ -324,4 +324,25 @@ int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err) {
   return 0;
 }
 
+HBsr scalar_form(const HBsr& A) {
+  const int b = A.br;
+  HBsr S;
+  S.br = S.bc = 1;
+  S.nbr = A.nbr * b;
+  S.nbc = A.nbc * b;
+  S.ptr.assign(S.nbr + 1, 0);
+  for (int32_t i = 0; i < A.nbr; ++i)
+    for (int r = 0; r < b; ++r) {
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+        for (int c = 0; c < b; ++c) {
+          const double v = A.blk(k)[r * b + c];
+          if (v == 0.0) continue;
+          S.col.push_back(A.col[k] * b + c);
+          S.val.push_back(v);
+        }
+      S.ptr[(size_t)i * b + r + 1] = (int32_t)S.col.size();
+    }
+  return S;
+}
+
 }  // namespace mgk

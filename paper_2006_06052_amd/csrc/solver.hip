@@ -647,6 +647,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   if (prm->ilu_sweeps < 0 || prm->ilu_sweeps > 64)
     throw Error(MGK_E_INVALID, "ilu_sweeps must be in 0..64");
   if (prm->ilu_smoother & ~1) throw Error(MGK_E_INVALID, "ilu_smoother is 0 or 1");
+  if (prm->schur_scalar_u & ~1) throw Error(MGK_E_INVALID, "schur_scalar_u is 0 or 1");
   if (prm->ilu_smoother && prm->enable_transpose)
     throw Error(MGK_E_INVALID, "the ILU smoother has no transposed cycle (enable_transpose)");
   if (kind == MGK_SCHUR && block_size != 4)
@@ -692,6 +693,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     } else if (kind == MGK_SCHUR) {
       SchurParts parts;
       if ((rc = schur_split(H, prm->schur_approx != 0, parts, err))) throw Error(rc, err);
+      if (prm->schur_scalar_u) parts.Auu = scalar_form(parts.Auu);
       if ((rc = build_hierarchy(parts.Auu, sp, S->H.host, err))) throw Error(rc, err);
       if (!prm->schur_spai0) {
         if ((rc = build_hierarchy(parts.S, sp, S->Hp.host, err))) throw Error(rc, err);
@@ -737,6 +739,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   } else if (kind == MGK_SCHUR) {
     SchurParts parts;
     if ((rc = schur_split(H, prm->schur_approx != 0, parts, err))) throw Error(rc, err);
+    if (prm->schur_scalar_u) parts.Auu = scalar_form(parts.Auu);
     HHierarchy hu, hp;
     if ((rc = build_hierarchy(parts.Auu, sp, hu, err))) throw Error(rc, err);
     upload_hierarchy(S->dev, hu, prm->hier, false, S->H, nullptr);

@@ -161,6 +161,20 @@ def test_host_ilu_factors_match_oracle_bitwise(n, level):
     assert np.array_equal(dinv, so.ilu_dinv())
 
 
+def test_host_setup_matches_oracle_schur_scalar_velocity():
+    """Schur split with the velocity AMG on scalar values (the paper's V2 format)."""
+    n = 12
+    th = S.theta_field(n, 1.0, 5)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    kw = dict(coarse_enough=150, schur_scalar_u=1)
+    hs = host_solver(ptr, col, val, 4, mgk.SCHUR, coarsening=mgk.PLAIN_AGGREGATION, **kw)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4, kind=oracle.KIND_SCHUR,
+                        coarsening=oracle.PLAIN, **kw)
+    assert hs.level_info(0, 0)["block"] == 1
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)
+    compare_hierarchies(hs, 1, os_, 1, levels_expected=2)
+
+
 def test_host_setup_scalar_csr_arm():
     """The whole setup at block size 1 on the scalar CSR matrix (V2-style scalar arm)."""
     n = 8

@@ -247,3 +247,26 @@ def test_paper_v2_shape_schur_ilu_smoothed(storage):
     say("paper v2 shape", storage, info["iters"], oi["iters"])
     assert info["status"] == 0
     check_solution(A, b, dx.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_schur_scalar_velocity_amg(storage):
+    """Schur preconditioner with the velocity AMG on scalar values: agrees with the oracle
+    (and, for this decoupled velocity operator, with the 3x3-block AMG)."""
+    n = 14
+    th, bsr, A = problem(n, 1.0, 19)
+    b = oracle.spmv(A, S.mms_solution(n))
+    kw = dict(coarse_enough=200, schur_scalar_u=1)
+    s = gpu_solver(bsr, mgk.SCHUR, krylov=mgk.FGMRES, hier=storage, **kw)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES, **kw)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    if storage == "f64":
+        r = np.random.default_rng(7).normal(size=A.shape[0])
+        s.precond(dev(r), dx)
+        zo = so.precond(r)
+        assert np.linalg.norm(dx.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+        dx.zero_()
+    info = s.solve(dev(b), dx, 1e-8)
+    xo, _ = so.solve(b, 1e-12)
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
