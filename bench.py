@@ -111,6 +111,23 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     return 2 * nbytes / t / 1e9
 
 
+def read_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Practical read-only HBM ceiling: a streaming sum over nbytes."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    for _ in range(3):
+        x.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del x
+    return nbytes / t / 1e9
+
+
 def _median_solve(fn, torch, steps=3, warmup=1):
     """Median wall time of fn() (which returns an info record or list of them), each call
     bracketed by device synchronizations."""
@@ -629,6 +646,8 @@ def main():
     if roofline:
         roofline["copy_ceiling_gbs"] = copy_ceiling(torch)
         roofline["frac_of_copy_ceiling"] = roofline["achieved"] / roofline["copy_ceiling_gbs"]
+        roofline["read_ceiling_gbs"] = read_ceiling(torch)
+        roofline["frac_of_read_ceiling"] = roofline["achieved"] / roofline["read_ceiling_gbs"]
     out["roofline"] = roofline
     if args.seed_sweep > 0:
         out["seed_sweep"] = seed_sweep(mgk, S, torch, n, args.seed_sweep, log)

@@ -13,10 +13,11 @@
 // then one dimension-reduction step: t = A K^-1 r, omega = (t, r) / (t, t)
 // (enlarged when |cos(t, r)| < 0.7), r -= omega t, x += omega K^-1 r.
 //
-// The orthogonalization against the first k shadow vectors solves for all
-// alpha_i at once from the dots P(0:k)^T G_k (a forward substitution with the
-// stored lower triangle of M), which is the sequential projection of the
-// algorithm written in one pass; M(:, k) is then recomputed from the updated G_k.
+// One pass of shadow dots d = P^T G_k per inner step serves the whole step: the
+// orthogonalization against the first k shadow vectors solves for all alpha_i
+// at once (a forward substitution with the stored lower triangle of M, which is
+// the sequential projection of the algorithm written in one pass), and the new
+// column of M follows as M(i, k) = d_i - sum_j alpha_j M(i, j).
 // Every scalar stays in device memory.  The convergence flag of step j is read
 // through pinned memory while the preconditioner and SpMV of step j+1, which do
 // not touch x or r, are already queued.
@@ -64,21 +65,24 @@ __global__ void k_idr_coef(int s, int k, double* __restrict__ d) {
   }
 }
 
-// alpha(0:k) = M(0:k, 0:k)^-1 dots(0:k).
-__global__ void k_idr_alpha(int k, double* __restrict__ d) {
+// From the shadow dots d = P^T G_k of the new direction (before it is made
+// orthogonal to p_0 .. p_{k-1}):
+//   alpha(0:k) = M(0:k, 0:k)^-1 d(0:k)                  (forward substitution)
+//   M(i, k) = d_i - sum_{j<k} alpha_j M(i, j), i >= k    (= p_i^T of the orthogonalized G_k,
+//                                                          since M(i, j) = p_i^T G_j)
+//   beta = f_k / M_kk (breakdown: beta = 0, flag set); f(k+1:s) -= beta M(k+1:s, k).
+__global__ void k_idr_proj(int s, int k, double* __restrict__ d) {
   if (threadIdx.x != 0) return;
   for (int i = 0; i < k; ++i) {
     double a = d[I_D + i];
     for (int j = 0; j < i; ++j) a = a - Mat(d, i, j) * d[I_A + j];
     d[I_A + i] = a / Mat(d, i, i);
   }
-}
-
-// M(k:s, k) = dots(k:s); beta = f_k / M_kk (breakdown: beta = 0, flag set);
-// f(k+1:s) -= beta M(k+1:s, k).
-__global__ void k_idr_beta(int s, int k, double* __restrict__ d) {
-  if (threadIdx.x != 0) return;
-  for (int i = k; i < s; ++i) Mat(d, i, k) = d[I_D + i];
+  for (int i = k; i < s; ++i) {
+    double m = d[I_D + i];
+    for (int j = 0; j < k; ++j) m = m - d[I_A + j] * Mat(d, i, j);
+    Mat(d, i, k) = m;
+  }
   const double mkk = Mat(d, k, k);
   if (mkk == 0.0) {
     d[I_BETA] = 0.0;
@@ -272,7 +276,7 @@ int idrs(mgk_solver* S, const double* b, double* x, double tol, bool trans, mgk_
   };
   // shadow dots of w into d[slot0 .. slot0+m)
   auto pdots = [&](int m, const double* w, int slot0) {
-    k_multidot<<<g, WG, 0, st>>>(n, m, W.P, n, w, S->part);
+    multidot(st, g, n, m, W.P, n, w, S->part);
     k_multifin<<<1, WG, 0, st>>>(S->part, g, m, d + slot0, d + I_X, 0);
   };
 
@@ -295,13 +299,9 @@ int idrs(mgk_solver* S, const double* b, double* x, double tol, bool trans, mgk_
       precond(S, v, vh, trans);
       k_idr_u<<<g, WG, 0, st>>>(n, s, k, vh, d, W.U);
       outer_spmv(S, Uk, Gk, trans);
-      if (k > 0) {
-        pdots(k, Gk, I_D);
-        k_idr_alpha<<<1, 64, 0, st>>>(k, d);
-        k_idr_orth<<<g, WG, 0, st>>>(n, k, d, W.G, W.U);
-      }
       pdots(s, Gk, I_D);
-      k_idr_beta<<<1, 64, 0, st>>>(s, k, d);
+      k_idr_proj<<<1, 64, 0, st>>>(s, k, d);
+      if (k > 0) k_idr_orth<<<g, WG, 0, st>>>(n, k, d, W.G, W.U);
     };
     auto reduce_pre = [&]() {
       precond(S, r, vh, trans);

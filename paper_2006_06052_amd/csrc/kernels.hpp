@@ -698,17 +698,20 @@ static __global__ __launch_bounds__(WG) void k_fill(size_t n, double v, double* 
 
 constexpr int MAXM = 32;
 
-// part[q * grid + blk] = <V_q, w> for q < m (V_q = V + q * ld).
+// part[q * grid + blk] = <V_q, w> for q < m <= MQ (V_q = V + q * ld).  MQ bounds the
+// accumulators a thread keeps; launch through multidot(), which picks the
+// smallest MQ that holds m (the summation order does not depend on MQ).
+template <int MQ>
 static __global__ __launch_bounds__(WG) void k_multidot(size_t n, int m, const double* __restrict__ V,
                                                  size_t ld, const double* __restrict__ w,
                                                  double* __restrict__ part) {
-  double acc[MAXM];
+  double acc[MQ];
 #pragma unroll
-  for (int q = 0; q < MAXM; ++q) acc[q] = 0.0;
+  for (int q = 0; q < MQ; ++q) acc[q] = 0.0;
   GRID_STRIDE(i, n) {
     const double wi = w[i];
 #pragma unroll
-    for (int q = 0; q < MAXM; ++q)
+    for (int q = 0; q < MQ; ++q)
       if (q < m) acc[q] += V[q * ld + i] * wi;
   }
   for (int q = 0; q < m; ++q) {
@@ -717,6 +720,14 @@ static __global__ __launch_bounds__(WG) void k_multidot(size_t n, int m, const d
     if (threadIdx.x == 0) part[(size_t)q * gridDim.x + blockIdx.x] = a;
     __syncthreads();
   }
+}
+
+static inline void multidot(hipStream_t st, int g, size_t n, int m, const double* V, size_t ld,
+                            const double* w, double* part) {
+  if (m <= 4) k_multidot<4><<<g, WG, 0, st>>>(n, m, V, ld, w, part);
+  else if (m <= 8) k_multidot<8><<<g, WG, 0, st>>>(n, m, V, ld, w, part);
+  else if (m <= 16) k_multidot<16><<<g, WG, 0, st>>>(n, m, V, ld, w, part);
+  else k_multidot<MAXM><<<g, WG, 0, st>>>(n, m, V, ld, w, part);
 }
 
 // h[q] = sum of the partials of dot q (count each); h2 accumulates into hsum.

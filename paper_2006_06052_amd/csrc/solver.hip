@@ -491,10 +491,10 @@ static void arnoldi_products(mgk_solver* S, int j, double* w, int* nw_unused) {
   const size_t n = S->n;
   const int g = red_grid(n);
   // h = V^T w; w -= V h; h2 = V^T w; w -= V h2; hsum = h + h2; ||w||^2
-  k_multidot<<<g, WG, 0, st>>>(n, j + 1, S->V, n, w, S->part);
+  multidot(st, g, n, j + 1, S->V, n, w, S->part);
   k_multifin<<<1, WG, 0, st>>>(S->part, g, j + 1, S->h, S->hsum, 0);
   k_multiaxpy<<<g, WG, 0, st>>>(n, j + 1, S->V, n, S->h, w, nullptr);
-  k_multidot<<<g, WG, 0, st>>>(n, j + 1, S->V, n, w, S->part);
+  multidot(st, g, n, j + 1, S->V, n, w, S->part);
   k_multifin<<<1, WG, 0, st>>>(S->part, g, j + 1, S->h, S->hsum, 1);
   k_multiaxpy<<<g, WG, 0, st>>>(n, j + 1, S->V, n, S->h, w, S->part);
   finalize(S, g, 0, FIN_STORE1, SC_TMP);
