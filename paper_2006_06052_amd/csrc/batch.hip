@@ -412,8 +412,8 @@ static void gvec(BatchWork& W, int set, int op, bool dots) {
 }
 
 static void gfin(BatchWork& W, int set, int op, int i0 = 0, int i1 = 0) {
-  k_g_finalize<<<1, WG, 0, W.dev.stream>>>(W.dvec + (size_t)set * W.nsys, W.nsys, W.vtotal,
-                                           W.part, op, i0, i1, W.active, W.scb);
+  k_g_finalize<<<W.nsys, WG, 0, W.dev.stream>>>(W.dvec + (size_t)set * W.nsys, W.nsys,
+                                                W.vtotal, W.part, op, i0, i1, W.active, W.scb);
 }
 
 static void gpublish(BatchWork& W) {

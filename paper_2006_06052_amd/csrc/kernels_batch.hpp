@@ -238,20 +238,24 @@ __global__ __launch_bounds__(WG) void k_g_vec(const GVec* __restrict__ vs, int n
 enum GFin { GF_STORE1 = 0, GF_STORE2, GF_ALPHA, GF_OMEGA, GF_RHO };
 
 // Per-system sums of the partials of tiles [tile0, tile0 + ntiles) of one or two
-// partial arrays (each `total` long), in tile order; partial source of GF_ALPHA /
+// partial arrays (each `total` long), in a fixed order; launched with one
+// workgroup per system; partial source of GF_ALPHA /
 // GF_OMEGA is the dot launch over (rhat, v) / (t, s), (t, t).
 __global__ __launch_bounds__(WG) void k_g_finalize(const GVec* __restrict__ vs, int nv, int total,
                                                    const double* __restrict__ part, int op,
                                                    int i0, int i1, const int* __restrict__ active,
                                                    double* __restrict__ scb) {
-  const int q = threadIdx.x;
+  // one workgroup per system: strided partial sums, then the fixed workgroup tree
+  const int q = blockIdx.x;
   if (q >= nv) return;
   const GVec& v = vs[q];
   double a = 0.0, b = 0.0;
-  for (int t = 0; t < v.ntiles; ++t) {
+  for (int t = threadIdx.x; t < v.ntiles; t += WG) {
     a += part[v.tile0 + t];
     b += part[total + v.tile0 + t];
   }
+  wg_sum2(a, b);
+  if (threadIdx.x != 0) return;
   double* sc = scb + (size_t)v.sys * SC_COUNT;
   if (op == GF_STORE1) { sc[i0] = a; return; }
   if (op == GF_STORE2) { sc[i0] = a; sc[i1] = b; return; }

@@ -302,13 +302,16 @@ static __global__ __launch_bounds__(WG) void k_finalize_m(const double* __restri
                                                    int two, int op, int i0, int i1, int K,
                                                    const int* __restrict__ active,
                                                    double* __restrict__ scm) {
-  const int k = threadIdx.x;
+  // one workgroup per column: strided partial sums, then the fixed workgroup tree
+  const int k = blockIdx.x;
   if (k >= K) return;
   double a = 0.0, b = 0.0;
-  for (int q = 0; q < count; ++q) {
+  for (int q = threadIdx.x; q < count; q += WG) {
     a += part[(size_t)q * KL + k];
     if (two) b += part[(size_t)(count + q) * KL + k];
   }
+  wg_sum2(a, b);
+  if (threadIdx.x != 0) return;
   if (!active[k] && op != FINM_STORE1 && op != FINM_STORE2) return;
   double* s = scm;
   switch (op) {

@@ -192,7 +192,7 @@ static void finalize_m(mgk_solver* S, int K, int count, int two, int op, int i0 
     src = W.part2;
     count = nb;
   }
-  k_finalize_m<<<1, KL, 0, st>>>(src, count, two, op, i0, i1, K, W.active, W.scm);
+  k_finalize_m<<<K, WG, 0, st>>>(src, count, two, op, i0, i1, K, W.active, W.scm);
 }
 
 static void publish_m(mgk_solver* S) {
