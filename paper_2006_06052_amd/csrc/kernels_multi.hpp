@@ -1,11 +1,12 @@
 // gfx950 kernels for K <= 32 right-hand sides solved together.
 //
 // Vectors are [n][K] row-major (the K right-hand sides of one scalar row are
-// contiguous).  A group of 32 lanes owns one block row; lane k < K computes
-// every scalar row of that block row for right-hand side k, so each stored
-// block is fetched once per group (the 32 lanes read the same addresses, which
-// the address unit broadcasts) and the x block is read as b coalesced
-// K-element rows.  A workgroup of 256 lanes covers 8 block rows.
+// contiguous).  In the matrix kernels one wavefront owns one block row and lane
+// k < K computes every scalar row of that block row for right-hand side k.  The
+// row index is uniform over the wavefront, so the row's column indices and block
+// values (and the smoother's block) arrive through scalar loads, fetched once per
+// wavefront rather than once per lane, and each x block is read as b coalesced
+// K-element rows.  A workgroup of 256 lanes covers 4 block rows.
 //
 // The products are HBM-bound (about 2 flop per byte of matrix per right-hand
 // side), so vector FMA is used, not MFMA.  Each output sums its blocks in
@@ -15,8 +16,21 @@
 
 namespace mgk {
 
-constexpr int KL = 32;                 // lanes per block-row group (max right-hand sides)
-constexpr int MROWS = WG / KL;         // block rows per workgroup
+constexpr int KL = 32;                 // max right-hand sides (lanes per column slot)
+constexpr int MROWS = WG / KL;         // row slots per workgroup in the vector kernels
+constexpr int WROWS = WG / 64;         // block rows per workgroup in the matrix kernels
+
+// Block row of this wavefront for logical workgroup lw of RW rows (one row per
+// wavefront, made uniform so that loads indexed by it become scalar loads).
+template <int RW = WROWS>
+__device__ __forceinline__ int wave_row(int lw) {
+  return lw * RW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// The fused-dot product runs 8 wavefronts per workgroup, so each per-column
+// partial covers 8 consecutive block rows summed in row order.
+constexpr int MDOT_WG = 512;
+constexpr int MDOT_ROWS = MDOT_WG / 64;
 
 template <int B, class TV, class TA>
 __device__ __forceinline__ void load_block(const TV* __restrict__ p, TA* out) {
@@ -30,7 +44,17 @@ __device__ __forceinline__ void load_block(const TV* __restrict__ p, TA* out) {
   }
 }
 
+// Blocks fetched together per step of block_row_multi: their column indices,
+// values and x rows are requested before the first FMA of the step.  The values
+// sit in scalar registers, so the step holds at most 128 bytes of them per block
+// times MU (4 blocks of FP32 4x4, 2 of FP64).
+template <int BR, int BC, class TV>
+constexpr int multi_unroll() { return sizeof(TV) * BR * BC > 64 ? 2 : 4; }
+
 // acc[r] = sum over blocks (i, j) of sum_c A_ij[r][c] X[j*BC + c][k]  (r < BR).
+// Blocks of a step past the row's end re-read the row's last block (in bounds)
+// and are skipped at the FMA, so the sum runs over the blocks in ascending order
+// whatever the unroll is.
 template <int BR, int BC, class TV, class TX, class TA>
 __device__ __forceinline__ void block_row_multi(int i, int k, int K, const int* __restrict__ ptr,
                                                 const int* __restrict__ col,
@@ -38,28 +62,44 @@ __device__ __forceinline__ void block_row_multi(int i, int k, int K, const int* 
                                                 const TX* __restrict__ X, TA* acc) {
 #pragma unroll
   for (int r = 0; r < BR; ++r) acc[r] = 0;
+  constexpr int MU = multi_unroll<BR, BC, TV>();
   const int k0 = ptr[i], k1 = ptr[i + 1];
-  for (int kb = k0; kb < k1; ++kb) {
-    const int j = col[kb];
-    TA a[BR * BC];
-    if constexpr (BR == BC) {
-      load_block<BR, TV, TA>(val + (size_t)kb * BR * BC, a);
-    } else {
+  for (int kb = k0; kb < k1; kb += MU) {
+    int j[MU];
 #pragma unroll
-      for (int e = 0; e < BR * BC; ++e) {
-        if constexpr (sizeof(TV) == 2)
-          a[e] = (TA)bf16_to_f32(reinterpret_cast<const uint16_t*>(val)[(size_t)kb * BR * BC + e]);
-        else
-          a[e] = (TA)val[(size_t)kb * BR * BC + e];
+    for (int u = 0; u < MU; ++u) j[u] = col[min(kb + u, k1 - 1)];
+    TA a[MU][BR * BC];
+#pragma unroll
+    for (int u = 0; u < MU; ++u) {
+      const size_t kk = (size_t)min(kb + u, k1 - 1);
+      if constexpr (BR == BC) {
+        load_block<BR, TV, TA>(val + kk * BR * BC, a[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < BR * BC; ++e) {
+          if constexpr (sizeof(TV) == 2)
+            a[u][e] = (TA)bf16_to_f32(reinterpret_cast<const uint16_t*>(val)[kk * BR * BC + e]);
+          else
+            a[u][e] = (TA)val[kk * BR * BC + e];
+        }
       }
     }
-    TA xv[BC];
+    TA xv[MU][BC];
 #pragma unroll
-    for (int c = 0; c < BC; ++c) xv[c] = (TA)X[((size_t)j * BC + c) * K + k];
+    for (int u = 0; u < MU; ++u)
 #pragma unroll
-    for (int r = 0; r < BR; ++r)
+      for (int c = 0; c < BC; ++c) xv[u][c] = (TA)X[((size_t)j[u] * BC + c) * K + k];
 #pragma unroll
-      for (int c = 0; c < BC; ++c) acc[r] = fma_(a[r * BC + c], xv[c], acc[r]);
+    for (int u = 0; u < MU; ++u) {
+      const bool in_row = kb + u < k1;
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        TA t = acc[r];
+#pragma unroll
+        for (int c = 0; c < BC; ++c) t = fma_(a[u][r * BC + c], xv[u][c], t);
+        acc[r] = in_row ? t : acc[r];
+      }
+    }
   }
 }
 
@@ -70,8 +110,8 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
                                              const TV* __restrict__ val,
                                              const TX* __restrict__ X, TY* __restrict__ Y,
                                              TA alpha, TA beta) {
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
+  const int i = wave_row(xcd_remap(blockIdx.x, gridDim.x));
+  const int k = threadIdx.x & 63;
   if (i >= nbr || k >= K) return;
   TA acc[BR];
   block_row_multi<BR, BC, TV, TX, TA>(i, k, K, ptr, col, val, X, acc);
@@ -85,9 +125,10 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
 }
 
 // Y = A X (FP64) with per-column partials of <W1_k, Y_k> and (two) <Y_k, Y_k>:
-// part[w * KL + k] and part[(G + w) * KL + k] for workgroup w of G.
+// part[w * KL + k] and part[(G + w) * KL + k] for workgroup w of G (the
+// workgroup's 8 rows summed in order).
 template <int B>
-__global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __restrict__ ptr,
+__global__ __launch_bounds__(MDOT_WG) void k_spmm_dot(int nbr, int K, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ val,
                                                  const double* __restrict__ X,
@@ -95,8 +136,8 @@ __global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __re
                                                  const double* __restrict__ W1,
                                                  double* __restrict__ part) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = lw * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
+  const int i = wave_row<MDOT_ROWS>(lw);
+  const int k = threadIdx.x & 63;
   double d1 = 0.0, d2 = 0.0;
   if (i < nbr && k < K) {
     double acc[B];
@@ -109,15 +150,15 @@ __global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __re
       d2 = fma_(acc[r], acc[r], d2);
     }
   }
-  __shared__ double sa[WG], sb[WG];
+  __shared__ double sa[MDOT_WG], sb[MDOT_WG];
   sa[threadIdx.x] = d1;
   sb[threadIdx.x] = d2;
   __syncthreads();
   if (threadIdx.x < KL) {
     double x = 0.0, y = 0.0;
-    for (int q = 0; q < MROWS; ++q) {
-      x += sa[q * KL + threadIdx.x];
-      y += sb[q * KL + threadIdx.x];
+    for (int q = 0; q < MDOT_ROWS; ++q) {
+      x += sa[q * 64 + threadIdx.x];
+      y += sb[q * 64 + threadIdx.x];
     }
     part[(size_t)lw * KL + threadIdx.x] = x;
     if (two) part[(size_t)(gridDim.x + lw) * KL + threadIdx.x] = y;
@@ -161,8 +202,8 @@ __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __
                                                    const TF* __restrict__ F,
                                                    const TX* __restrict__ Z,
                                                    TX* __restrict__ T) {
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
+  const int i = wave_row(xcd_remap(blockIdx.x, gridDim.x));
+  const int k = threadIdx.x & 63;
   if (i >= nbr || k >= K) return;
   TA acc[BR];
   block_row_multi<BR, BC, TV, TX, TA>(i, k, K, ptr, col, val, Z, acc);
@@ -182,8 +223,8 @@ __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __re
                                                  const TF* __restrict__ F,
                                                  const TX* __restrict__ Z,
                                                  TO* __restrict__ Zout) {
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
+  const int i = wave_row(xcd_remap(blockIdx.x, gridDim.x));
+  const int k = threadIdx.x & 63;
   if (i >= nbr || k >= K) return;
   TA acc[B];
   block_row_multi<B, B, TV, TX, TA>(i, k, K, ptr, col, val, Z, acc);
@@ -206,8 +247,8 @@ template <int B, class TM, class TF, class TX, class TA>
 __global__ __launch_bounds__(WG) void k_block_diag_m(int nbr, int K, const TM* __restrict__ M,
                                                      const TF* __restrict__ F,
                                                      TX* __restrict__ Z) {
-  const int i = blockIdx.x * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
+  const int i = wave_row(blockIdx.x);
+  const int k = threadIdx.x & 63;
   if (i >= nbr || k >= K) return;
   const TM* m = M + (size_t)i * B * B;
   TA f[B];
@@ -223,13 +264,13 @@ __global__ __launch_bounds__(WG) void k_block_diag_m(int nbr, int K, const TM* _
 }
 
 // Z = Cinv R for the dense FP64 coarsest inverse (n x n), R and Z [n][K]:
-// 8 rows of Z per workgroup, lane k per right-hand side, j ascending.
+// one row of Z per wavefront, lane k per right-hand side, j ascending.
 template <class TI, class TO>
 __global__ __launch_bounds__(WG) void k_coarse_gemm(int n, int K, const double* __restrict__ Cinv,
                                                     const TI* __restrict__ R,
                                                     TO* __restrict__ Z) {
-  const int i = blockIdx.x * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
+  const int i = wave_row(blockIdx.x);
+  const int k = threadIdx.x & 63;
   if (i >= n || k >= K) return;
   const double* a = Cinv + (size_t)i * n;
   double acc = 0.0;
