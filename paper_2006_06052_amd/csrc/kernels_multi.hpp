@@ -1,36 +1,45 @@
 // gfx950 kernels for K <= 32 right-hand sides solved together.
 //
 // Vectors are [n][K] row-major (the K right-hand sides of one scalar row are
-// contiguous).  In the matrix kernels one wavefront owns one block row and lane
-// k < K computes every scalar row of that block row for right-hand side k.  The
-// row index is uniform over the wavefront, so the row's column indices and block
-// values (and the smoother's block) arrive through scalar loads, fetched once per
-// wavefront rather than once per lane, and each x block is read as b coalesced
-// K-element rows.  A workgroup of 256 lanes covers 4 block rows.
+// contiguous).  In the matrix kernels a workgroup of 256 lanes covers 8 block
+// rows, 32 lanes per row, and lane k < K computes every scalar row of its block
+// row for right-hand side k.  The workgroup first copies its rows' column indices
+// and block values (a contiguous range) into LDS with coalesced loads; each lane
+// then reads them from LDS, so a stored block is fetched from HBM once, and reads
+// each x block as b coalesced K-element rows.
 //
 // The products are HBM-bound (about 2 flop per byte of matrix per right-hand
 // side), so vector FMA is used, not MFMA.  Each output sums its blocks in
 // ascending order with explicit FMAs.
 #pragma once
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mgk {
 
-constexpr int KL = 32;                 // max right-hand sides (lanes per column slot)
-constexpr int MROWS = WG / KL;         // row slots per workgroup in the vector kernels
-constexpr int WROWS = WG / 64;         // block rows per workgroup in the matrix kernels
+constexpr int KL = 32;                 // max right-hand sides (lanes per half-wavefront)
+constexpr int MROWS = WG / KL;         // block rows (row slots) per workgroup
 
-// Block row of this wavefront for logical workgroup lw of RW rows (one row per
-// wavefront, made uniform so that loads indexed by it become scalar loads).
-template <int RW = WROWS>
-__device__ __forceinline__ int wave_row(int lw) {
-  return lw * RW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+// Matrix kernels: a wavefront owns two block rows, i0 (lanes 0-31) and i0 + 1
+// (lanes 32-63); lane k = lane & 31 is the right-hand side.  i0 is uniform over
+// the wavefront (the smoother's diagonal blocks of both rows arrive through
+// scalar loads and each half selects its own).
+struct MRow {
+  int i0;  // first row of the pair (uniform)
+  int h;   // 0: row i0, 1: row i0 + 1
+  int i;   // i0 + h
+  int k;   // right-hand side
+};
+
+__device__ __forceinline__ MRow mrow(int lw) {
+  MRow m;
+  m.i0 = lw * MROWS + 2 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  m.h = (threadIdx.x >> 5) & 1;
+  m.i = m.i0 + m.h;
+  m.k = threadIdx.x & 31;
+  return m;
 }
-
-// The fused-dot product runs 8 wavefronts per workgroup, so each per-column
-// partial covers 8 consecutive block rows summed in row order.
-constexpr int MDOT_WG = 512;
-constexpr int MDOT_ROWS = MDOT_WG / 64;
 
 template <int B, class TV, class TA>
 __device__ __forceinline__ void load_block(const TV* __restrict__ p, TA* out) {
@@ -44,63 +53,119 @@ __device__ __forceinline__ void load_block(const TV* __restrict__ p, TA* out) {
   }
 }
 
-// Blocks fetched together per step of block_row_multi: their column indices,
-// values and x rows are requested before the first FMA of the step.  The values
-// sit in scalar registers, so the step holds at most 128 bytes of them per block
-// times MU (4 blocks of FP32 4x4, 2 of FP64).
-template <int BR, int BC, class TV>
-constexpr int multi_unroll() { return sizeof(TV) * BR * BC > 64 ? 2 : 4; }
+template <int BR, int BC, class TV, class TA>
+__device__ __forceinline__ void load_rect(const TV* __restrict__ p, TA* out) {
+  if constexpr (BR == BC) {
+    load_block<BR, TV, TA>(p, out);
+  } else {
+#pragma unroll
+    for (int e = 0; e < BR * BC; ++e) {
+      if constexpr (sizeof(TV) == 2)
+        out[e] = (TA)bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[e]);
+      else
+        out[e] = (TA)p[e];
+    }
+  }
+}
 
-// acc[r] = sum over blocks (i, j) of sum_c A_ij[r][c] X[j*BC + c][k]  (r < BR).
-// Blocks of a step past the row's end re-read the row's last block (in bounds)
-// and are skipped at the FMA, so the sum runs over the blocks in ascending order
-// whatever the unroll is.
+// Matrix values and column indices staged in LDS per pass (at most 16 KB of
+// values): the workgroup's 8 rows own the contiguous block range
+// [ptr[r0], ptr[r0 + 8]), which is copied with coalesced loads, so no lane waits
+// on a column index or a block from HBM one block at a time.
+template <int BR, int BC, class TV>
+constexpr int mstage_cap() { return 16384 / (BR * BC * (int)sizeof(TV)); }
+
+// x rows requested together per step of a lane's walk over its row.
+constexpr int MU = 4;
+
+// acc[r] = sum over blocks (i, j) of sum_c A_ij[r][c] X[j*BC + c][k]  (r < BR) for
+// row i of the workgroup whose rows start at r0 (on: the lane has a row and a
+// right-hand side).  Every lane of the workgroup must call this (it holds
+// barriers).  Each row sums its blocks in ascending order: passes ascend, and
+// within a pass the lane walks its row's blocks in order; steps past the row's
+// end re-read an in-bounds block and are skipped at the FMA.
 template <int BR, int BC, class TV, class TX, class TA>
-__device__ __forceinline__ void block_row_multi(int i, int k, int K, const int* __restrict__ ptr,
-                                                const int* __restrict__ col,
-                                                const TV* __restrict__ val,
-                                                const TX* __restrict__ X, TA* acc) {
+__device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool on, int k, int K,
+                                                  const int* __restrict__ ptr,
+                                                  const int* __restrict__ col,
+                                                  const TV* __restrict__ val,
+                                                  const TX* __restrict__ X, TA* acc) {
+  constexpr int BB = BR * BC;
+  constexpr int CAP = mstage_cap<BR, BC, TV>();
+  typedef typename std::conditional<sizeof(TV) == 2, uint16_t, TV>::type TS;
+  __shared__ int s_col[CAP];
+  __shared__ TS s_val[CAP * BB];
 #pragma unroll
   for (int r = 0; r < BR; ++r) acc[r] = 0;
-  constexpr int MU = multi_unroll<BR, BC, TV>();
-  const int k0 = ptr[i], k1 = ptr[i + 1];
-  for (int kb = k0; kb < k1; kb += MU) {
-    int j[MU];
+  const TS* gval = reinterpret_cast<const TS*>(val);
+  const int c_begin = ptr[r0], c_end = ptr[min(r0 + MROWS, nbr)];
+  const int k0 = on ? ptr[i] : 0, k1 = on ? ptr[i + 1] : 0;
+  for (int c = c_begin; c < c_end; c += CAP) {
+    const int cn = min(CAP, c_end - c);
+    // every load of the pass is issued before the first LDS write
+    constexpr int NC = (CAP + WG - 1) / WG, NV = (CAP * BB + WG - 1) / WG;
+    int tc[NC];
+    TS tv[NV];
 #pragma unroll
-    for (int u = 0; u < MU; ++u) j[u] = col[min(kb + u, k1 - 1)];
-    TA a[MU][BR * BC];
+    for (int u = 0; u < NC; ++u) {
+      const int q = threadIdx.x + u * WG;
+      if (q < cn) tc[u] = col[c + q];
+    }
 #pragma unroll
-    for (int u = 0; u < MU; ++u) {
-      const size_t kk = (size_t)min(kb + u, k1 - 1);
-      if constexpr (BR == BC) {
-        load_block<BR, TV, TA>(val + kk * BR * BC, a[u]);
-      } else {
+    for (int u = 0; u < NV; ++u) {
+      const int q = threadIdx.x + u * WG;
+      if (q < cn * BB) tv[u] = gval[(size_t)c * BB + q];
+    }
 #pragma unroll
-        for (int e = 0; e < BR * BC; ++e) {
-          if constexpr (sizeof(TV) == 2)
-            a[u][e] = (TA)bf16_to_f32(reinterpret_cast<const uint16_t*>(val)[kk * BR * BC + e]);
-          else
-            a[u][e] = (TA)val[kk * BR * BC + e];
+    for (int u = 0; u < NC; ++u) {
+      const int q = threadIdx.x + u * WG;
+      if (q < cn) s_col[q] = tc[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int q = threadIdx.x + u * WG;
+      if (q < cn * BB) s_val[q] = tv[u];
+    }
+    __syncthreads();
+    const int lo = max(k0, c), hi = min(k1, c + cn);
+    for (int kb = lo; kb < hi; kb += MU) {
+      int q[MU];
+      TA xv[MU][BC];
+#pragma unroll
+      for (int u = 0; u < MU; ++u) {
+        q[u] = min(kb + u, hi - 1) - c;
+        const int j = s_col[q[u]];
+#pragma unroll
+        for (int cc = 0; cc < BC; ++cc) xv[u][cc] = (TA)X[((size_t)j * BC + cc) * K + k];
+      }
+#pragma unroll
+      for (int u = 0; u < MU; ++u) {
+        TA a[BB];
+        load_rect<BR, BC, TV, TA>(reinterpret_cast<const TV*>(s_val + q[u] * BB), a);
+        const bool in_row = kb + u < hi;
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+          TA t = acc[r];
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) t = fma_(a[r * BC + cc], xv[u][cc], t);
+          acc[r] = in_row ? t : acc[r];
         }
       }
     }
-    TA xv[MU][BC];
-#pragma unroll
-    for (int u = 0; u < MU; ++u)
-#pragma unroll
-      for (int c = 0; c < BC; ++c) xv[u][c] = (TA)X[((size_t)j[u] * BC + c) * K + k];
-#pragma unroll
-    for (int u = 0; u < MU; ++u) {
-      const bool in_row = kb + u < k1;
-#pragma unroll
-      for (int r = 0; r < BR; ++r) {
-        TA t = acc[r];
-#pragma unroll
-        for (int c = 0; c < BC; ++c) t = fma_(a[u][r * BC + c], xv[u][c], t);
-        acc[r] = in_row ? t : acc[r];
-      }
-    }
+    __syncthreads();
   }
+}
+
+// Block M_i of a block-diagonal matrix for the lane's row, both rows' blocks
+// fetched through scalar loads.
+template <int B, class TM, class TA>
+__device__ __forceinline__ void diag_block(const MRow& m, bool has_b, const TM* __restrict__ M,
+                                           TA* out) {
+  TA va[B * B], vb[B * B];
+  load_block<B, TM, TA>(M + (size_t)m.i0 * B * B, va);
+  load_block<B, TM, TA>(M + (size_t)(has_b ? m.i0 + 1 : m.i0) * B * B, vb);
+#pragma unroll
+  for (int e = 0; e < B * B; ++e) out[e] = m.h ? vb[e] : va[e];
 }
 
 // Y = alpha A X + beta Y.
@@ -110,11 +175,13 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
                                              const TV* __restrict__ val,
                                              const TX* __restrict__ X, TY* __restrict__ Y,
                                              TA alpha, TA beta) {
-  const int i = wave_row(xcd_remap(blockIdx.x, gridDim.x));
-  const int k = threadIdx.x & 63;
-  if (i >= nbr || k >= K) return;
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const MRow m = mrow(lw);
+  const int i = m.i, k = m.k;
+  const bool on = i < nbr && k < K;
   TA acc[BR];
-  block_row_multi<BR, BC, TV, TX, TA>(i, k, K, ptr, col, val, X, acc);
+  block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, X, acc);
+  if (!on) return;
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const size_t e = ((size_t)i * BR + r) * K + k;
@@ -128,7 +195,7 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
 // part[w * KL + k] and part[(G + w) * KL + k] for workgroup w of G (the
 // workgroup's 8 rows summed in order).
 template <int B>
-__global__ __launch_bounds__(MDOT_WG) void k_spmm_dot(int nbr, int K, const int* __restrict__ ptr,
+__global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ val,
                                                  const double* __restrict__ X,
@@ -136,29 +203,31 @@ __global__ __launch_bounds__(MDOT_WG) void k_spmm_dot(int nbr, int K, const int*
                                                  const double* __restrict__ W1,
                                                  double* __restrict__ part) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = wave_row<MDOT_ROWS>(lw);
-  const int k = threadIdx.x & 63;
+  const MRow m = mrow(lw);
+  const bool on = m.i < nbr && m.k < K;
   double d1 = 0.0, d2 = 0.0;
-  if (i < nbr && k < K) {
-    double acc[B];
-    block_row_multi<B, B, double, double, double>(i, k, K, ptr, col, val, X, acc);
+  double acc[B];
+  block_rows_staged<B, B, double, double, double>(lw * MROWS, nbr, m.i, on, m.k, K, ptr, col, val,
+                                                  X, acc);
+  if (on) {
 #pragma unroll
     for (int r = 0; r < B; ++r) {
-      const size_t e = ((size_t)i * B + r) * K + k;
+      const size_t e = ((size_t)m.i * B + r) * K + m.k;
       Y[e] = acc[r];
       d1 = fma_(W1[e], acc[r], d1);
       d2 = fma_(acc[r], acc[r], d2);
     }
   }
-  __shared__ double sa[MDOT_WG], sb[MDOT_WG];
+  // lane (w, h, k) holds row lw * 8 + 2 w + h = lw * 8 + threadIdx.x / 32
+  __shared__ double sa[WG], sb[WG];
   sa[threadIdx.x] = d1;
   sb[threadIdx.x] = d2;
   __syncthreads();
   if (threadIdx.x < KL) {
     double x = 0.0, y = 0.0;
-    for (int q = 0; q < MDOT_ROWS; ++q) {
-      x += sa[q * 64 + threadIdx.x];
-      y += sb[q * 64 + threadIdx.x];
+    for (int q = 0; q < MROWS; ++q) {
+      x += sa[q * KL + threadIdx.x];
+      y += sb[q * KL + threadIdx.x];
     }
     part[(size_t)lw * KL + threadIdx.x] = x;
     if (two) part[(size_t)(gridDim.x + lw) * KL + threadIdx.x] = y;
@@ -202,11 +271,13 @@ __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __
                                                    const TF* __restrict__ F,
                                                    const TX* __restrict__ Z,
                                                    TX* __restrict__ T) {
-  const int i = wave_row(xcd_remap(blockIdx.x, gridDim.x));
-  const int k = threadIdx.x & 63;
-  if (i >= nbr || k >= K) return;
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const MRow m = mrow(lw);
+  const int i = m.i, k = m.k;
+  const bool on = i < nbr && k < K;
   TA acc[BR];
-  block_row_multi<BR, BC, TV, TX, TA>(i, k, K, ptr, col, val, Z, acc);
+  block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, Z, acc);
+  if (!on) return;
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const size_t e = ((size_t)i * BR + r) * K + k;
@@ -223,21 +294,25 @@ __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __re
                                                  const TF* __restrict__ F,
                                                  const TX* __restrict__ Z,
                                                  TO* __restrict__ Zout) {
-  const int i = wave_row(xcd_remap(blockIdx.x, gridDim.x));
-  const int k = threadIdx.x & 63;
-  if (i >= nbr || k >= K) return;
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const MRow m = mrow(lw);
+  const int i = m.i, k = m.k;
+  const bool on = i < nbr && k < K;
   TA acc[B];
-  block_row_multi<B, B, TV, TX, TA>(i, k, K, ptr, col, val, Z, acc);
+  block_rows_staged<B, B, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, Z, acc);
+  if (m.i0 >= nbr) return;
+  TA mb[B * B];
+  diag_block<B, TM, TA>(m, m.i0 + 1 < nbr, M, mb);
+  if (!on) return;
   TA res[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) res[r] = (TA)F[((size_t)i * B + r) * K + k] - acc[r];
-  const TM* m = M + (size_t)i * B * B;
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     const size_t e = ((size_t)i * B + r) * K + k;
     TA out = (TA)Z[e];
 #pragma unroll
-    for (int c = 0; c < B; ++c) out = fma_((TA)m[r * B + c], res[c], out);
+    for (int c = 0; c < B; ++c) out = fma_(mb[r * B + c], res[c], out);
     Zout[e] = (TO)out;
   }
 }
@@ -247,10 +322,12 @@ template <int B, class TM, class TF, class TX, class TA>
 __global__ __launch_bounds__(WG) void k_block_diag_m(int nbr, int K, const TM* __restrict__ M,
                                                      const TF* __restrict__ F,
                                                      TX* __restrict__ Z) {
-  const int i = wave_row(blockIdx.x);
-  const int k = threadIdx.x & 63;
+  const MRow m = mrow(blockIdx.x);
+  if (m.i0 >= nbr) return;
+  TA mb[B * B];
+  diag_block<B, TM, TA>(m, m.i0 + 1 < nbr, M, mb);
+  const int i = m.i, k = m.k;
   if (i >= nbr || k >= K) return;
-  const TM* m = M + (size_t)i * B * B;
   TA f[B];
 #pragma unroll
   for (int c = 0; c < B; ++c) f[c] = (TA)F[((size_t)i * B + c) * K + k];
@@ -258,19 +335,19 @@ __global__ __launch_bounds__(WG) void k_block_diag_m(int nbr, int K, const TM* _
   for (int r = 0; r < B; ++r) {
     TA acc = 0;
 #pragma unroll
-    for (int c = 0; c < B; ++c) acc = fma_((TA)m[r * B + c], f[c], acc);
+    for (int c = 0; c < B; ++c) acc = fma_(mb[r * B + c], f[c], acc);
     Z[((size_t)i * B + r) * K + k] = (TX)acc;
   }
 }
 
 // Z = Cinv R for the dense FP64 coarsest inverse (n x n), R and Z [n][K]:
-// one row of Z per wavefront, lane k per right-hand side, j ascending.
+// 8 rows of Z per workgroup, lane k per right-hand side, j ascending.
 template <class TI, class TO>
 __global__ __launch_bounds__(WG) void k_coarse_gemm(int n, int K, const double* __restrict__ Cinv,
                                                     const TI* __restrict__ R,
                                                     TO* __restrict__ Z) {
-  const int i = wave_row(blockIdx.x);
-  const int k = threadIdx.x & 63;
+  const int i = blockIdx.x * MROWS + threadIdx.x / KL;
+  const int k = threadIdx.x % KL;
   if (i >= n || k >= K) return;
   const double* a = Cinv + (size_t)i * n;
   double acc = 0.0;

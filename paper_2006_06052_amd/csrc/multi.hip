@@ -75,7 +75,7 @@ static MultiWork* ensure_multi(mgk_solver* S) {
     W->active = (int*)W->alloc(sizeof(int) * KL);
     W->mask = (int*)W->alloc(sizeof(int) * KL);
     // per-column partial rows: two dots per SpMM workgroup (8 block rows each)
-    W->part_rows = 2 * ((size_t)S->nbr / WROWS + 2) + 2 * 1024;
+    W->part_rows = 2 * ((size_t)S->nbr / MROWS + 2) + 2 * 1024;
     W->part = (double*)W->alloc(sizeof(double) * KL * W->part_rows);
     W->part2 = (double*)W->alloc(sizeof(double) * KL * (2 * (W->part_rows / MRED_CHUNK + 2)));
     HIPCK(hipHostMalloc((void**)&W->hsc, sizeof(double) * SM_COUNT * KL, hipHostMallocDefault));
@@ -103,15 +103,15 @@ struct CycleM {
     DLevel& L = H.lv[l];
     const int nl = (int)H.lv.size();
     if (l == nl - 1) {
-      k_coarse_gemm<TIN, TOUT><<<(H.nc + WROWS - 1) / WROWS, WG, 0, st>>>(H.nc, K, H.cinv, r,
+      k_coarse_gemm<TIN, TOUT><<<(H.nc + MROWS - 1) / MROWS, WG, 0, st>>>(H.nc, K, H.cinv, r,
                                                                           zout);
       return;
     }
     TX* z = (TX*)W.lv[l].z;
     TX* t = (TX*)W.lv[l].t;
     MLevel& C = W.lv[l + 1];
-    const int g = (L.nbr + WROWS - 1) / WROWS;
-    const int gr = (L.R.nbr + WROWS - 1) / WROWS;
+    const int g = (L.nbr + MROWS - 1) / MROWS;
+    const int gr = (L.R.nbr + MROWS - 1) / MROWS;
     k_block_diag_m<B, TM, TIN, TX, TA><<<g, WG, 0, st>>>(L.nbr, K, (const TM*)L.M, r, z);
     k_residual_m<B, B, TV, TX, TIN, TA><<<g, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col,
                                                            (const TV*)L.A.val, r, z, t);
@@ -153,7 +153,7 @@ static void vcycle_m(mgk_solver* S, int K, const double* r, double* z) {
 
 static void outer_residual_m(mgk_solver* S, int K, const double* B, const double* X, double* R) {
   hipStream_t st = S->dev.stream;
-  const int g = (S->nbr + WROWS - 1) / WROWS;
+  const int g = (S->nbr + MROWS - 1) / MROWS;
   const DMat& A = S->A;
   switch (S->b) {
     case 1: k_residual_m<1, 1, double, double, double, double><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, B, X, R); break;
@@ -166,13 +166,13 @@ static void outer_residual_m(mgk_solver* S, int K, const double* B, const double
 static int outer_spmm_dot(mgk_solver* S, int K, const double* X, double* Y, int two,
                           const double* W1) {
   hipStream_t st = S->dev.stream;
-  const int g = (S->nbr + MDOT_ROWS - 1) / MDOT_ROWS;
+  const int g = (S->nbr + MROWS - 1) / MROWS;
   const DMat& A = S->A;
   double* part = S->multi->part;
   switch (S->b) {
-    case 1: k_spmm_dot<1><<<g, MDOT_WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
-    case 3: k_spmm_dot<3><<<g, MDOT_WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
-    case 4: k_spmm_dot<4><<<g, MDOT_WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
+    case 1: k_spmm_dot<1><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
+    case 3: k_spmm_dot<3><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
+    case 4: k_spmm_dot<4><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
   }
   return g;
 }
