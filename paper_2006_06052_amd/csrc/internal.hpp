@@ -108,7 +108,21 @@ struct DMat {
   int *tptr = nullptr, *trow = nullptr, *tblk = nullptr;
   double avg_row = 0.0, avg_col = 0.0;
   Tile tile, ttile;          // engine tiles for products with A and with A^T
+  bool cached = false;       // values and columns read with cached loads
 };
+
+// Value loads of the block-row kernels: streamed (non-temporal) for FP64 and FP32
+// operators, which keeps the gathered vector resident in L2 and the Infinity Cache;
+// ordinary (cached) loads for BF16 operators, measured 6% faster over a whole
+// BF16-hierarchy solve at 96^3 while the same switch made the FP32 hierarchy 1-2%
+// slower.  The environment variable MGK_CACHED_LOADS, read at setup, overrides the
+// choice (0: stream every operator, 1: BF16 operators cached, 2: every operator
+// cached).  Results are bitwise the same either way.
+inline bool operator_cached(int storage) {
+  const char* e = getenv("MGK_CACHED_LOADS");
+  const int mode = e ? atoi(e) : 1;
+  return mode >= 2 || (mode == 1 && storage == MGK_BF16);
+}
 
 inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index) {
   DMat M;
@@ -132,6 +146,7 @@ inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_ind
     for (size_t i = 0; i < nv; ++i) v[i] = f32_to_bf16((float)A.val[i]);
     M.val = D.upload(v.data(), nv);
   }
+  M.cached = operator_cached(storage);
   M.avg_row = A.nbr ? (double)M.nnzb / A.nbr : 0.0;
   if (transpose_index) {
     std::vector<int> tp(A.nbc + 1, 0), tr(M.nnzb), tb(M.nnzb);
@@ -242,8 +257,12 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, 
   tile_switch_r<BR, wide_ok<BR, BC, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
     const int g = nwg_rows<BR, S_, R_>(nrows);
-    k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
-                                                                        (TA)alpha, (TA)beta);
+    if (M.cached)
+      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_, true><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta);
+    else
+      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
+                                                                          (TA)alpha, (TA)beta);
   });
 }
 
@@ -291,8 +310,12 @@ static void residual_s(hipStream_t st, const DMat& M, bool trans, const Tile& ti
   tile_switch_r<BR, wide_ok<BR, BC, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
     const int g = nwg_rows<BR, S_, R_>(nrows);
-    k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
-                                                                             f, z, t);
+    if (M.cached)
+      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_, true><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, f, z, t);
+    else
+      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
+                                                                               f, z, t);
   });
 }
 
@@ -317,8 +340,12 @@ static void smooth_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile
   tile_switch_r<B, wide_ok<B, B, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
     const int g = nwg_rows<B, S_, R_>(nrows);
-    k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
-                                                                              Mb, f, z, zout);
+    if (M.cached)
+      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_, true><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, Mb, f, z, zout);
+    else
+      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
+                                                                                Mb, f, z, zout);
   });
 }
 

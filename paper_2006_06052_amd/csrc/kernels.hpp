@@ -53,22 +53,31 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t u) {
 
 // ---- value loads -----------------------------------------------------------
 
+// A value load: streamed (non-temporal) by default; ordinary (cached) loads for
+// the values of operators small enough to stay in the Infinity Cache between
+// their uses in a cycle.
+template <bool CACHED, class T>
+__device__ __forceinline__ T ld_val(const T* p) {
+  if constexpr (CACHED) return *p;
+  else return __builtin_nontemporal_load(p);
+}
+
 // BC consecutive values of a stored block (one block row, or several adjacent
-// block rows for the wide BF16 lanes), streamed (non-temporal).
-template <int BC, class TV, class TA>
+// block rows for the wide BF16 lanes).
+template <int BC, class TV, class TA, bool CACHED = false>
 __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
   if constexpr (sizeof(TV) == 8 && BC == 4) {
-    const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
-    const d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p) + 1);
+    const d2v a = ld_val<CACHED>(reinterpret_cast<const d2v*>(p));
+    const d2v b = ld_val<CACHED>(reinterpret_cast<const d2v*>(p) + 1);
     out[0] = a.x; out[1] = a.y; out[2] = b.x; out[3] = b.y;
   } else if constexpr (sizeof(TV) == 4 && BC == 4) {
-    const f4v a = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    const f4v a = ld_val<CACHED>(reinterpret_cast<const f4v*>(p));
     out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
   } else if constexpr (sizeof(TV) == 2 && BC % 8 == 0) {
     // several consecutive block rows: 16-byte loads of eight values each
 #pragma unroll
     for (int q = 0; q < BC / 8; ++q) {
-      const u4v a = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p) + q);
+      const u4v a = ld_val<CACHED>(reinterpret_cast<const u4v*>(p) + q);
       out[8 * q + 0] = __uint_as_float(a.x << 16);
       out[8 * q + 1] = __uint_as_float(a.x & 0xffff0000u);
       out[8 * q + 2] = __uint_as_float(a.y << 16);
@@ -79,7 +88,7 @@ __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
       out[8 * q + 7] = __uint_as_float(a.w & 0xffff0000u);
     }
   } else if constexpr (sizeof(TV) == 2 && BC == 4) {
-    const u2v a = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+    const u2v a = ld_val<CACHED>(reinterpret_cast<const u2v*>(p));
     out[0] = __uint_as_float(a.x << 16);
     out[1] = __uint_as_float(a.x & 0xffff0000u);
     out[2] = __uint_as_float(a.y << 16);
@@ -87,10 +96,10 @@ __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
   } else if constexpr (sizeof(TV) == 2) {
     const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
 #pragma unroll
-    for (int c = 0; c < BC; ++c) out[c] = (TA)bf16_to_f32(__builtin_nontemporal_load(q + c));
+    for (int c = 0; c < BC; ++c) out[c] = (TA)bf16_to_f32(ld_val<CACHED>(q + c));
   } else {
 #pragma unroll
-    for (int c = 0; c < BC; ++c) out[c] = (TA)__builtin_nontemporal_load(p + c);
+    for (int c = 0; c < BC; ++c) out[c] = (TA)ld_val<CACHED>(p + c);
   }
 }
 
@@ -177,7 +186,8 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
 // short and would otherwise be bound by one dependent col -> x chain per
 // block).  When T > U the stripe accumulators rotate by U after each step so
 // that block u of a step always lands in accumulator u.
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA, int RPL>
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA, int RPL,
+          bool CACHED = false>
 __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
                                               const int* __restrict__ ptr,
                                               const int* __restrict__ col,
@@ -204,7 +214,7 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
       for (int u = 0; u < U; ++u) {
         const int k = kb + u * S;
         ok[u] = k < k1;
-        j[u] = ok[u] ? __builtin_nontemporal_load(col + k) : 0;
+        j[u] = ok[u] ? ld_val<CACHED>(col + k) : 0;
         kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
       }
       TA v[U][RPL * BC], xv[U][BC];
@@ -213,7 +223,8 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
         if (ok[u]) {
           load_x<BC, TX, TA>(x + (size_t)j[u] * BC, xv[u]);
           if constexpr (!TRANS) {
-            load_vals<RPL * BC, TV, TA>(val + (size_t)kk[u] * (BR * BC) + L.r * BC, v[u]);
+            load_vals<RPL * BC, TV, TA, CACHED>(val + (size_t)kk[u] * (BR * BC) + L.r * BC,
+                                                v[u]);
           } else {
             // Block kk of A (BC x BR) read by columns: (A^T)[r][c] = A_kk[c][r].
             const TV* b = val + (size_t)kk[u] * (BR * BC);
@@ -311,7 +322,7 @@ __device__ __forceinline__ void wg_sum2(T& a, T& b) {
 
 // y = alpha A x + beta y   (beta == 0: y is not read).
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TY, class TA,
-          int RPL = 1>
+          int RPL = 1, bool CACHED = false>
 __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ ptr,
                                              const int* __restrict__ col,
                                              const int* __restrict__ blk,
@@ -327,7 +338,8 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
 #pragma unroll
   for (int q = 0; q < RPL; ++q) yv[q] = (own && beta != TA(0)) ? (TA)y[row0 + q] : TA(0);
   TA acc[RPL];
-  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, x, acc);
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, blk, val, x,
+                                                               acc);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -409,7 +421,7 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
 
 // t = f - A z  (A may be rectangular: BR x BC blocks).
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TF, class TA,
-          int RPL = 1>
+          int RPL = 1, bool CACHED = false>
 __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const int* __restrict__ blk,
@@ -424,7 +436,8 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
 #pragma unroll
   for (int q = 0; q < RPL; ++q) fv[q] = own ? (TA)f[row0 + q] : TA(0);
   TA acc[RPL];
-  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, blk, val, z,
+                                                               acc);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)(fv[q] - acc[q]);
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
 
 // Post-smoothing: zout = z + M (f - A z), M block diagonal (M^T when TRANS).
 template <int BR, int S, int U, bool TRANS, class TV, class TX, class TF, class TO, class TM,
-          class TA, int RPL = 1>
+          class TA, int RPL = 1, bool CACHED = false>
 static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
                                                const int* __restrict__ col,
                                                const int* __restrict__ blk,
@@ -457,7 +470,8 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
     for (int c = 0; c < BR; ++c) mv[q][c] = own ? (TA)(TRANS ? m[c * BR + r] : m[r * BR + c]) : TA(0);
   }
   TA acc[RPL];
-  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL>(L, nbr, ptr, col, blk, val, z, acc);
+  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, blk, val, z,
+                                                               acc);
   TA res[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) res[q] = own ? fv[q] - acc[q] : TA(0);

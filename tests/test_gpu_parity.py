@@ -294,6 +294,29 @@ def test_results_independent_of_kernel_tile(storage):
             gpu_solver(bsr, hier=storage, force_tile=30402)   # no 3-row lanes of 4x4 blocks
 
 
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_cached_and_streamed_value_loads_agree(storage, monkeypatch):
+    """Value loads are streamed or cached by operator precision; the arithmetic is the same,
+    so SpMV, V-cycle and solves are bitwise identical whichever load every operator uses."""
+    n = 14
+    th, bsr, A = problem(n, 0.5, 8)
+    b = dev(S.mms_rhs(n))
+    x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
+    outs = []
+    for mode in ("0", "2"):
+        monkeypatch.setenv("MGK_CACHED_LOADS", mode)
+        s = gpu_solver(bsr, hier=storage, coarse_enough=200)
+        y = torch.empty_like(b)
+        s.spmv(x0, y)
+        z = torch.empty_like(b)
+        s.precond(x0, z)
+        x = torch.zeros_like(b)
+        info = s.solve(b, x, 1e-8)
+        outs.append((y.cpu().numpy(), z.cpu().numpy(), x.cpu().numpy(), info["iters"]))
+    for a, c in zip(outs[0], outs[1]):
+        assert np.array_equal(a, c)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_multi_rhs_lockstep(storage):
     """K right-hand sides in one lockstep solve: every column meets the tolerance (oracle
