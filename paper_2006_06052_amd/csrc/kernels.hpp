@@ -518,7 +518,20 @@ __global__ __launch_bounds__(WG) void k_coarse_gemv(int n, const double* __restr
   const int i = blockIdx.x;
   const double* a = Cinv + (size_t)i * n;
   double s = 0.0, dummy = 0.0;
-  for (int j = threadIdx.x; j < n; j += WG) s = fma_(a[j], (double)r[j], s);
+  int j = threadIdx.x;
+  // four row entries per step with every load issued first; the products are added in
+  // the same order as one entry per step
+  for (; j + 3 * WG < n; j += 4 * WG) {
+    double av[4], rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      av[q] = a[j + q * WG];
+      rv[q] = (double)r[j + q * WG];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s = fma_(av[q], rv[q], s);
+  }
+  for (; j < n; j += WG) s = fma_(a[j], (double)r[j], s);
   wg_sum2(s, dummy);
   if (threadIdx.x == 0) z[i] = (TO)s;
 }
