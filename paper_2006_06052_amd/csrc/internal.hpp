@@ -111,17 +111,21 @@ struct DMat {
   bool cached = false;       // values and columns read with cached loads
 };
 
-// Value loads of the block-row kernels: streamed (non-temporal) for FP64 and FP32
-// operators, which keeps the gathered vector resident in L2 and the Infinity Cache;
-// ordinary (cached) loads for BF16 operators, measured 6% faster over a whole
-// BF16-hierarchy solve at 96^3 while the same switch made the FP32 hierarchy 1-2%
-// slower.  The environment variable MGK_CACHED_LOADS, read at setup, overrides the
-// choice (0: stream every operator, 1: BF16 operators cached, 2: every operator
-// cached).  Results are bitwise the same either way.
-inline bool operator_cached(int storage) {
+// Value and column loads of the block-row kernels: the preconditioner's operators
+// (every level, prolongator and restriction, in any storage precision) are read with
+// ordinary cached loads, the FP64 outer operator of the Krylov iteration with streaming
+// (non-temporal) loads.  Measured at 96^3 over four right-hand sides: cached loads made
+// the FP64 and BF16 hierarchy solves 5% faster and left FP32 unchanged, while on the
+// outer operator they cost 10% (its value stream then evicts the gathered x, a 28 MB
+// vector, from L2).  The environment variable MGK_CACHED_LOADS, read at setup,
+// overrides the choice with a bit mask of the operators read with cached loads: 1 BF16,
+// 2 FP32 and 4 FP64 preconditioner operators, 8 the FP64 outer operator (default 7).
+// Results are bitwise the same either way.
+inline bool operator_cached(int storage, bool outer) {
   const char* e = getenv("MGK_CACHED_LOADS");
-  const int mode = e ? atoi(e) : 1;
-  return mode >= 2 || (mode == 1 && storage == MGK_BF16);
+  const int mask = e ? atoi(e) : 7;
+  if (outer) return (mask & 8) != 0;
+  return (mask & (storage == MGK_BF16 ? 1 : storage == MGK_F32 ? 2 : 4)) != 0;
 }
 
 inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index) {
@@ -146,7 +150,7 @@ inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_ind
     for (size_t i = 0; i < nv; ++i) v[i] = f32_to_bf16((float)A.val[i]);
     M.val = D.upload(v.data(), nv);
   }
-  M.cached = operator_cached(storage);
+  M.cached = operator_cached(storage, false);
   M.avg_row = A.nbr ? (double)M.nnzb / A.nbr : 0.0;
   if (transpose_index) {
     std::vector<int> tp(A.nbc + 1, 0), tr(M.nnzb), tb(M.nnzb);

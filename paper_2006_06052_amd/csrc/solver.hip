@@ -710,6 +710,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     return;
   }
   S->A = upload_mat(S->dev, H, MGK_F64, tr);
+  S->A.cached = operator_cached(MGK_F64, true);
   tune_mat(S->dev, S->A, MGK_F64, tr);
   const SetupParams sp = setup_params(*prm, kind);
   int rc;

@@ -303,7 +303,7 @@ def test_cached_and_streamed_value_loads_agree(storage, monkeypatch):
     b = dev(S.mms_rhs(n))
     x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
     outs = []
-    for mode in ("0", "2"):
+    for mode in ("0", "15"):
         monkeypatch.setenv("MGK_CACHED_LOADS", mode)
         s = gpu_solver(bsr, hier=storage, coarse_enough=200)
         y = torch.empty_like(b)
