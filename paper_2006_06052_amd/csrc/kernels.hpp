@@ -14,9 +14,11 @@
 //    block of the row, so BR adjacent lanes read one block row-contiguously
 //    and S*BR adjacent lanes read S consecutive blocks; the S partial sums of
 //    a row are combined with cross-lane shuffles;
-//  - block values and column indices are read with non-temporal loads (they
-//    are streamed exactly once), which keeps the gathered x vector resident in
-//    L2 and the Infinity Cache;
+//  - block values and column indices of the outer FP64 operator are read with
+//    non-temporal loads (streamed once per product), which keeps the gathered x
+//    vector resident in L2; the preconditioner's smaller operators, each used
+//    several times per iteration, are read with ordinary cached loads (measured
+//    faster for them);
 //  - workgroup ids are remapped so that each of the 8 XCDs (each with its own
 //    L2) processes one contiguous range of block rows, keeping the x windows of
 //    neighbouring rows in the same L2;
@@ -53,9 +55,9 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t u) {
 
 // ---- value loads -----------------------------------------------------------
 
-// A value load: streamed (non-temporal) by default; ordinary (cached) loads for
-// the values of operators small enough to stay in the Infinity Cache between
-// their uses in a cycle.
+// A matrix value or column-index load: streamed (non-temporal) by default, an
+// ordinary cached load when CACHED (the launch chooses per operator: cached for the
+// preconditioner's operators, streamed for the outer FP64 operator).
 template <bool CACHED, class T>
 __device__ __forceinline__ T ld_val(const T* p) {
   if constexpr (CACHED) return *p;
