@@ -397,11 +397,11 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
     const int lim = L.i < rb1 ? nbr : 0;   // rows past this workgroup's range idle
     const bool own = L.active && L.s == 0 && L.i < rb1;
     const size_t row = (size_t)L.i * BR + L.r;
-    const double wv = own ? w1[row] : 0.0;   // loaded ahead of the row product
+    const double wv = own ? __builtin_nontemporal_load(w1 + row) : 0.0;   // ahead of the product
     const double acc = row_product<BR, BC, S, U, TRANS, TV, TX, double>(L, lim, ptr, col, blk,
                                                                         val, x);
     if (own) {
-      y[row] = acc;
+      __builtin_nontemporal_store(acc, y + row);
       const int q = (L.i - rb0) * BR + L.r;
       sd1[q] = wv * acc;
       sd2[q] = acc * acc;
