@@ -28,6 +28,7 @@ struct GStage {
   int total = 0;
   Tile tile;
   int cap = PERSIST;               // workgroups per launch (tuned for row stages)
+  bool cached = false;             // operator loads cached (the operators' own policy)
 };
 
 struct BatchWork {
@@ -124,8 +125,12 @@ static void g_spmv(hipStream_t st, const GStage& g, const int* active, double be
   if (g.h.empty()) return;
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
-    k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA>
-        <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
+    if (g.cached)
+      k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA, true>
+          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
+    else
+      k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA>
+          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
   });
 }
 
@@ -134,8 +139,12 @@ static void g_residual(hipStream_t st, const GStage& g, const int* active) {
   if (g.h.empty()) return;
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
-    k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA>
-        <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+    if (g.cached)
+      k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA, true>
+          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+    else
+      k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA>
+          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
   });
 }
 
@@ -144,8 +153,12 @@ static void g_smooth(hipStream_t st, const GStage& g, const int* active) {
   if (g.h.empty()) return;
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
-    k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA>
-        <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+    if (g.cached)
+      k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA, true>
+          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+    else
+      k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA>
+          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
   });
 }
 
@@ -287,12 +300,15 @@ static void build_stages(BatchWork& W) {
                                       Lv.nbr, 0, s, 0});
         W.sm[v][l].h.push_back(GItem{Lv.A.ptr, Lv.A.col, Lv.A.val, Lv.M, Lv.z, rin, zout,
                                      Lv.nbr, 0, s, 0});
+        W.res[v][l].cached = W.sm[v][l].cached = Lv.A.cached;
       }
       W.R[l].h.push_back(GItem{Lv.R.ptr, Lv.R.col, Lv.R.val, nullptr, Lv.t, nullptr, C.r,
                                Lv.R.nbr, 0, s, 0});
       const void* zc = l + 1 == nl - 1 ? C.z : C.z2;
       W.P[l].h.push_back(GItem{Lv.P.ptr, Lv.P.col, Lv.P.val, nullptr, zc, nullptr, Lv.z,
                                Lv.P.nbr, 0, s, 0});
+      W.R[l].cached = Lv.R.cached;
+      W.P[l].cached = Lv.P.cached;
     }
     DLevel& Cl = H.lv[nl - 1];
     W.coarse.h.push_back(GItem{nullptr, nullptr, nullptr, H.cinv, Cl.r, nullptr, Cl.z, H.nc, 0,
@@ -303,6 +319,7 @@ static void build_stages(BatchWork& W) {
                                       S->t, S->nbr, 0, s, 0});
     W.outer_res.h.push_back(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, nullptr, nullptr,
                                   S->r, S->nbr, 0, s, 0});
+    W.outer_spmv[0].cached = W.outer_spmv[1].cached = W.outer_res.cached = S->A.cached;
   }
   finish_fixed(W, W.coarse, 1);
   for (int l = 0; l < L; ++l)

@@ -285,12 +285,13 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
   }
 }
 
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA>
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA,
+          bool CACHED = false>
 __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int* __restrict__ ptr,
                                           const int* __restrict__ col, const int* __restrict__ blk,
                                           const TV* __restrict__ val, const TX* __restrict__ x) {
   TA out[1];
-  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, 1>(L, nbr, ptr, col, blk, val, x, out);
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, 1, CACHED>(L, nbr, ptr, col, blk, val, x, out);
   return out[0];
 }
 

@@ -43,7 +43,8 @@ __device__ __forceinline__ int find_item(const GItem* __restrict__ items, int ni
        w < (total); w += (int)gridDim.x)
 
 // y = A x + beta y
-template <int BR, int BC, int S, int U, class TV, class TX, class TY, class TA>
+template <int BR, int BC, int S, int U, class TV, class TX, class TY, class TA,
+          bool CACHED = false>
 __global__ __launch_bounds__(WG) void k_g_spmv(const GItem* __restrict__ items, int nitems,
                                                int total, const int* __restrict__ active,
                                                TA beta) {
@@ -51,8 +52,9 @@ __global__ __launch_bounds__(WG) void k_g_spmv(const GItem* __restrict__ items, 
     const GItem& g = items[find_item(items, nitems, w)];
     if (!active[g.sys]) continue;
     const LaneInfo L = lane_info<BR, S>(w - g.tile0);
-    TA acc = row_product<BR, BC, S, U, false, TV, TX, TA>(L, g.nbr, g.ptr, g.col, nullptr,
-                                                          (const TV*)g.val, (const TX*)g.in);
+    TA acc = row_product<BR, BC, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
+                                                                  (const TV*)g.val,
+                                                                  (const TX*)g.in);
     if (L.active && L.s == 0 && L.i < g.nbr) {
       const size_t row = (size_t)L.i * BR + L.r;
       TY* y = (TY*)g.out;
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(WG) void k_g_spmv(const GItem* __restrict__ items, 
 }
 
 // t = f - A z
-template <int B, int S, int U, class TV, class TX, class TF, class TA>
+template <int B, int S, int U, class TV, class TX, class TF, class TA, bool CACHED = false>
 __global__ __launch_bounds__(WG) void k_g_residual(const GItem* __restrict__ items, int nitems,
                                                    int total, const int* __restrict__ active) {
   GROUP_TILES(w, total) {
@@ -74,14 +76,16 @@ __global__ __launch_bounds__(WG) void k_g_residual(const GItem* __restrict__ ite
     const bool own = L.active && L.s == 0 && L.i < g.nbr;
     const size_t row = (size_t)L.i * B + L.r;
     const TA fv = own ? (TA)((const TF*)g.f)[row] : TA(0);   // ahead of the row product
-    TA acc = row_product<B, B, S, U, false, TV, TX, TA>(L, g.nbr, g.ptr, g.col, nullptr,
-                                                        (const TV*)g.val, (const TX*)g.in);
+    TA acc = row_product<B, B, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
+                                                                (const TV*)g.val,
+                                                                (const TX*)g.in);
     if (own) ((TX*)g.out)[row] = (TX)(fv - acc);
   }
 }
 
 // z_out = z + M (f - A z)
-template <int B, int S, int U, class TV, class TX, class TF, class TO, class TM, class TA>
+template <int B, int S, int U, class TV, class TX, class TF, class TO, class TM, class TA,
+          bool CACHED = false>
 __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items, int nitems,
                                                  int total, const int* __restrict__ active) {
   GROUP_TILES(w, total) {
@@ -98,8 +102,8 @@ __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items
     TA mv[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) mv[c] = own ? (TA)m[L.r * B + c] : TA(0);
-    TA acc = row_product<B, B, S, U, false, TV, TX, TA>(L, g.nbr, g.ptr, g.col, nullptr,
-                                                        (const TV*)g.val, z);
+    TA acc = row_product<B, B, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
+                                                                (const TV*)g.val, z);
     const TA res = own ? fv - acc : TA(0);
     TA rv[B];
 #pragma unroll
