@@ -132,6 +132,39 @@ def test_vcycle_matches_oracle_fp64():
         assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
 
 
+SMOOTHERS = {"jacobi": (mgk.AMG_JACOBI, dict(), oracle.JACOBI),
+             "spai0_scalar": (mgk.AMG_SPAI0, dict(block_spai0=0), oracle.SPAI0_SCALAR)}
+
+
+@pytest.mark.parametrize("smoother", list(SMOOTHERS))
+def test_other_smoothers_vcycle_and_solve(smoother):
+    """Damped block Jacobi (omega_J = 2/3) and scalar-row SPAI(0) on every level: the FP64
+    V-cycle (forward and transposed) against the oracle's at 1e-10, then solves with the
+    FP64 and FP32 hierarchies against the oracle's FP64 solution."""
+    kind, kw, osm = SMOOTHERS[smoother]
+    n = 14
+    th, bsr, A = problem(n, 0.5, 8)
+    so = oracle.Solver(A, 4, smoother=osm, coarse_enough=300)
+    s = gpu_solver(bsr, kind=kind, coarse_enough=300, enable_transpose=1, **kw)
+    assert s.nlevels() >= 3
+    r = np.random.default_rng(9).normal(size=A.shape[0])
+    dz = torch.empty(A.shape[0], dtype=torch.float64, device=DEV)
+    for tr in (False, True):
+        say("smoother", smoother, "transposed", tr)
+        s.precond(dev(r), dz, transposed=tr)
+        zo = so.precond(r, transposed=tr)
+        assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+    b = S.mms_rhs(n)
+    xo, _ = so.solve(b, 1e-12)
+    for storage in ("f64", "f32"):
+        s2 = gpu_solver(bsr, kind=kind, coarse_enough=300, hier=storage, **kw)
+        dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+        info = s2.solve(dev(b), dx, 1e-8)
+        say("smoother solve", smoother, storage, info)
+        assert info["status"] == 0
+        check_solution(A, b, dx.cpu().numpy(), xo)
+
+
 # ------------------------------------------------------------------ solves
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
