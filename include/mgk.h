@@ -203,6 +203,29 @@ int mgk_setup_host(const mgk_bsr* A, int32_t block_size, mgk_precond_kind kind,
  * method, right-preconditioned.  d_x holds the initial guess on entry. */
 int mgk_solve(mgk_solver* s, const double* d_b, double* d_x, double rtol, mgk_info* info);
 
+/* mgk_solve without any device allocation, for callers that cannot allocate
+ * device memory while they run (tight serving loops, code that must not call
+ * hipMalloc between set-up and tear-down).  It runs the same BiCGStab kernels as
+ * mgk_solve with the same results bit for bit, but its Krylov workspace (eight
+ * vectors, the reduction partials and the device scalars) lives in one static
+ * device array of the library, 34 MiB per GPU, held from the library's first use
+ * on that GPU until the process ends; the preconditioner's own buffers belong to
+ * the solver as for mgk_solve.  The call itself allocates nothing (no hipMalloc,
+ * no hipFree, no allocating library routine).
+ *  - s: a solver from mgk_setup with prm.krylov = MGK_BICGSTAB (else
+ *    MGK_E_STATE) and at most 524288 scalar unknowns (n_brows * block; larger
+ *    systems return MGK_E_INVALID before any device work).  Its stream must
+ *    belong to the current device (else MGK_E_INVALID).
+ *  - d_b, d_x, rtol, info: as for mgk_solve.
+ * Every call on a GPU shares that GPU's one array, which keeps the last call's
+ * contents (every buffer is written before it is read, so nothing needs to start
+ * at zero).  Calls that overlap in time on one GPU - from several threads, or
+ * while another such call's work is still queued - race on the array and give
+ * wrong results; calls in sequence are safe (each returns after its work is
+ * done). */
+int mgk_solve_noalloc(mgk_solver* s, const double* d_b, double* d_x, double rtol,
+                      mgk_info* info);
+
 /* Adjoint solve A^T lambda = g with BiCGStab preconditioned by the transpose
  * of the forward V-cycle (A_l^T, M_l^T, same R_l and P_l, transposed coarse
  * inverse).  Needs prm->enable_transpose and a monolithic AMG kind. */

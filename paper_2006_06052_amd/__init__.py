@@ -65,7 +65,8 @@ class LevelDesc(C.Structure):
 
 
 EXPORTS = ["mgk_params_default", "mgk_stokes_sizes", "mgk_stokes_assemble", "mgk_csr_to_bsr",
-           "mgk_setup", "mgk_setup_host", "mgk_solve", "mgk_solve_transposed", "mgk_solve_multi",
+           "mgk_setup", "mgk_setup_host", "mgk_solve", "mgk_solve_noalloc",
+           "mgk_solve_transposed", "mgk_solve_multi",
            "mgk_batch_setup", "mgk_batch_solve", "mgk_spmv", "mgk_precond_apply",
            "mgk_level_count", "mgk_level_info", "mgk_level_export", "mgk_ilu_info",
            "mgk_ilu_export", "mgk_theta_grad", "mgk_bsr_grad", "mgk_destroy", "mgk_last_error"]
@@ -90,6 +91,7 @@ def lib():
     L.mgk_setup.argtypes = [C.POINTER(_Bsr), I32, I32, C.POINTER(Params), P, C.POINTER(P)]
     L.mgk_setup_host.argtypes = [C.POINTER(_Bsr), I32, I32, C.POINTER(Params), C.POINTER(P)]
     L.mgk_solve.argtypes = [P, P, P, D, C.POINTER(Info)]
+    L.mgk_solve_noalloc.argtypes = [P, P, P, D, C.POINTER(Info)]
     L.mgk_ilu_info.argtypes = [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64)]
     L.mgk_ilu_export.argtypes = [P, I32, P, P, P]
     L.mgk_solve_transposed.argtypes = [P, P, P, D, C.POINTER(Info)]
@@ -246,6 +248,11 @@ class Solver:
     def solve(self, b, x, rtol: float = 1e-8) -> dict:
         """x (in: initial guess, out: solution); returns the info record."""
         return self._solve(lib().mgk_solve, b, x, rtol)
+
+    def solve_noalloc(self, b, x, rtol: float = 1e-8) -> dict:
+        """solve() with the Krylov workspace in the library's static device array: the
+        call allocates no device memory (BiCGStab solvers of at most 524288 unknowns)."""
+        return self._solve(lib().mgk_solve_noalloc, b, x, rtol)
 
     def solve_multi(self, B, X, rtol: float = 1e-8) -> list:
         """K <= 32 right-hand sides together: B, X are [n, K] (right-hand sides fastest);

@@ -941,6 +941,111 @@ int mgk_solve_transposed(mgk_solver* s, const double* d_g, double* d_lambda, dou
   return solve_common(s, d_g, d_lambda, rtol, info, true);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free solve
+
+namespace mgk {
+
+// Workspace of mgk_solve_noalloc: the eight BiCGStab vectors, the reduction partials
+// (both stages) and the device scalars of one solve with at most NOALLOC_MAX_N scalar
+// unknowns, in one file-scope device array (34 MiB) that every GPU the library runs
+// on holds until the process ends.  Host code never uses the array's name as an
+// address: each device's copy is looked up once with hipGetSymbolAddress and the
+// pointer kept per device.
+constexpr size_t NOALLOC_MAX_N = (size_t)1 << 19;
+constexpr size_t na_round(size_t d) { return (d + 31) & ~(size_t)31; }   // 256-byte regions
+// partials: two per workgroup of the fused outer SpMV (at most n / 32 for any block
+// size) or MAXM per reduction workgroup, as sized by alloc_krylov for n unknowns
+constexpr size_t NOALLOC_PART = na_round(NOALLOC_MAX_N / 2 + 4096);
+constexpr size_t NOALLOC_PART2 = na_round(2 * (NOALLOC_PART / RED_CHUNK + 2));
+constexpr size_t NOALLOC_DOUBLES =
+    8 * NOALLOC_MAX_N + NOALLOC_PART + NOALLOC_PART2 + na_round(SC_COUNT);
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+// The device address of this device's copy of `scratch` (looked up on the first call
+// per device, with that device current).
+static double* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV)
+    throw Error(MGK_E_INVALID, "solve_noalloc: device ordinal out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(MGK_E_HIP, "solve_noalloc: no device address for the workspace");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Points the solver's BiCGStab workspace at the static array for the duration of one
+// call and restores the solver's own buffers afterwards (also when the solve throws).
+struct ScratchWorkspace {
+  mgk_solver* S;
+  double* saved[11];
+  size_t saved_len;
+  ScratchWorkspace(mgk_solver* s, double* base) : S(s) {
+    double** f[11] = {&S->r, &S->rh, &S->p, &S->v, &S->ph, &S->s, &S->sh, &S->t,
+                      &S->part, &S->part2, &S->sc};
+    for (int i = 0; i < 11; ++i) saved[i] = *f[i];
+    saved_len = S->part_len;
+    double* q = base;
+    for (int i = 0; i < 8; ++i, q += NOALLOC_MAX_N) *f[i] = q;
+    S->part = q;
+    q += NOALLOC_PART;
+    S->part2 = q;
+    q += NOALLOC_PART2;
+    S->sc = q;
+    S->part_len = NOALLOC_PART;
+  }
+  ~ScratchWorkspace() {
+    double** f[11] = {&S->r, &S->rh, &S->p, &S->v, &S->ph, &S->s, &S->sh, &S->t,
+                      &S->part, &S->part2, &S->sc};
+    for (int i = 0; i < 11; ++i) *f[i] = saved[i];
+    S->part_len = saved_len;
+  }
+};
+
+}  // namespace mgk
+
+extern "C" {
+
+int mgk_solve_noalloc(mgk_solver* s, const double* d_b, double* d_x, double rtol,
+                      mgk_info* info) {
+  if (!s || !d_b || !d_x || !info || !(rtol > 0.0)) {
+    mgk::g_err = "solve_noalloc: null argument or non-positive rtol";
+    return MGK_E_INVALID;
+  }
+  if (s->batch || s->host_only) {
+    mgk::g_err = "solve_noalloc: needs a single-system solver with device data";
+    return MGK_E_STATE;
+  }
+  if (s->prm.krylov != MGK_BICGSTAB) {
+    mgk::g_err = "solve_noalloc: only BiCGStab solvers (mgk_params.krylov = MGK_BICGSTAB)";
+    return MGK_E_STATE;
+  }
+  if (s->n > mgk::NOALLOC_MAX_N) {
+    mgk::g_err = "solve_noalloc: " + std::to_string(s->n) + " unknowns exceed the static "
+                 "workspace limit of " + std::to_string(mgk::NOALLOC_MAX_N);
+    return MGK_E_INVALID;
+  }
+  return mgk::guard([&]() -> int {
+    int dev = -1, sdev = -1;
+    HIPCK(hipGetDevice(&dev));
+    HIPCK(hipStreamGetDevice(s->dev.stream, &sdev));
+    if (sdev != dev)
+      throw mgk::Error(MGK_E_INVALID, "solve_noalloc: the solver's stream belongs to device " +
+                                          std::to_string(sdev) + ", the current device is " +
+                                          std::to_string(dev));
+    mgk::ScratchWorkspace ws(s, mgk::scratch_ptr(dev));
+    return solve_common(s, d_b, d_x, rtol, info, false);
+  });
+}
+
 int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t transposed) {
   if (!s || !d_r || !d_z) {
     mgk::g_err = "precond_apply: null argument";
