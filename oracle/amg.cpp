@@ -10,8 +10,11 @@
 //   strength   j != i strong iff N_ij > eps^2 sqrt(N_ii) sqrt(N_jj), with
 //              N_ij the squared Frobenius norm of block (i,j) summed row-major;
 //              eps halves from one level to the next;
-//   aggregates three greedy phases in ascending node order (a node with no
-//              strong neighbour is isolated and joins no aggregate);
+//   aggregates greedy phases in ascending node order: seed full strong
+//              neighbourhoods, then attach leftovers to the phase-1 aggregate of
+//              their lowest strong neighbour (the classical third phase for
+//              leftovers is unreachable after these two); a node with no strong
+//              neighbour is isolated and joins no aggregate;
 //   P          (I - omega D^-1 A_F) P_tent with the row-sum lumped filtered
 //              matrix A_F, D = diagonal block of A_F, omega = (4/3)/rho and
 //              rho the Gershgorin bound of D^-1 A_F;
@@ -94,7 +97,7 @@ Strength strength(const Csr& A, int b, double eps) {
   return st;
 }
 
-// Three-phase greedy aggregation in ascending node order.
+// Greedy aggregation in ascending node order; returns -1 if a node were left over.
 i64 aggregate(const Strength& st, std::vector<i32>& agg) {
   const i64 nn = (i64)st.S.size();
   agg.assign(nn, -1);
@@ -123,15 +126,12 @@ i64 aggregate(const Strength& st, std::vector<i32>& agg) {
         break;
       }
   }
-  // Phase 3: each node still free forms an aggregate with its free strong
-  // neighbours.
-  for (i64 i = 0; i < nn; ++i) {
-    if (st.iso[i] || agg[i] >= 0) continue;
-    agg[i] = next;
-    for (i32 j : st.S[i])
-      if (!st.iso[j] && agg[j] < 0) agg[j] = next;
-    ++next;
-  }
+  // No third phase is needed: phase 1 skips a non-isolated node only when one of its
+  // non-isolated strong neighbours is already in a phase-1 aggregate, and phase 2
+  // attaches it to the first such neighbour's aggregate, so every non-isolated node is
+  // aggregated here.  A node left over would be a broken invariant.
+  for (i64 i = 0; i < nn; ++i)
+    if (!st.iso[i] && agg[i] < 0) return -1;
   return next;
 }
 
@@ -183,6 +183,10 @@ bool coarsen(Level& L, int b, double eps, bool smooth_p, Csr& Ac, const char** m
   Strength st = strength(A, b, eps);
   L.isolated = st.iso;
   L.n_agg = aggregate(st, L.agg);
+  if (L.n_agg < 0) {
+    *msg = "oracle: aggregation left a connected node unassigned";
+    return false;
+  }
   if (L.n_agg == 0 || L.n_agg >= nn) return false;
 
   // Tentative prolongator: identity block at (i, agg(i)), unnormalized.

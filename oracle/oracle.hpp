@@ -12,7 +12,12 @@
 // FP64, compiled with -ffp-contract=off, and every sum runs in the ascending
 // order stated at its definition.
 //
-// Pins (tests/test_oracle_pins.py) cover every function below, including the
+// Pins (tests/test_oracle_pins.py) cover every function below: the strength test
+// (eps^2 threshold against the geometric mean of the two diagonal norms, hand-derived
+// chains), eps halving per level and the lumping of weak connections into the filtered
+// diagonal (hand-derived anisotropic lines: aggregates, omega, P and the level-1 matrix),
+// the damped block Jacobi smoother (its closed form), that two aggregation phases leave
+// no connected node over (random matrices), and further the
 // plain-aggregation prolongator (hand-derived 1D case, block invariants,
 // Galerkin product), the diagonal Schur approximation and its SPAI(0) pressure
 // step (derived from the pinned full approximation; least-squares optimality),

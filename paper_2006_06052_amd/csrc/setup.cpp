@@ -80,8 +80,9 @@ void strength(const HBsr& A, double eps, std::vector<char>& strong, std::vector<
 
 // Greedy aggregation: (1) a row whose non-isolated strong neighbours are all
 // unassigned seeds an aggregate with them; (2) leftovers join the phase-1
-// aggregate of their first (lowest) strong neighbour that has one; (3) any row
-// still unassigned seeds an aggregate with its unassigned strong neighbours.
+// aggregate of their first (lowest) strong neighbour that has one.  No row can be
+// left after (2) (the classical third phase for leftovers never runs); -1 reports a
+// broken invariant.
 int32_t aggregation(const HBsr& A, const std::vector<char>& strong, const std::vector<char>& iso,
                     std::vector<int32_t>& agg) {
   const int32_t n = A.nbr;
@@ -109,15 +110,10 @@ int32_t aggregation(const HBsr& A, const std::vector<char>& strong, const std::v
       }
     }
   }
-  for (int32_t i = 0; i < n; ++i) {
-    if (iso[i] || agg[i] != -1) continue;
-    agg[i] = count;
-    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      const int32_t j = A.col[k];
-      if (strong[k] && !iso[j] && agg[j] == -1) agg[j] = count;
-    }
-    ++count;
-  }
+  // Every connected row is assigned now: phase 1 passes over a connected row only when a
+  // connected strong neighbour already sits in a phase-1 aggregate, and phase 2 joins it.
+  for (int32_t i = 0; i < n; ++i)
+    if (!iso[i] && agg[i] == -1) return -1;
   return count;
 }
 
@@ -491,6 +487,10 @@ int build_hierarchy(const HBsr& A0, const SetupParams& prm, HHierarchy& H, std::
       std::vector<char> strong, iso;
       strength(L.A, eps, strong, iso);
       L.n_agg = aggregation(L.A, strong, iso, L.agg);
+      if (L.n_agg < 0) {
+        err = "aggregation left a connected block row unassigned";
+        return -1;
+      }
       if (L.n_agg == 0 || L.n_agg >= L.A.nbr) {
         coarsest = true;
         L.agg.clear();

@@ -246,6 +246,159 @@ def test_prolongator_1d_hand_derived():
     assert np.allclose(P[3:9].sum(axis=1), 1.0)
 
 
+def scaled_chain(m, diag, off=-1.0, diag_odd=None):
+    """chain(m) with interior diagonal `diag` (or `diag_odd` on odd nodes) and off-diagonal
+    `off`; identity rows at both ends."""
+    rows, cols, vals = [0, m - 1], [0, m - 1], [1.0, 1.0]
+    for i in range(1, m - 1):
+        d = diag_odd if (diag_odd is not None and i % 2) else diag
+        rows += [i, i, i]
+        cols += [i - 1, i, i + 1]
+        vals += [off, d, off]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m, m))
+
+
+@pytest.mark.parametrize("diag,strong", [(10.0, True), (12.4, True), (12.6, False)])
+def test_strength_threshold_is_eps_squared(diag, strong):
+    """Strength (b = 1): a_ij^2 > eps^2 |a_ii| |a_jj| with eps = 0.08.  For the chain with
+    interior rows [-1, d, -1] the interior couplings are strong iff 1 > 0.0064 d^2, i.e.
+    d < 12.5: d = 10 and 12.4 aggregate like the plain chain.  With d = 12.6 the interior
+    couplings are weak; only nodes 1 and 9 keep a strong coupling, to the identity rows at
+    the ends (1 > 0.0064 * 12.6 * 1), whose nodes are isolated, so nodes 1 and 9 become
+    singleton aggregates and every other node is isolated.  Reading the threshold as eps
+    instead of eps^2 (1 > 0.08 d^2 for the interior couplings, d < 3.54) would leave no
+    interior coupling strong in all three cases."""
+    s = oracle.Solver(scaled_chain(11, diag), 1, coarse_enough=1, max_levels=2)
+    assert s.nlevels() == 2
+    if strong:
+        assert list(s.level(0)["agg"]) == [-1, 0, 0, 1, 1, 1, 2, 2, 2, 2, -1]
+    else:
+        assert list(s.level(0)["agg"]) == [-1, 0, -1, -1, -1, -1, -1, -1, -1, 1, -1]
+
+
+@pytest.mark.parametrize("c,strong", [(0.85, True), (0.75, False)])
+def test_strength_uses_geometric_mean_of_both_diagonals(c, strong):
+    """Interior diagonals alternate 1 (even nodes) and 100 (odd nodes), couplings -c.  The
+    test c^2 > eps^2 sqrt(N_ii) sqrt(N_jj) = 0.0064 * 1 * 100 gives c > 0.8 for every
+    coupling: 0.85 strong, 0.75 weak.  Using only the row's own diagonal would make even
+    rows strong (c > 0.08) and odd rows weak (c > 8) for both values; the minimum or the
+    maximum of the two diagonals would give the same answer for both values.  The end
+    couplings (odd node 1 or 9 against the identity row, diagonals 100 and 1) follow the
+    same rule, so with c = 0.75 every node is isolated."""
+    A = scaled_chain(11, 1.0, off=-c, diag_odd=100.0)
+    s = oracle.Solver(A, 1, coarse_enough=1, max_levels=2)
+    if strong:
+        assert s.nlevels() == 2
+        assert list(s.level(0)["agg"]) == [-1, 0, 0, 1, 1, 1, 2, 2, 2, 2, -1]
+    else:
+        assert s.nlevels() == 1
+
+
+def anisotropic_lines(mx=5, my=12, delta=1.0 / 32):
+    """my x-lines of mx nodes, periodic in y.  Nodes i = 0 and mx - 1 of every line are
+    identity rows (columns kept); interior nodes have 2 + 2 delta on the diagonal, -1 to
+    their x-neighbours and -delta to their y-neighbours.  Node (i, j) is i + mx j."""
+    rows, cols, vals = [], [], []
+    g = lambda i, j: i + mx * (j % my)  # noqa: E731
+    for j in range(my):
+        for i in range(mx):
+            r = g(i, j)
+            if i == 0 or i == mx - 1:
+                rows.append(r); cols.append(r); vals.append(1.0)  # noqa: E702
+                continue
+            for c, v in ((g(i - 1, j), -1.0), (g(i + 1, j), -1.0), (g(i, j - 1), -delta),
+                         (g(i, j + 1), -delta), (r, 2.0 + 2.0 * delta)):
+                rows.append(r); cols.append(c); vals.append(v)  # noqa: E702
+    return sp.csr_matrix((vals, (rows, cols)), shape=(mx * my, mx * my))
+
+
+def test_weak_lumping_and_eps_halving_hand_derived():
+    """Anisotropic lines (delta = 1/32; every value below is exact in binary or derived
+    by hand).
+
+    Level 0 (eps = 0.08): x-couplings are strong (1 > 0.0064 * 2.0625^2), y-couplings weak
+    (delta^2 = 0.00098 < 0.0272).  Each line's three interior nodes form one aggregate
+    (phase 1 seeds {1, 2}, node 3 joins it in phase 2): 12 aggregates.  The weak
+    y-couplings are lumped into the diagonal of the filtered matrix, so A_F has rows
+    [-1, 2, -1] (2.0625 - 1/32 - 1/32 = 2): Gershgorin bound 2, omega = (4/3)/2 = 2/3, and
+    the prolongator of each line is (2/3, 1, 2/3) with no entry in any other line
+    (dropping instead of lumping gives omega = 0.6875 and P = 0.677...; keeping the weak
+    couplings gives entries in the neighbouring lines).
+
+    Level 1 = R A P: per line p^T A_x p = 10/9 and sum p_i^2 = 17/9, so a ring of 12 nodes
+    with diagonal 10/9 + 34 delta/9 and couplings -17 delta/9 (relative strength 0.048).
+    With eps halved to 0.04 the ring couplings are strong and the ring aggregates as
+    {11, 0, 1}, {2, 3, 4}, {5, 6, 7}, {8, 9, 10}; with eps kept at 0.08 (or the eps
+    threshold instead of eps^2) they are weak, every level-1 node is isolated and the
+    hierarchy stops at two levels.  Level-1 omega: the Gershgorin bound of the ring is
+    (10 + 68 delta) / (10 + 34 delta)."""
+    delta = 1.0 / 32
+    A = anisotropic_lines(delta=delta)
+    s = oracle.Solver(A, 1, coarse_enough=5)
+    assert s.nlevels() == 3
+    L0 = s.level(0)
+    agg = L0["agg"].reshape(12, 5)
+    assert np.array_equal(agg[:, 0], -np.ones(12)) and np.array_equal(agg[:, 4], -np.ones(12))
+    for j in range(12):
+        assert list(agg[j, 1:4]) == [j, j, j]
+    assert L0["n_agg"] == 12
+    assert L0["omega"] == 2.0 / 3.0
+    P = dense(L0["P"])
+    expect = np.zeros((60, 12))
+    for j in range(12):
+        expect[5 * j + 1:5 * j + 4, j] = [2.0 / 3.0, 1.0, 2.0 / 3.0]
+    assert np.abs(P - expect).max() <= 1e-15
+    assert L0["P"].nnz == 36
+    L1 = s.level(1)
+    A1 = dense(L1["A"])
+    ring = np.zeros((12, 12))
+    for j in range(12):
+        ring[j, j] = 10.0 / 9.0 + 34.0 * delta / 9.0
+        ring[j, (j + 1) % 12] = ring[j, (j - 1) % 12] = -17.0 * delta / 9.0
+    assert np.abs(A1 - ring).max() <= 1e-14
+    assert list(L1["agg"]) == [0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3, 0]
+    assert L1["omega"] == pytest.approx((4.0 / 3.0) * (10 + 34 * delta) / (10 + 68 * delta),
+                                        rel=1e-14)
+
+
+def test_two_phases_aggregate_every_connected_node():
+    """The third aggregation phase (leftover nodes seeding aggregates) is unreachable: a
+    node that phase 1 skips has a non-isolated strong neighbour already aggregated in
+    phase 1, which phase 2 joins.  The oracle reports an error if a node were left; random
+    nonsymmetric matrices with random strength patterns never trigger it, and every
+    non-isolated node ends in an aggregate."""
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n = int(rng.integers(6, 40))
+        A = sp.random(n, n, density=float(rng.uniform(0.05, 0.4)), random_state=int(trial),
+                      data_rvs=lambda k: rng.uniform(-1, 1, k))
+        A = sp.csr_matrix(A + sp.diags(rng.uniform(1, 4, n)))
+        s = oracle.Solver(A, 1, coarse_enough=1, max_levels=2)
+        if s.nlevels() < 2:
+            continue
+        L0 = s.level(0)
+        iso = np.array([all(abs(A[i, j]) ** 2 <= 0.0064 * abs(A[i, i]) * abs(A[j, j])
+                            for j in A[i].indices if j != i) for i in range(n)])
+        assert np.array_equal(L0["agg"] < 0, iso)
+
+
+def test_damped_jacobi_smoother_closed_form():
+    """Damped block Jacobi: M_i = omega_J A_ii^-1 on every level (omega_J = 2/3 and 0.5),
+    against numpy's inverse of each diagonal block."""
+    n = 7
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 13))
+    for om in (2.0 / 3.0, 0.5):
+        s = oracle.Solver(A, 4, smoother=oracle.JACOBI, jacobi_omega=om, coarse_enough=30)
+        assert s.nlevels() >= 3
+        for l in range(s.nlevels() - 1):
+            L = s.level(l)
+            Ad = dense(L["A"])
+            for i in range(Ad.shape[0] // 4):
+                Dii = Ad[4 * i:4 * i + 4, 4 * i:4 * i + 4]
+                ref = om * np.linalg.inv(Dii)
+                assert np.abs(L["M"][i] - ref).max() <= 1e-12 * np.abs(ref).max(), (om, l, i)
+
+
 def test_plain_aggregation_1d_hand_derived():
     """Plain aggregation: P is the tentative prolongator (one unit entry per aggregated
     node, omega 0), and for the 1D Laplacian each aggregate sums to the coarse stencil
