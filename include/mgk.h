@@ -273,7 +273,10 @@ int mgk_ilu_export(mgk_solver* s, int32_t which, int32_t* rowptr, int32_t* col, 
 int mgk_level_count(mgk_solver* s, int32_t hier);
 int mgk_level_info(mgk_solver* s, int32_t hier, int32_t level, mgk_level_desc* out);
 /* which 0: A_l, 1: P_l, 2: R_l; writes BSR arrays sized by mgk_level_info;
- * agg (may be NULL) receives the aggregate of each block row (-1 isolated). */
+ * agg (may be NULL) receives the aggregate of each block row (-1 isolated).
+ * which 3: the smoother blocks M_l (SPAI(0) or damped Jacobi, n_brows row-major
+ * b x b blocks) into val only; MGK_E_STATE on the coarsest level or with the ILU
+ * smoother. */
 int mgk_level_export(mgk_solver* s, int32_t hier, int32_t level, int32_t which,
                      int32_t* rowptr, int32_t* col, double* val, int32_t* agg);
 

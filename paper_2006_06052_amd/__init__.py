@@ -324,6 +324,16 @@ class Solver:
             _err(rc)
         return out[0], out[1], dinv.reshape(nb.value, b, b)
 
+    def level_smoother(self, level: int, hier: int = 0):
+        """Host FP64 copy of the smoother blocks M_l, (n_brows, b, b)."""
+        d = self.level_info(level, hier)
+        b, nb = d["block"], d["n_brows"]
+        val = np.zeros(max(nb, 1) * b * b, np.float64)
+        rc = lib().mgk_level_export(self._h, hier, level, 3, None, None, _np_ptr(val), None)
+        if rc:
+            _err(rc)
+        return val[:nb * b * b].reshape(nb, b, b)
+
     def level_export(self, level: int, which: int = 0, hier: int = 0):
         """Host FP64 copy (rowptr, col, val) of A_l (0), P_l (1) or R_l (2), plus aggregates."""
         d = self.level_info(level, hier)

@@ -1151,11 +1151,19 @@ int mgk_level_export(mgk_solver* s, int32_t hier, int32_t level, int32_t which, 
     mgk::g_err = "level_export needs keep_host = 1 at setup";
     return MGK_E_STATE;
   }
-  if (level < 0 || level >= (int)H.host.levels.size() || which < 0 || which > 2) {
+  if (level < 0 || level >= (int)H.host.levels.size() || which < 0 || which > 3) {
     mgk::g_err = "level_export: bad level or matrix";
     return MGK_E_INVALID;
   }
   const mgk::HLevel& L = H.host.levels[level];
+  if (which == 3) {
+    if (L.M.empty()) {
+      mgk::g_err = "level_export: this level has no block-diagonal smoother";
+      return MGK_E_STATE;
+    }
+    if (val) std::memcpy(val, L.M.data(), sizeof(double) * L.M.size());
+    return MGK_OK;
+  }
   const mgk::HBsr& M = which == 0 ? L.A : (which == 1 ? L.P : L.R);
   if (rowptr) std::memcpy(rowptr, M.ptr.data(), sizeof(int32_t) * M.ptr.size());
   if (col) std::memcpy(col, M.col.data(), sizeof(int32_t) * M.col.size());

@@ -84,6 +84,8 @@ def compare_hierarchies(hs, which_h, os_, which_o, levels_expected=None):
             break
         assert np.array_equal(agg, L["agg"]), f"aggregates, level {l}"
         assert d["omega"] == L["omega"], f"omega, level {l}"
+        if "M" in L and np.any(L["M"]):
+            assert np.array_equal(hs.level_smoother(l, which_h), L["M"]), f"M, level {l}"
         for which, key in ((1, "P"), (2, "R")):
             p, c, v, _ = hs.level_export(l, which, which_h)
             op, oc, ov = oracle_blocks(L[key], b)
@@ -243,3 +245,49 @@ def test_singular_block_row_rejected():
     with pytest.raises(mgk.MgkError) as e:
         host_solver(ptr, col, v, 4, coarse_enough=10)
     assert e.value.code in (-4, -1)
+
+
+# Hierarchies of the benchmark workloads at their full sizes, bit for bit.
+CONFIG_SHAPES = {
+    # 48^3, theta = exp(N(0, 0.5^2)) seed 5 (the differentiable-solve workload)
+    "cube48_theta": dict(n=48, sigma=0.5, seed=5, kind="amg"),
+    # 64^3, mu = 1 (the 32-right-hand-side workload)
+    "cube64_mu1": dict(n=64, sigma=None, seed=None, kind="amg"),
+    # 64^3, theta = exp(N(0, 1)) seed 3: the Schur workload's velocity and pressure hierarchies
+    "cube64_schur": dict(n=64, sigma=1.0, seed=3, kind="schur"),
+    # 64^3, seed 3, the paper's Schur configuration: plain-aggregation velocity AMG and the
+    # diagonal pressure approximation of eq. SchurApprox
+    "cube64_paper_schur": dict(n=64, sigma=1.0, seed=3, kind="schur",
+                               kw=dict(coarsening=1, schur_approx=1)),
+    # 56^3, theta = exp(N(0, 0.5^2)) seed 45: one of the eight batched systems
+    "cube56_theta": dict(n=56, sigma=0.5, seed=45, kind="amg"),
+    # 96^3, mu = 1 (the headline workload)
+    "cube96_mu1": dict(n=96, sigma=None, seed=None, kind="amg"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", list(CONFIG_SHAPES))
+def test_host_setup_matches_oracle_at_workload_shape(name):
+    """Aggregates, omega, A/P/R patterns and values and the smoother blocks of every level
+    equal the oracle's at the benchmark sizes (default parameters: eps 0.08, 3000 coarse
+    unknowns)."""
+    c = CONFIG_SHAPES[name]
+    n = c["n"]
+    th = None if c["sigma"] is None else S.theta_field(n, c["sigma"], c["seed"])
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    A = oracle.stokes_matrix(n, th)
+    kw = c.get("kw", {})
+    if c["kind"] == "schur":
+        hs = host_solver(ptr, col, val, 4, mgk.SCHUR, krylov=mgk.FGMRES, **kw)
+        del ptr, col, val
+        os_ = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.FGMRES, **kw)
+        del A
+        compare_hierarchies(hs, 0, os_, 0, levels_expected=3)
+        compare_hierarchies(hs, 1, os_, 1, levels_expected=3)
+    else:
+        hs = host_solver(ptr, col, val, 4)
+        del ptr, col, val
+        os_ = oracle.Solver(A, 4)
+        del A
+        compare_hierarchies(hs, 0, os_, 0, levels_expected=3)
