@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liborc.so")
 SOURCES = ["csr.cpp", "stokes.cpp", "amg.cpp", "krylov.cpp", "ilu.cpp", "capi.cpp"]
 
 KIND_AMG, KIND_SCHUR, KIND_IDENTITY, KIND_ILU = 0, 1, 2, 3
-SPAI0_BLOCK, JACOBI, SPAI0_SCALAR, ILU0 = 0, 1, 2, 3
+SPAI0_BLOCK, JACOBI, SPAI0_SCALAR, ILU0, ILUT = 0, 1, 2, 3, 4
 BICGSTAB, FGMRES, IDRS = 0, 1, 2
 SMOOTHED, PLAIN = 0, 1
 
@@ -47,7 +47,8 @@ class _Params(C.Structure):
                 ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
                 ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32),
-                ("schur_scalar_u", C.c_int32)]
+                ("schur_scalar_u", C.c_int32), ("ilu_kind", C.c_int32),
+                ("ilut_p", C.c_double), ("ilut_tau", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -87,6 +88,11 @@ def lib():
         L.orc_ilu_dinv.argtypes = [P, P]
         L.orc_ilu_dinv.restype = None
         L.orc_idr_shadow.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.restype = C.c_int
+        L.orc_set_limits.argtypes = [P, C.c_int, C.c_int]
+        L.orc_set_limits.restype = None
         L.orc_gather_block_row.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int64, P, P,
                                            C.c_int32]
         _lib = L
@@ -116,6 +122,15 @@ def stokes_matrix(n: int, theta: np.ndarray | None = None) -> sp.csr_matrix:
     if rc:
         raise ValueError("oracle assembly failed")
     return sp.csr_matrix((val, col, ptr), shape=(nr, nr))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (sparse products)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
 
 
 def theta_gradient(n: int, lam: np.ndarray, x: np.ndarray) -> np.ndarray:
@@ -166,7 +181,8 @@ class Solver:
                  jacobi_omega: float = 2.0 / 3.0, coarsening: int = SMOOTHED,
                  schur_approx: int = 0, schur_spai0: int = 0, schur_lower: int = 0,
                  idr_s: int = 5, ilu_level: int = 0, ilu_sweeps: int = 2,
-                 schur_scalar_u: int = 0):
+                 schur_scalar_u: int = 0, ilu_kind: int = 0, ilut_p: float = 2.0,
+                 ilut_tau: float = 1e-2):
         A = sp.csr_matrix(A)
         A.sort_indices()
         self.n = A.shape[0]
@@ -175,7 +191,7 @@ class Solver:
         self.prm = _Params(krylov, fgmres_m, maxiter, max_restarts, eps_strong, coarse_enough,
                            max_levels, smoother, kind, jacobi_omega, coarsening, schur_approx,
                            schur_spai0, schur_lower, idr_s, ilu_level, ilu_sweeps,
-                           schur_scalar_u)
+                           schur_scalar_u, ilu_kind, ilut_p, ilut_tau)
         self.block = block
         L = lib()
         h = L.orc_setup(self.n, *(_p(a) for a in self._keep), block, C.byref(self.prm))
@@ -188,6 +204,10 @@ class Solver:
         if h and _lib is not None:
             _lib.orc_free(h)
             self._h = None
+
+    def set_limits(self, maxiter: int, max_restarts: int) -> None:
+        """Change the iteration limits of later solves (setup is unchanged)."""
+        lib().orc_set_limits(self._h, int(maxiter), int(max_restarts))
 
     def ilu_factor(self) -> sp.csr_matrix:
         """Combined block ILU factor (L strictly lower with unit diagonal implied, U on and

@@ -326,6 +326,8 @@ bool amg_build(const Csr& A, int b, const AmgParams& prm, Hierarchy& H, const ch
     }
     if (prm.smoother == ILU0) {
       if (!ilu_build(L.A, b, 0, prm.ilu_sweeps, L.F, msg)) return false;
+    } else if (prm.smoother == ILUT) {
+      if (!ilut_build(L.A, b, prm.ilut_p, prm.ilut_tau, prm.ilu_sweeps, L.F, msg)) return false;
     } else if (!build_smoother(L.A, b, prm, L.M)) {
       *msg = "oracle: singular smoother block";
       return false;

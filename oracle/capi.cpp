@@ -1,5 +1,7 @@
 // C entry points of the oracle, loaded by the tests through ctypes.
 // TEST INFRASTRUCTURE ONLY (see oracle.hpp).
+#include <omp.h>
+
 #include <cstring>
 #include <exception>
 #include <memory>
@@ -64,6 +66,9 @@ struct orc_params {
   int32_t ilu_level;     // fill level of the block ILU(k) preconditioner (kind 3)
   int32_t ilu_sweeps;    // Jacobi sweeps per triangular factor
   int32_t schur_scalar_u;  // 1: Schur velocity AMG on scalar values
+  int32_t ilu_kind;      // kind 3: 0 block ILU(k), 1 block ILUT(p, tau)
+  double ilut_p;
+  double ilut_tau;
 };
 
 struct orc_info {
@@ -122,6 +127,8 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
     s->aprm.jacobi_omega = prm->jacobi_omega;
     s->aprm.smooth_p = prm->coarsening == 0;
     s->aprm.ilu_sweeps = prm->ilu_sweeps;
+    s->aprm.ilut_p = prm->ilut_p;
+    s->aprm.ilut_tau = prm->ilut_tau;
     if (prm->krylov == 2 && (prm->idr_s < 1 || prm->idr_s > 32)) {
       g_err = "oracle: IDR(s) needs 1 <= s <= 32";
       return nullptr;
@@ -137,7 +144,11 @@ orc_solver* orc_setup(int64_t nr, const int64_t* ptr, const int32_t* col, const 
         g_err = "oracle: ILU(k) needs k in {0, 1} and sweeps >= 0";
         return nullptr;
       }
-      if (!ilu_build(s->A, block, prm->ilu_level, prm->ilu_sweeps, s->F, &msg)) {
+      const bool ok = prm->ilu_kind == 1
+                          ? ilut_build(s->A, block, prm->ilut_p, prm->ilut_tau, prm->ilu_sweeps,
+                                       s->F, &msg)
+                          : ilu_build(s->A, block, prm->ilu_level, prm->ilu_sweeps, s->F, &msg);
+      if (!ok) {
         g_err = msg ? msg : "oracle: ILU setup failed";
         return nullptr;
       }
@@ -320,4 +331,13 @@ extern "C" int orc_gather_block_row(int64_t nr, const int64_t* ptr, const int32_
     for (int q = 0; q < b * b; ++q) vals[(size_t)t * b * b + q] = br.vals[(size_t)t * b * b + q];
   }
   return m;
+}
+
+// Thread count of the OpenMP loops (SpMV, sparse products) and the iteration limits of
+// an existing solver, for timing bounded samples of a solve.
+extern "C" void orc_set_threads(int n) { omp_set_num_threads(n); }
+extern "C" int orc_max_threads() { return omp_get_max_threads(); }
+extern "C" void orc_set_limits(orc_solver* s, int maxiter, int max_restarts) {
+  s->prm.maxiter = maxiter;
+  s->prm.max_restarts = max_restarts;
 }

@@ -3,7 +3,7 @@
 //
 // The paper's monolithic variant preconditions IDR(5) with ILU(1) (Section 4,
 // the ILU(1) solver listing), and its Schur variants smooth the velocity AMG
-// with ILUT.  Here the factorization is taken on b x b node blocks:
+// with ILUT (ilut_build below).  ILU(k) is taken on b x b node blocks:
 //   symbolic: the pattern of block row i is A's pattern (level 0) plus every
 //     (i, j) reached through an eliminated k < i with level
 //     lev(i,k) + lev(k,j) + 1 <= K, smallest level kept;
@@ -21,6 +21,7 @@
 #include "oracle.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 
 namespace orc {
@@ -104,6 +105,107 @@ bool ilu_build(const Csr& A, int b, int level, int sweeps, Ilu& F, const char** 
     }
     F.cols[i] = std::move(cols);
     F.vals[i] = std::move(W);
+  }
+  return true;
+}
+
+namespace {
+double fnorm(int bs, const double* X) {
+  double s = 0.0;
+  for (int e = 0; e < bs; ++e) s = s + X[e] * X[e];
+  return std::sqrt(s);
+}
+}  // namespace
+
+// Block ILUT(p, tau): incomplete LU with threshold dropping and a cap on the fill per
+// row (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Sec. 10.4, ILUT),
+// taken on b x b node blocks with block norms in place of entry magnitudes.  Row i:
+//   tol = tau * ||A(i, :)||_F (all stored entries of the block row);
+//   w = A(i, :); for k < i in ascending order among w's blocks (fill included):
+//     w(k) <- w(k) U(k,k)^-1; if ||w(k)||_F < tol drop it, else w(j) -= w(k) U(k,j)
+//     for every block j > k of U's row k (creating fill);
+//   U part: drop blocks j > i with ||w(j)||_F < tol;
+//   keep at most floor(p * nL) blocks of the L part and floor(p * nU) of the U part (nL,
+//   nU: A's blocks of row i below / above the diagonal), the largest norms first, ties
+//   to the smaller column; the diagonal block is always kept and inverted.
+bool ilut_build(const Csr& A, int b, double p, double tau, int sweeps, Ilu& F,
+                const char** msg) {
+  const i64 nn = A.nr / b;
+  const int bs = b * b;
+  F = Ilu();
+  F.b = b;
+  F.nn = nn;
+  F.sweeps = sweeps;
+  F.cols.resize(nn);
+  F.vals.resize(nn);
+  F.Dinv.assign((size_t)nn * bs, 0.0);
+  std::vector<double> T(bs), Pr(bs);
+  for (i64 i = 0; i < nn; ++i) {
+    BlockRow br = gather_block_row(A, b, i);
+    double s2 = 0.0;
+    for (size_t e = 0; e < br.vals.size(); ++e) s2 = s2 + br.vals[e] * br.vals[e];
+    const double tol = tau * std::sqrt(s2);
+    int nL = 0, nU = 0;
+    std::map<i32, std::vector<double>> w;
+    for (size_t t = 0; t < br.cols.size(); ++t) {
+      if (br.cols[t] < i) ++nL;
+      if (br.cols[t] > i) ++nU;
+      w[br.cols[t]].assign(&br.vals[t * bs], &br.vals[t * bs] + bs);
+    }
+    for (auto it = w.begin(); it != w.end() && it->first < i;) {
+      const i32 k = it->first;
+      bmul(b, it->second.data(), &F.Dinv[(size_t)k * bs], T.data());
+      if (fnorm(bs, T.data()) < tol) {
+        it = w.erase(it);
+        continue;
+      }
+      it->second = T;
+      for (size_t t = 0; t < F.cols[k].size(); ++t) {
+        const i32 j = F.cols[k][t];
+        if (j <= k) continue;
+        bmul(b, T.data(), &F.vals[k][t * bs], Pr.data());
+        auto f = w.find(j);
+        if (f == w.end()) f = w.emplace(j, std::vector<double>(bs, 0.0)).first;
+        for (int e = 0; e < bs; ++e) f->second[e] = f->second[e] - Pr[e];
+      }
+      ++it;
+    }
+    auto d = w.find((i32)i);
+    if (d == w.end()) {
+      *msg = "oracle: ILUT needs a diagonal block in every row";
+      return false;
+    }
+    // candidates of each triangle in ascending column order, then the largest kept
+    std::vector<std::pair<i32, double>> lo, up;
+    for (auto& kv : w) {
+      const double nr = fnorm(bs, kv.second.data());
+      if (kv.first < i) lo.push_back({kv.first, nr});
+      else if (kv.first > i && !(nr < tol)) up.push_back({kv.first, nr});
+    }
+    auto keep = [](std::vector<std::pair<i32, double>>& v, size_t cap) {
+      std::stable_sort(v.begin(), v.end(), [](const std::pair<i32, double>& a,
+                                              const std::pair<i32, double>& c) {
+        return a.second > c.second;
+      });
+      if (v.size() > cap) v.resize(cap);
+      std::sort(v.begin(), v.end());
+    };
+    keep(lo, (size_t)std::floor(p * nL));
+    keep(up, (size_t)std::floor(p * nU));
+    if (!gj_inverse(b, d->second.data(), &F.Dinv[(size_t)i * bs])) {
+      *msg = "oracle: singular ILUT pivot block";
+      return false;
+    }
+    for (auto& c : lo) {
+      F.cols[i].push_back(c.first);
+      F.vals[i].insert(F.vals[i].end(), w[c.first].begin(), w[c.first].end());
+    }
+    F.cols[i].push_back((i32)i);
+    F.vals[i].insert(F.vals[i].end(), d->second.begin(), d->second.end());
+    for (auto& c : up) {
+      F.cols[i].push_back(c.first);
+      F.vals[i].insert(F.vals[i].end(), w[c.first].begin(), w[c.first].end());
+    }
   }
   return true;
 }

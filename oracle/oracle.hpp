@@ -25,7 +25,9 @@
 // published outputs for the shadow space, the m + m/s termination bound, dense
 // LU), and block ILU(k) (exact LU of a tridiagonal matrix, (LU)_ij = A_ij on the
 // factor's pattern, exactness of enough Jacobi sweeps, block Jacobi at zero
-// sweeps).
+// sweeps), and block ILUT (a hand-derived 4 x 4 case with a fill block dropped by the
+// tolerance and one by the cap, the exact LU at tau = 0, block Jacobi for a tolerance
+// above every row norm, the per-row cap on random matrices).
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -76,7 +78,7 @@ void stokes_assemble(int n, const double* theta, Csr& A);
 void theta_gradient(int n, const double* lambda, const double* x, double* g);
 
 // ---- smoothed-aggregation hierarchy (amg.cpp) ----------------------------
-enum Smoother { SPAI0_BLOCK = 0, JACOBI = 1, SPAI0_SCALAR = 2, ILU0 = 3 };
+enum Smoother { SPAI0_BLOCK = 0, JACOBI = 1, SPAI0_SCALAR = 2, ILU0 = 3, ILUT = 4 };
 
 struct AmgParams {
   double eps_strong = 0.08;
@@ -85,7 +87,9 @@ struct AmgParams {
   int smoother = SPAI0_BLOCK;
   double jacobi_omega = 2.0 / 3.0;
   bool smooth_p = true;       // false: plain aggregation, P = P_tent
-  int ilu_sweeps = 2;         // Jacobi sweeps per factor of the ILU0 smoother
+  int ilu_sweeps = 2;         // Jacobi sweeps per factor of the ILU0 / ILUT smoother
+  double ilut_p = 2.0;        // ILUT fill cap relative to A's blocks per row and triangle
+  double ilut_tau = 1e-2;     // ILUT drop tolerance relative to the block row's norm
 };
 
 // Block ILU(k) (ilu.cpp): per block row, the sorted block columns of the
@@ -101,6 +105,9 @@ struct Ilu {
   std::vector<double> Dinv;
 };
 bool ilu_build(const Csr& A, int b, int level, int sweeps, Ilu& F, const char** msg);
+// Block ILUT(p, tau) (threshold dropping and a fill cap per row), same factor layout.
+bool ilut_build(const Csr& A, int b, double p, double tau, int sweeps, Ilu& F,
+                const char** msg);
 void ilu_apply(const Ilu& F, const double* r, double* z);
 
 struct Level {
@@ -108,7 +115,7 @@ struct Level {
   std::vector<i32> agg;       // aggregate of each node, -1 if isolated
   std::vector<char> isolated;
   std::vector<double> M;      // smoother: one b x b block per node
-  Ilu F;                      // block ILU(0) factors when the smoother is ILU0
+  Ilu F;                      // block ILU(0) / ILUT factors when the smoother is one
   double omega = 0;           // prolongator damping used to build P
   i64 n_agg = 0;
 };

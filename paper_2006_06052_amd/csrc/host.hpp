@@ -40,7 +40,10 @@ struct SetupParams {
   int smoother = SM_SPAI0_BLOCK;
   double jacobi_omega = 2.0 / 3.0;
   bool smooth_p = true;          // false: plain aggregation, P = P_tent
-  bool ilu_smoother = false;     // block ILU(0) smoothing instead of the block-diagonal smoother
+  bool ilu_smoother = false;     // block ILU smoothing instead of the block-diagonal smoother
+  int ilu_kind = 0;              // ... with ILU(0) (0) or ILUT(ilut_p, ilut_tau) (1)
+  double ilut_p = 2.0;
+  double ilut_tau = 1e-2;
   int ilu_sweeps = 2;            // Jacobi sweeps per factor of the ILU smoother
 };
 
@@ -81,6 +84,8 @@ HBsr scalar_form(const HBsr& A);
 int scalar_spai0(const HBsr& A, std::vector<double>& m, std::string& err);
 
 int ilu_factor(const HBsr& A, int level, IluFactors& out, std::string& err);
+// Block ILUT(p, tau): threshold dropping and at most floor(p n) blocks per row and triangle.
+int ilut_factor(const HBsr& A, double p, double tau, IluFactors& out, std::string& err);
 
 // Ingest helpers.
 int csr_to_bsr(int32_t nrows, const int32_t* ptr, const int32_t* col, const double* val,

@@ -15,6 +15,7 @@
 #include "host.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 
 namespace mgk {
@@ -114,6 +115,119 @@ int ilu_factor(const HBsr& A, int level, IluFactors& out, std::string& err) {
       HBsr& M = j < i ? out.L : out.U;
       M.col.push_back(j);
       M.val.insert(M.val.end(), &vals[i][t * bs], &vals[i][t * bs] + bs);
+    }
+    out.L.ptr[i + 1] = (int32_t)out.L.col.size();
+    out.U.ptr[i + 1] = (int32_t)out.U.col.size();
+  }
+  out.Dinv = std::move(Dinv);
+  return 0;
+}
+
+// Block ILUT(p, tau) (Saad's threshold ILU, Iterative Methods for Sparse Linear Systems,
+// Sec. 10.4), the smoother the paper names for its Schur velocity AMG (Section 4, the V2
+// and V3 listings), on b x b blocks with Frobenius norms in place of magnitudes.  Block
+// row i is eliminated against the already finished rows:
+//   drop tolerance t_i = tau * ||A(i, :)||_F over the row's stored entries (block
+//     columns ascending, entries row-major);
+//   working row w = A(i, :); for k < i in ascending order, fill included: w(k) = w(k)
+//     U(k,k)^-1, dropped when ||w(k)||_F < t_i, otherwise w(j) -= w(k) U(k,j) for the
+//     stored blocks j > k of U's row k (absent w(j) start at zero);
+//   upper blocks with ||w(j)||_F < t_i are dropped;
+//   L keeps at most floor(p n_L) and U at most floor(p n_U) blocks, n_L and n_U being
+//     A's stored blocks of row i below and above the diagonal: the largest norms, ties to
+//     the smaller block column; the diagonal block is always kept.
+// Same arithmetic rules as ILU(k), so the factors are reproducible bit for bit.
+int ilut_factor(const HBsr& A, double p, double tau, IluFactors& out, std::string& err) {
+  if (A.br != A.bc) {
+    err = "ILUT needs square blocks";
+    return -1;
+  }
+  if (!(p >= 0.0) || !(tau >= 0.0) || !std::isfinite(p) || !std::isfinite(tau)) {
+    err = "ILUT needs finite p >= 0 and tau >= 0";
+    return -1;
+  }
+  const int b = A.br, bs = b * b;
+  const int32_t n = A.nbr;
+  auto norm = [bs](const double* X) {
+    double s = 0.0;
+    for (int e = 0; e < bs; ++e) s = s + X[e] * X[e];
+    return std::sqrt(s);
+  };
+  auto init = [&](HBsr& M) {
+    M = HBsr();
+    M.br = M.bc = b;
+    M.nbr = M.nbc = n;
+    M.ptr.assign(n + 1, 0);
+  };
+  init(out.L);
+  init(out.U);
+  std::vector<double> Dinv((size_t)n * bs);
+  std::vector<double> T(bs), Pr(bs);
+  struct Cand {
+    int32_t col;
+    double nrm;
+  };
+  std::vector<Cand> lo, up;
+  for (int32_t i = 0; i < n; ++i) {
+    double s2 = 0.0;
+    int nL = 0, nU = 0;
+    std::map<int32_t, std::vector<double>> w;
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const double* X = A.blk(k);
+      for (int e = 0; e < bs; ++e) s2 = s2 + X[e] * X[e];
+      nL += A.col[k] < i;
+      nU += A.col[k] > i;
+      w[A.col[k]].assign(X, X + bs);
+    }
+    const double tol = tau * std::sqrt(s2);
+    for (auto it = w.begin(); it != w.end() && it->first < i;) {
+      const int32_t k = it->first;
+      block_mul(b, it->second.data(), &Dinv[(size_t)k * bs], T.data());
+      if (norm(T.data()) < tol) {
+        it = w.erase(it);
+        continue;
+      }
+      it->second.assign(T.begin(), T.end());
+      for (int32_t q = out.U.ptr[k]; q < out.U.ptr[k + 1]; ++q) {
+        block_mul(b, T.data(), &out.U.val[(size_t)q * bs], Pr.data());
+        std::vector<double>& wj = w[out.U.col[q]];
+        if (wj.empty()) wj.assign(bs, 0.0);
+        for (int e = 0; e < bs; ++e) wj[e] = wj[e] - Pr[e];
+      }
+      ++it;
+    }
+    const auto d = w.find(i);
+    if (d == w.end()) {
+      err = "ILUT: a block row has no diagonal block";
+      return -1;
+    }
+    lo.clear();
+    up.clear();
+    for (const auto& kv : w) {
+      const double nr = norm(kv.second.data());
+      if (kv.first < i) lo.push_back({kv.first, nr});
+      else if (kv.first > i && !(nr < tol)) up.push_back({kv.first, nr});
+    }
+    auto select = [](std::vector<Cand>& v, size_t cap) {
+      std::stable_sort(v.begin(), v.end(), [](const Cand& a, const Cand& c) {
+        return a.nrm > c.nrm;
+      });
+      if (v.size() > cap) v.resize(cap);
+      std::sort(v.begin(), v.end(), [](const Cand& a, const Cand& c) { return a.col < c.col; });
+    };
+    select(lo, (size_t)std::floor(p * nL));
+    select(up, (size_t)std::floor(p * nU));
+    if (!gauss_jordan_inverse(b, d->second.data(), &Dinv[(size_t)i * bs])) {
+      err = "ILUT: singular pivot block";
+      return -4;
+    }
+    for (const Cand& c : lo) {
+      out.L.col.push_back(c.col);
+      out.L.val.insert(out.L.val.end(), w[c.col].begin(), w[c.col].end());
+    }
+    for (const Cand& c : up) {
+      out.U.col.push_back(c.col);
+      out.U.val.insert(out.U.val.end(), w[c.col].begin(), w[c.col].end());
     }
     out.L.ptr[i + 1] = (int32_t)out.L.col.size();
     out.U.ptr[i + 1] = (int32_t)out.U.col.size();

@@ -503,7 +503,9 @@ int build_hierarchy(const HBsr& A0, const SetupParams& prm, HHierarchy& H, std::
         L.R = block_transpose(L.P);
         HBsr AP = block_spgemm(L.A, L.P);
         Ac = block_spgemm(L.R, AP);
-        rc = prm.ilu_smoother ? ilu_factor(L.A, 0, L.ilu, err) : build_smoother(L.A, prm, L.M, err);
+        rc = !prm.ilu_smoother ? build_smoother(L.A, prm, L.M, err)
+             : prm.ilu_kind == 1 ? ilut_factor(L.A, prm.ilut_p, prm.ilut_tau, L.ilu, err)
+                                 : ilu_factor(L.A, 0, L.ilu, err);
         if (rc) return rc;
       }
     }

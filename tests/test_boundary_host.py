@@ -291,3 +291,42 @@ def test_host_setup_matches_oracle_at_workload_shape(name):
         os_ = oracle.Solver(A, 4)
         del A
         compare_hierarchies(hs, 0, os_, 0, levels_expected=3)
+
+
+@pytest.mark.parametrize("n,p,tau", [(6, 2.0, 1e-2), (7, 1.0, 5e-2), (6, 3.0, 1e-3)])
+def test_host_ilut_factors_match_oracle_bitwise(n, p, tau):
+    """Block ILUT(p, tau) host factorization: L and U blocks (pattern and values) and the
+    pivot inverses bit-exact against the oracle."""
+    th = S.theta_field(n, 0.5, 30 + n)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    hs = host_solver(ptr, col, val, 4, mgk.ILU, ilu_kind=1, ilut_p=p, ilut_tau=tau)
+    (lp, lc, lv), (up, uc, uv), dinv = hs.ilu_export()
+    so = oracle.Solver(oracle.stokes_matrix(n, th), 4, kind=oracle.KIND_ILU, ilu_kind=1,
+                       ilut_p=p, ilut_tau=tau)
+    F = so.ilu_factor()
+    optr, ocol, oval = oracle_blocks(F, 4)
+    dropped = 0
+    for i in range(n ** 3):
+        oc = ocol[optr[i]:optr[i + 1]]
+        ov = oval[optr[i]:optr[i + 1]]
+        lo, up_ = oc < i, oc > i
+        assert np.array_equal(lc[lp[i]:lp[i + 1]], oc[lo]) and np.array_equal(lv[lp[i]:lp[i + 1]], ov[lo])
+        assert np.array_equal(uc[up[i]:up[i + 1]], oc[up_]) and np.array_equal(uv[up[i]:up[i + 1]], ov[up_])
+        dropped += (ptr[i + 1] - ptr[i]) - (lp[i + 1] - lp[i]) - (up[i + 1] - up[i]) - 1
+    assert np.array_equal(dinv, so.ilu_dinv())
+    assert dropped != 0 or tau < 1e-2          # the threshold is active in these cases
+
+
+def test_host_setup_matches_oracle_ilut_smoothed_schur():
+    """The paper's Schur configuration with the ILUT-smoothed velocity AMG (plain
+    aggregation, diagonal pressure approximation): the hierarchy bit-exact against the
+    oracle's (each level's ILUT factors enter the FP64 V-cycle compared on the GPU)."""
+    n = 12
+    th = S.theta_field(n, 1.0, 3)
+    ptr, col, val = mgk.stokes_bsr(n, th)
+    kw = dict(coarse_enough=150, schur_approx=1, schur_spai0=1)
+    hs = host_solver(ptr, col, val, 4, mgk.SCHUR, coarsening=mgk.PLAIN_AGGREGATION,
+                     ilu_smoother=1, ilu_kind=1, **kw)
+    os_ = oracle.Solver(oracle.stokes_matrix(n, th), 4, kind=oracle.KIND_SCHUR,
+                        coarsening=oracle.PLAIN, smoother=oracle.ILUT, **kw)
+    compare_hierarchies(hs, 0, os_, 0, levels_expected=2)

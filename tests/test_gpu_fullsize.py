@@ -229,13 +229,15 @@ def test_batch_eight_systems_vs_oracle():
 
 # the paper's Schur configuration on the 64^3 log-normal system, as the benchmark times it:
 # IDR(5), plain-aggregation velocity AMG (scalar or 3x3-block values), pressure step one
-# SPAI(0) application of the diagonal Schur approximation, and the block ILU(0)-smoothed
-# velocity AMG
+# SPAI(0) application of the diagonal Schur approximation, and the velocity AMG smoothed by
+# block ILUT(2, 0.01) (the paper's smoother) or block ILU(0)
 PAPER_SCHUR64 = {
     "scalar_f64": dict(hier="f64", schur_scalar_u=1),
     "f64": dict(hier="f64"),
     "f32": dict(hier="f32"),
     "bf16": dict(hier="bf16"),
+    "ilut_f64": dict(hier="f64", ilu_smoother=1, ilu_kind=1, ilu_sweeps=2),
+    "ilut_f32": dict(hier="f32", ilu_smoother=1, ilu_kind=1, ilu_sweeps=2),
     "ilu_f64": dict(hier="f64", ilu_smoother=1, ilu_sweeps=2),
     "ilu_f32": dict(hier="f32", ilu_smoother=1, ilu_sweeps=2),
 }
@@ -250,13 +252,18 @@ def cube64_lognormal():
     return mgk.stokes_bsr(n, th), A, oracle.spmv(A, xs), xs
 
 
+# The log-normal viscosity (sigma = 1, spanning about e^(+-4)) amplifies the residual into
+# the solution: at rtol 1e-8 the solution error is about 1e-6 (1.08e-6 measured for the FP32
+# arm).  The benchmark therefore solves this workload to rtol 1e-9, where both bars hold on
+# the same solve.
+PAPER_SCHUR64_RTOL = 1e-9
+
+
 @pytest.mark.parametrize("arm", list(PAPER_SCHUR64))
 def test_cube64_paper_schur_idrs(cube64_lognormal, arm):
     """b = A x* (x* the manufactured nodal values), so x* is the exact solution.  The solve
-    the benchmark times (rtol 1e-8) must meet the residual bar.  The viscosity spans about
-    e^(+-4), and this system amplifies a 1e-8 residual to about 1e-6 in the solution, so the
-    1e-6 solution bar is checked after the same solver continues from that result to rtol
-    1e-10."""
+    the benchmark times (rtol 1e-9) must meet both bars: ||b - A x|| <= 1e-8 ||b|| (by the
+    oracle's SpMV) and ||x - x*|| <= 1e-6 ||x*||."""
     (ptr, col, val), A, b, xs = cube64_lognormal
     kw = dict(PAPER_SCHUR64[arm])
     hier = {"f64": mgk.F64, "f32": mgk.F32, "bf16": mgk.BF16}[kw.pop("hier")]
@@ -264,16 +271,14 @@ def test_cube64_paper_schur_idrs(cube64_lognormal, arm):
     s = solver(ptr, col, val, kind=mgk.SCHUR, hier=hier, krylov=mgk.IDRS, idr_s=5,
                coarsening=mgk.PLAIN_AGGREGATION, schur_approx=1, schur_spai0=1, **kw)
     dx = torch.zeros(b.size, dtype=torch.float64, device=DEV)
-    info = s.solve(dev(b), dx, 1e-8)
+    info = s.solve(dev(b), dx, PAPER_SCHUR64_RTOL)
     say("paper_schur64 gpu", arm, info)
     x = dx.cpu().numpy()
     res = np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b)
-    assert info["status"] == 0 and res <= 1e-8, res
-    say("paper_schur64 error at rtol 1e-8", np.linalg.norm(x - xs) / np.linalg.norm(xs))
-    info = s.solve(dev(b), dx, 1e-10)
-    assert info["status"] == 0, info
-    x = dx.cpu().numpy()
-    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    say("paper_schur64 residual", res, "error", err)
+    assert info["status"] == 0 and res <= PAPER_SCHUR64_RTOL, res
+    assert err <= 1e-6, err
 
 
 @pytest.fixture(scope="module")

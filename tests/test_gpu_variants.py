@@ -249,6 +249,73 @@ def test_paper_v2_shape_schur_ilu_smoothed(storage):
     check_solution(A, b, dx.cpu().numpy(), xo)
 
 
+@pytest.mark.parametrize("p,tau,sweeps", [(2.0, 1e-2, 2), (1.0, 5e-2, 3), (3.0, 1e-3, 0)])
+def test_ilut_application_matches_oracle(p, tau, sweeps):
+    """Block ILUT(p, tau) as the monolithic preconditioner: the FP64 application (Jacobi
+    sweeps on the threshold factors) agrees with the oracle's to rounding."""
+    n = 10
+    th, bsr, A = problem(n, 0.5, 25)
+    s = gpu_solver(bsr, mgk.ILU, ilu_kind=1, ilut_p=p, ilut_tau=tau, ilu_sweeps=sweeps)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_ILU, ilu_kind=1, ilut_p=p, ilut_tau=tau,
+                       ilu_sweeps=sweeps)
+    r = np.random.default_rng(8).normal(size=A.shape[0])
+    dz = torch.empty(A.shape[0], dtype=torch.float64, device=DEV)
+    s.precond(dev(r), dz)
+    zo = so.precond(r)
+    assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-12 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_paper_schur_ilut_smoothed(storage):
+    """The paper's Schur configuration (listings V2-V4): IDR(5); velocity AMG with plain
+    aggregation smoothed by block ILUT(2, 0.01) on the 3x3 blocks; SPAI(0) pressure step on
+    the diagonal Schur approximation.  The FP64 preconditioner application agrees with the
+    oracle's; FP64, FP32 and BF16 hierarchies solve to the oracle's solution."""
+    n = 14
+    th, bsr, A = problem(n, 1.0, 18)
+    b = oracle.spmv(A, S.mms_solution(n))
+    kw = dict(schur_approx=1, schur_spai0=1, coarse_enough=300, ilu_sweeps=2)
+    s = gpu_solver(bsr, mgk.SCHUR, krylov=mgk.IDRS, idr_s=5, hier=storage, ilu_smoother=1,
+                   ilu_kind=1, coarsening=mgk.PLAIN_AGGREGATION, **kw)
+    so = oracle.Solver(A, 4, kind=oracle.KIND_SCHUR, krylov=oracle.IDRS, idr_s=5,
+                       smoother=oracle.ILUT, coarsening=oracle.PLAIN, **kw)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    if storage == "f64":
+        r = np.random.default_rng(10).normal(size=A.shape[0])
+        s.precond(dev(r), dx)
+        zo = so.precond(r)
+        assert np.linalg.norm(dx.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+        dx.zero_()
+    info = s.solve(dev(b), dx, 1e-8)
+    xo, oi = so.solve(b, 1e-12)
+    say("paper schur ilut", storage, info["iters"], oi["iters"])
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_amg_with_ilut_smoother(storage):
+    """Monolithic AMG with every level smoothed by block ILUT: FP64 V-cycle vs oracle,
+    solves vs the oracle's solution."""
+    n = 12
+    th, bsr, A = problem(n, 0.5, 26)
+    b = oracle.spmv(A, S.mms_solution(n))
+    s = gpu_solver(bsr, hier=storage, coarse_enough=300, ilu_smoother=1, ilu_kind=1,
+                   ilu_sweeps=2)
+    so = oracle.Solver(A, 4, coarse_enough=300, smoother=oracle.ILUT, ilu_sweeps=2)
+    dx = torch.zeros(A.shape[0], dtype=torch.float64, device=DEV)
+    if storage == "f64":
+        r = np.random.default_rng(11).normal(size=A.shape[0])
+        s.precond(dev(r), dx)
+        zo = so.precond(r)
+        assert np.linalg.norm(dx.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+        dx.zero_()
+    info = s.solve(dev(b), dx, 1e-8)
+    xo, _ = so.solve(b, 1e-12)
+    assert info["status"] == 0
+    check_solution(A, b, dx.cpu().numpy(), xo)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_schur_scalar_velocity_amg(storage):
     """Schur preconditioner with the velocity AMG on scalar values: agrees with the oracle

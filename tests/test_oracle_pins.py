@@ -747,6 +747,75 @@ def test_ilu_sweeps_limit_and_zero_sweeps():
     assert np.allclose(zero.precond(r), np.linalg.solve(Dm, r), rtol=1e-12)
 
 
+def test_ilut_hand_derived():
+    """ILUT(p = 1, tau = 0.05) of the 4 x 4 matrix [[4,1,0,1],[1,4,1,0],[0,1,4,1],[1,0,1,4]]
+    by hand (every row norm is sqrt(18), so the drop tolerance is 0.05 sqrt(18) = 0.2121):
+      row 0: U = (4, 1, 0, 1);
+      row 1: l10 = 1/4 (kept), fill u13 = -1/4 passes the tolerance but the cap of
+             p * 1 upper block keeps only u12 = 1; u11 = 4 - 1/4 = 3.75;
+      row 2: l21 = 1/3.75, u22 = 4 - 1/3.75, u23 = 1;
+      row 3: l30 = 1/4; the fill at (3,1), -1/4, becomes -1/4 / 3.75 = -0.0667 and is
+             dropped (below 0.2121, and not eliminated further); l32 = 1 / u22;
+             u33 = 4 - 1/4 - l32."""
+    A = sp.csr_matrix(np.array([[4.0, 1, 0, 1], [1, 4, 1, 0], [0, 1, 4, 1], [1, 0, 1, 4]]))
+    s = oracle.Solver(A, 1, kind=oracle.KIND_ILU, ilu_kind=1, ilut_p=1.0, ilut_tau=0.05)
+    F = dense(s.ilu_factor())
+    u22 = 4.0 - 1.0 / 3.75
+    l32 = 1.0 / u22
+    expect = np.array([[4.0, 1.0, 0.0, 1.0],
+                       [0.25, 3.75, 1.0, 0.0],
+                       [0.0, 1.0 / 3.75, u22, 1.0],
+                       [0.25, 0.0, l32, 4.0 - 0.25 - l32]])
+    assert np.abs(F - expect).max() <= 1e-15
+    assert s.ilu_factor().nnz == 12          # neither (3,1) nor (1,3) is stored
+    assert np.allclose(s.ilu_dinv()[:, 0, 0], 1.0 / np.diag(expect), rtol=1e-15)
+
+
+def test_ilut_limits():
+    """tau = 0 with an unlimited fill cap keeps every block: ILUT is then the exact block
+    LU without pivoting, L U = A (the smallest pivot of this diagonally dominated system
+    keeps it stable); a tolerance larger than any row norm drops every off-diagonal block,
+    leaving the diagonal blocks of A and their inverses (block Jacobi)."""
+    n = 4
+    A = oracle.stokes_matrix(n, S.theta_field(n, 0.5, 6))
+    b = 4
+    full = oracle.Solver(A, b, kind=oracle.KIND_ILU, ilu_kind=1, ilut_p=1e6, ilut_tau=0.0)
+    L, U = split_lu(dense(full.ilu_factor()), b)
+    Ad = dense(A)
+    assert np.abs(L @ U - Ad).max() <= 1e-11 * np.abs(Ad).max()
+    diag = oracle.Solver(A, b, kind=oracle.KIND_ILU, ilu_kind=1, ilut_p=2.0, ilut_tau=1e9)
+    Fd = dense(diag.ilu_factor())
+    nb = n ** 3
+    for i in range(nb):
+        blk = Fd[b * i:b * i + b]
+        Dii = Ad[b * i:b * i + b, b * i:b * i + b]
+        assert np.array_equal(blk[:, b * i:b * i + b], Dii)
+        assert np.count_nonzero(blk) == np.count_nonzero(Dii)
+        assert np.allclose(diag.ilu_dinv()[i], np.linalg.inv(Dii), rtol=1e-12)
+
+
+def test_ilut_cap_keeps_largest_blocks():
+    """With tau = 0 the cap alone decides: every row of L and of U keeps at most
+    floor(p * n) blocks (n: A's blocks of that row and triangle) and always its diagonal
+    block.  Checked on a random block matrix with random fill for three caps."""
+    rng = np.random.default_rng(3)
+    nb, b = 12, 3
+    D = sp.random(nb * b, nb * b, density=0.25, random_state=4, data_rvs=lambda k: rng.normal(size=k))
+    A = sp.csr_matrix(D + sp.eye(nb * b) * 8.0)
+    for p in (0.5, 1.0, 1.5):
+        s = oracle.Solver(A, b, kind=oracle.KIND_ILU, ilu_kind=1, ilut_p=p, ilut_tau=0.0)
+        Fd = dense(s.ilu_factor())
+        Ad = dense(A)
+        for i in range(nb):
+            a_blocks = [j for j in range(nb) if np.any(Ad[b * i:b * i + b, b * j:b * j + b])]
+            nL = sum(j < i for j in a_blocks)
+            nU = sum(j > i for j in a_blocks)
+            f_blocks = [j for j in range(nb) if np.any(Fd[b * i:b * i + b, b * j:b * j + b])]
+            assert sum(j < i for j in f_blocks) <= int(np.floor(p * nL))
+            assert sum(j > i for j in f_blocks) <= int(np.floor(p * nU))
+            assert i in f_blocks
+
+
 def test_idrs_with_ilu1_reaches_dense_solution():
     """The paper's monolithic configuration (IDR(5) with ILU(1)) on a small system."""
     n = 6
