@@ -99,8 +99,10 @@ typedef struct {
   int32_t keep_host;       /* 1: keep FP64 host copies of every level for
                               mgk_level_export (default 0) */
   int32_t enable_transpose;/* 1: build the A^T indices for adjoint solves (default 0) */
-  int32_t time_spmv;       /* 1: time every outer-operator SpMV of a solve with HIP
-                              events on the solver's stream (mgk_info.spmv_ms) */
+  int32_t time_spmv;       /* bit mask: 1 times every outer-operator SpMV of a solve
+                              (mgk_info.spmv_ms), 2 every preconditioner application
+                              (mgk_info.precond_ms), with HIP events on the solver's
+                              stream around each launch sequence */
   int32_t force_tile;      /* 0: the autotuner picks each operator's kernel tile;
                               otherwise 10000*RPL + 100*S + U (S lanes per block row, U
                               blocks per step, RPL scalar rows per lane) for every
@@ -130,7 +132,16 @@ typedef struct {
   int32_t schur_scalar_u;  /* MGK_SCHUR: 1 builds the velocity AMG on the scalar values of
                               A_uu (1x1 blocks, zero entries dropped) instead of 3x3 blocks -
                               the paper's scalar (V2) versus block-valued (V3) solver */
-  int32_t reserved;
+  int32_t ilu_kind;        /* factorization of MGK_ILU and of the ILU smoother: 0 (default)
+                              block ILU(k) (k = ilu_level for MGK_ILU, 0 for the smoother);
+                              1 block ILUT(ilut_p, ilut_tau) - threshold ILU (Saad), the
+                              smoother of the paper's velocity AMG (Section 4, listings V2
+                              and V3): blocks below ilut_tau times the block row's Frobenius
+                              norm are dropped during and after elimination, and each row
+                              keeps at most floor(ilut_p * n) blocks per triangle (n: A's
+                              blocks of that row and triangle), the largest first */
+  double ilut_p;           /* ILUT fill cap factor, 0..1e6, default 2 */
+  double ilut_tau;         /* ILUT drop tolerance, >= 0, default 0.01 */
 } mgk_params;
 
 typedef struct {
@@ -142,8 +153,12 @@ typedef struct {
   double setup_ms;
   double solve_ms;
   int64_t device_bytes;    /* device memory held by the solver */
-  double spmv_ms;          /* with time_spmv: summed duration of the outer SpMVs */
+  double spmv_ms;          /* with time_spmv bit 1: summed duration of the outer SpMVs */
   int32_t spmv_calls;      /* ... and their number */
+  int32_t outer_tile;      /* kernel tile of the outer operator, 10000*RPL + 100*S + U */
+  double precond_ms;       /* with time_spmv bit 2: summed duration of the preconditioner
+                              applications */
+  int32_t precond_calls;   /* ... and their number */
   int32_t reserved;
 } mgk_info;
 

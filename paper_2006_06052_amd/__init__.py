@@ -45,14 +45,17 @@ class Params(C.Structure):
                 ("coarsening", C.c_int32), ("schur_approx", C.c_int32),
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
                 ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("ilu_smoother", C.c_int32),
-                ("schur_scalar_u", C.c_int32), ("reserved", C.c_int32)]
+                ("schur_scalar_u", C.c_int32), ("ilu_kind", C.c_int32),
+                ("ilut_p", C.c_double), ("ilut_tau", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("levels", C.c_int32), ("restarts", C.c_int32),
                 ("status", C.c_int32), ("rel_resid", C.c_double), ("setup_ms", C.c_double),
                 ("solve_ms", C.c_double), ("device_bytes", C.c_int64),
-                ("spmv_ms", C.c_double), ("spmv_calls", C.c_int32), ("reserved", C.c_int32)]
+                ("spmv_ms", C.c_double), ("spmv_calls", C.c_int32), ("outer_tile", C.c_int32),
+                ("precond_ms", C.c_double), ("precond_calls", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -119,8 +119,10 @@ struct DMat {
 // outer operator they cost 10% (its value stream then evicts the gathered x, a 28 MB
 // vector, from L2).  The environment variable MGK_CACHED_LOADS, read at setup,
 // overrides the choice with a bit mask of the operators read with cached loads: 1 BF16,
-// 2 FP32 and 4 FP64 preconditioner operators, 8 the FP64 outer operator (default 7).
-// Results are bitwise the same either way.
+// 2 FP32 and 4 FP64 preconditioner operators, 8 the FP64 outer operator (in every product
+// with it, the fused SpMV-and-dots included) together with the level 0 of an FP64
+// hierarchy, which shares the outer operator's arrays (default 7).  Results are bitwise
+// the same either way.
 inline bool operator_cached(int storage, bool outer) {
   const char* e = getenv("MGK_CACHED_LOADS");
   const int mask = e ? atoi(e) : 7;
@@ -286,6 +288,9 @@ static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& til
     if (trans)
       k_spmv_dot<BR, BC, S_, U_, true, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
                                                                          y, two, w1, part);
+    else if (M.cached)
+      k_spmv_dot<BR, BC, S_, U_, false, double, double, true><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, x, y, two, w1, part);
     else
       k_spmv_dot<BR, BC, S_, U_, false, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
                                                                           y, two, w1, part);
@@ -555,6 +560,8 @@ struct mgk_solver {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> tev;   // timing events around outer SpMV launches
   size_t tev_used = 0;
+  std::vector<hipEvent_t> pev;   // timing events around preconditioner applications
+  size_t pev_used = 0;
   // FGMRES
   double *V = nullptr, *Z = nullptr, *h = nullptr, *hsum = nullptr, *yv = nullptr;
   double* hpin = nullptr;
@@ -571,6 +578,8 @@ struct mgk_solver {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : tev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : pev)
       if (e) (void)hipEventDestroy(e);
     if (hsc) (void)hipHostFree(hsc);
     if (hpin) (void)hipHostFree(hpin);

@@ -365,7 +365,7 @@ constexpr int dot_rows() {
   return BR == 1 ? 64 : 16;
 }
 
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX>
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, bool CACHED = false>
 __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const int* __restrict__ blk,
@@ -399,8 +399,8 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
     const bool own = L.active && L.s == 0 && L.i < rb1;
     const size_t row = (size_t)L.i * BR + L.r;
     const double wv = own ? __builtin_nontemporal_load(w1 + row) : 0.0;   // ahead of the product
-    const double acc = row_product<BR, BC, S, U, TRANS, TV, TX, double>(L, lim, ptr, col, blk,
-                                                                        val, x);
+    const double acc = row_product<BR, BC, S, U, TRANS, TV, TX, double, CACHED>(L, lim, ptr, col,
+                                                                                blk, val, x);
     if (own) {
       __builtin_nontemporal_store(acc, y + row);
       const int q = (L.i - rb0) * BR + L.r;

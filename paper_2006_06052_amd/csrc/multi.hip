@@ -169,10 +169,16 @@ static int outer_spmm_dot(mgk_solver* S, int K, const double* X, double* Y, int 
   const int g = (S->nbr + MROWS - 1) / MROWS;
   const DMat& A = S->A;
   double* part = S->multi->part;
+  const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
+  if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
   switch (S->b) {
     case 1: k_spmm_dot<1><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
     case 3: k_spmm_dot<3><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
     case 4: k_spmm_dot<4><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
+  }
+  if (timed) {
+    HIPCK(hipEventRecord(S->tev[S->tev_used + 1], st));
+    S->tev_used += 2;
   }
   return g;
 }
@@ -375,16 +381,25 @@ extern "C" int mgk_solve_multi(mgk_solver* s, int32_t nrhs, const double* d_B, d
   return mgk::guard([&]() -> int {
     auto t0 = std::chrono::steady_clock::now();
     std::memset(infos, 0, sizeof(mgk_info) * nrhs);
+    s->tev_used = 0;
     const int rc = mgk::bicgstab_multi(s, nrhs, d_B, d_X, rtol, infos);
     HIPCK(hipStreamSynchronize(s->dev.stream));
     HIPCK(hipGetLastError());
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    double spmm_ms = 0.0;   // the outer SpMM launches (time_spmv bit 1)
+    for (size_t e = 0; e + 1 < s->tev_used; e += 2) {
+      float t = 0.0f;
+      HIPCK(hipEventElapsedTime(&t, s->tev[e], s->tev[e + 1]));
+      spmm_ms += t;
+    }
     for (int k = 0; k < nrhs; ++k) {
       infos[k].levels = (int)s->H.lv.size();
       infos[k].setup_ms = s->setup_ms;
       infos[k].solve_ms = ms;
       infos[k].device_bytes = s->dev.bytes + s->multi->bytes;
+      infos[k].spmv_ms = spmm_ms;
+      infos[k].spmv_calls = (int32_t)(s->tev_used / 2);
     }
     return rc;
   });

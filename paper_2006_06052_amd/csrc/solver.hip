@@ -265,7 +265,7 @@ namespace mgk {
 void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots,
                 const double* w1, int* nwg) {
   hipStream_t st = S->dev.stream;
-  const bool timed = S->prm.time_spmv && S->tev_used + 2 <= S->tev.size();
+  const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
   if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
   const Tile sp = trans ? S->A.ttile : S->A.tile;
   int g = 0;
@@ -340,7 +340,20 @@ static void ilu_apply_t(mgk_solver* S, const double* r, double* z) {
   }
 }
 
+static void precond_apply(mgk_solver* S, const double* r, double* z, bool trans);
+
+// One preconditioner application z = B r, bracketed by timing events when requested.
 void precond(mgk_solver* S, const double* r, double* z, bool trans) {
+  const bool timed = (S->prm.time_spmv & 2) && S->pev_used + 2 <= S->pev.size();
+  if (timed) HIPCK(hipEventRecord(S->pev[S->pev_used], S->dev.stream));
+  precond_apply(S, r, z, trans);
+  if (timed) {
+    HIPCK(hipEventRecord(S->pev[S->pev_used + 1], S->dev.stream));
+    S->pev_used += 2;
+  }
+}
+
+static void precond_apply(mgk_solver* S, const double* r, double* z, bool trans) {
   if (S->kind == MGK_ILU) {
     if (trans) throw Error(MGK_E_STATE, "transposed ILU preconditioner is not available");
     if (S->prm.hier == MGK_F64) ilu_apply_t<double, double>(S, r, z);
@@ -594,6 +607,9 @@ static SetupParams setup_params(const mgk_params& p, int kind) {
   sp.smoother = kind == MGK_AMG_JACOBI ? SM_JACOBI : (p.block_spai0 ? SM_SPAI0_BLOCK : SM_SPAI0_SCALAR);
   sp.smooth_p = p.coarsening == MGK_SMOOTHED_AGGREGATION;
   sp.ilu_smoother = p.ilu_smoother != 0;
+  sp.ilu_kind = p.ilu_kind;
+  sp.ilut_p = p.ilut_p;
+  sp.ilut_tau = p.ilut_tau;
   sp.ilu_sweeps = p.ilu_sweeps;
   return sp;
 }
@@ -618,9 +634,13 @@ static void alloc_krylov(mgk_solver* S) {
   S->part2 = (double*)D.alloc(sizeof(double) * (2 * (S->part_len / RED_CHUNK + 2)));
   HIPCK(hipHostMalloc((void**)&S->hsc, sizeof(double) * SC_COUNT, hipHostMallocDefault));
   for (auto& e : S->ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  if (S->prm.time_spmv) {
+  if (S->prm.time_spmv & 1) {
     S->tev.resize(2 * (2 * (size_t)S->prm.maxiter + 64));
     for (auto& e : S->tev) HIPCK(hipEventCreate(&e));
+  }
+  if (S->prm.time_spmv & 2) {
+    S->pev.resize(2 * (2 * (size_t)S->prm.maxiter + 64));
+    for (auto& e : S->pev) HIPCK(hipEventCreate(&e));
   }
   if (S->prm.krylov == MGK_IDRS) S->idr = idr_create(S);
   if (S->prm.krylov == MGK_FGMRES) {
@@ -647,6 +667,10 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   if (prm->ilu_sweeps < 0 || prm->ilu_sweeps > 64)
     throw Error(MGK_E_INVALID, "ilu_sweeps must be in 0..64");
   if (prm->ilu_smoother & ~1) throw Error(MGK_E_INVALID, "ilu_smoother is 0 or 1");
+  if (prm->ilu_kind & ~1) throw Error(MGK_E_INVALID, "ilu_kind is 0 (ILU(k)) or 1 (ILUT)");
+  if (prm->ilu_kind == 1 && !(prm->ilut_p >= 0.0 && prm->ilut_p <= 1e6 && prm->ilut_tau >= 0.0 &&
+                              std::isfinite(prm->ilut_tau)))
+    throw Error(MGK_E_INVALID, "ILUT needs 0 <= ilut_p <= 1e6 and finite ilut_tau >= 0");
   if (prm->schur_scalar_u & ~1) throw Error(MGK_E_INVALID, "schur_scalar_u is 0 or 1");
   if (prm->ilu_smoother && prm->enable_transpose)
     throw Error(MGK_E_INVALID, "the ILU smoother has no transposed cycle (enable_transpose)");
@@ -688,7 +712,10 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     const SetupParams sp = setup_params(*prm, kind);
     int rc;
     if (kind == MGK_ILU) {
-      if ((rc = ilu_factor(H, prm->ilu_level, S->ilu_host, err))) throw Error(rc, err);
+      if ((rc = prm->ilu_kind == 1
+                    ? ilut_factor(H, prm->ilut_p, prm->ilut_tau, S->ilu_host, err)
+                    : ilu_factor(H, prm->ilu_level, S->ilu_host, err)))
+        throw Error(rc, err);
       S->ilu_kept = true;
     } else if (kind == MGK_SCHUR) {
       SchurParts parts;
@@ -716,7 +743,9 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   int rc;
   if (kind == MGK_ILU) {
     IluFactors f;
-    if ((rc = ilu_factor(H, prm->ilu_level, f, err))) throw Error(rc, err);
+    if ((rc = prm->ilu_kind == 1 ? ilut_factor(H, prm->ilut_p, prm->ilut_tau, f, err)
+                                 : ilu_factor(H, prm->ilu_level, f, err)))
+      throw Error(rc, err);
     S->Lf = upload_mat(S->dev, f.L, prm->hier, false);
     S->Uf = upload_mat(S->dev, f.U, prm->hier, false);
     tune_mat(S->dev, S->Lf, prm->hier, false);
@@ -822,6 +851,9 @@ int mgk_params_default(mgk_params* p) {
   p->idr_s = 5;
   p->ilu_level = 0;
   p->ilu_sweeps = 2;
+  p->ilu_kind = 0;
+  p->ilut_p = 2.0;
+  p->ilut_tau = 1e-2;
   return MGK_OK;
 }
 
@@ -908,6 +940,7 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     auto t0 = std::chrono::steady_clock::now();
     std::memset(info, 0, sizeof(*info));
     s->tev_used = 0;
+    s->pev_used = 0;
     int rc;
     if (!trans && s->prm.krylov == MGK_FGMRES) rc = mgk::fgmres(s, d_b, d_x, rtol, info);
     else if (s->prm.krylov == MGK_IDRS) rc = mgk::idrs(s, d_b, d_x, rtol, trans, info);
@@ -928,6 +961,16 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     }
     info->spmv_ms = spmv_ms;
     info->spmv_calls = (int32_t)(s->tev_used / 2);
+    double pc_ms = 0.0;
+    for (size_t e = 0; e + 1 < s->pev_used; e += 2) {
+      float ms = 0.0f;
+      HIPCK(hipEventElapsedTime(&ms, s->pev[e], s->pev[e + 1]));
+      pc_ms += ms;
+    }
+    info->precond_ms = pc_ms;
+    info->precond_calls = (int32_t)(s->pev_used / 2);
+    const mgk::Tile& ot = s->A.tile;
+    info->outer_tile = 10000 * ot.rpl + 100 * ot.s + ot.u;
     return rc;
   });
 }
