@@ -605,6 +605,19 @@ def cpu_baseline(n, b_np, log_fn, one_thread_iters=6):
                                         f"at 1 thread, scaled to {info['iters']}"}}
 
 
+def outer_kernel_name(info):
+    """Demangled name of the fused outer SpMV-and-dots kernel the solve ran: its engine tile
+    (10000 RPL + 100 S + U), the cached-load bit of the outer operator and the diagonal
+    layout flag are template arguments."""
+    t = info["outer_tile"]
+    rpl, ts, tu = t // 10000, (t // 100) % 100, t % 100
+    mask = os.environ.get("MGK_CACHED_LOADS")
+    cached = "true" if mask is not None and int(mask) & 8 else "false"
+    dia = "true" if info["outer_dia"] else "false"
+    return (f"mgk::k_spmv_dot<4, 4, {ts}, {tu}, false, double, double, {rpl}, {cached}, "
+            f"{dia}>")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -722,11 +735,12 @@ def main():
             dot_bytes = spmv_bytes + 8 * N
             t_in = ev["spmv_ms"] * 1e-3 / ev["spmv_calls"]
             ach = dot_bytes / t_in / 1e9
-            ts, tu = (info["outer_tile"] // 100) % 100, info["outer_tile"] % 100
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": f"mgk::k_spmv_dot<4, 4, {ts}, {tu}, false, double, double>",
-                        "what": "FP64 4x4 BSR outer operator fused with the next Krylov dots",
+                        "kernel": outer_kernel_name(info),
+                        "what": "FP64 4x4 BSR outer operator fused with the next Krylov dots "
+                                "(priced at its BSR bytes whichever layout the kernel reads)",
+                        "outer_tile": info["outer_tile"], "outer_dia": info["outer_dia"],
                         "bytes_per_launch": dot_bytes, "spmv_bytes": spmv_bytes,
                         "dot_vector_bytes": 8 * N,
                         "avg_launch_us": t_in * 1e6, "launches": ev["spmv_calls"],

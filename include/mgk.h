@@ -106,9 +106,9 @@ typedef struct {
   int32_t force_tile;      /* 0: the autotuner picks each operator's kernel tile;
                               otherwise 10000*RPL + 100*S + U (S lanes per block row, U
                               blocks per step, RPL scalar rows per lane) for every
-                              operator.  RPL 2 or 4 exists for BF16 4x4 blocks only; other
-                              operators then take (S, U) if that tile exists for them, else
-                              the autotuner's tile.  An unknown tile is MGK_E_INVALID.
+                              operator.  RPL 2 or 4 exists for 4x4 blocks only (and not for
+                              transposed products); other products then take (S, U) if that
+                              tile exists for them, else the autotuner's tile.  An unknown tile is MGK_E_INVALID.
                               Results are bitwise the same for every tile. */
   int32_t coarsening;      /* mgk_coarsening, default MGK_SMOOTHED_AGGREGATION */
   int32_t schur_approx;    /* MGK_SCHUR pressure operator: 0 (default) S = C - B_lo
@@ -142,6 +142,16 @@ typedef struct {
                               blocks of that row and triangle), the largest first */
   double ilut_p;           /* ILUT fill cap factor, 0..1e6, default 2 */
   double ilut_tau;         /* ILUT drop tolerance, >= 0, default 0.01 */
+  int32_t layout;          /* 0 (default): a square 3x3 / 4x4 operator whose blocks lie on at
+                              most 8 block diagonals, padded by at most 15%, is also stored in
+                              a diagonal layout (values only, columns implied by the diagonal
+                              offsets) that the forward products read instead of the BSR
+                              arrays (the outer operator and the matching hierarchy levels of
+                              a structured grid); 1: BSR only; 2: the diagonal layout for
+                              every such operator whatever its padding.  Results agree to
+                              rounding (bit for bit when every block row holds either all the
+                              operator's block diagonals or only its diagonal block). */
+  int32_t reserved;
 } mgk_params;
 
 typedef struct {
@@ -159,14 +169,16 @@ typedef struct {
   double precond_ms;       /* with time_spmv bit 2: summed duration of the preconditioner
                               applications */
   int32_t precond_calls;   /* ... and their number */
-  int32_t reserved;
+  int32_t outer_dia;       /* block diagonals of the outer operator's diagonal layout
+                              (0: read as BSR) */
 } mgk_info;
 
 typedef struct {
   int32_t n_brows, block;  /* rows of A_l in blocks, block size */
   int64_t nnzb;            /* stored blocks of A_l */
   int32_t n_agg;           /* block columns of P_l (0 on the coarsest level) */
-  int32_t pad;
+  int32_t dia;             /* block diagonals of A_l's diagonal layout on the device (0: BSR
+                              only, or a host-only setup) */
   int64_t p_nnzb, r_nnzb;  /* stored blocks of P_l and R_l */
   double omega;            /* prolongator damping used to build P_l */
 } mgk_level_desc;

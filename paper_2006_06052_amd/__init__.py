@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("schur_spai0", C.c_int32), ("schur_lower", C.c_int32), ("idr_s", C.c_int32),
                 ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32), ("ilu_smoother", C.c_int32),
                 ("schur_scalar_u", C.c_int32), ("ilu_kind", C.c_int32),
-                ("ilut_p", C.c_double), ("ilut_tau", C.c_double)]
+                ("ilut_p", C.c_double), ("ilut_tau", C.c_double), ("layout", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -55,7 +56,7 @@ class Info(C.Structure):
                 ("solve_ms", C.c_double), ("device_bytes", C.c_int64),
                 ("spmv_ms", C.c_double), ("spmv_calls", C.c_int32), ("outer_tile", C.c_int32),
                 ("precond_ms", C.c_double), ("precond_calls", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("outer_dia", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,7 +64,7 @@ class Info(C.Structure):
 
 class LevelDesc(C.Structure):
     _fields_ = [("n_brows", C.c_int32), ("block", C.c_int32), ("nnzb", C.c_int64),
-                ("n_agg", C.c_int32), ("pad", C.c_int32), ("p_nnzb", C.c_int64),
+                ("n_agg", C.c_int32), ("dia", C.c_int32), ("p_nnzb", C.c_int64),
                 ("r_nnzb", C.c_int64), ("omega", C.c_double)]
 
 
@@ -301,7 +302,7 @@ class Solver:
         rc = lib().mgk_level_info(self._h, hier, level, C.byref(d))
         if rc:
             _err(rc)
-        return {k: getattr(d, k) for k, _ in d._fields_ if k != "pad"}
+        return {k: getattr(d, k) for k, _ in d._fields_}
 
     def ilu_export(self):
         """Host FP64 block ILU factors: (L, U) as (rowptr, col, val[nnzb, b, b]) and Dinv."""

@@ -360,9 +360,12 @@ static void batch_setup_impl(mgk_solver* S, int nsys, const mgk_bsr* const* A, i
   S->kind = kind;
   S->b = block_size;
   S->dev.stream = (hipStream_t)stream;
+  // the grouped kernels read the BSR arrays only: no diagonal-layout copies
+  mgk_params sub_prm = *prm;
+  sub_prm.layout = 1;
   for (int s = 0; s < nsys; ++s) {
     mgk_solver* sub = nullptr;
-    const int rc = mgk_setup(A[s], block_size, (mgk_precond_kind)kind, prm, stream, &sub);
+    const int rc = mgk_setup(A[s], block_size, (mgk_precond_kind)kind, &sub_prm, stream, &sub);
     if (rc) throw Error(rc, "batch: system " + std::to_string(s) + ": " + g_err);
     W->sys.push_back(sub);
     if (sub->H.lv.size() < 2)

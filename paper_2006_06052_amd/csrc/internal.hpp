@@ -109,7 +109,37 @@ struct DMat {
   double avg_row = 0.0, avg_col = 0.0;
   Tile tile, ttile;          // engine tiles for products with A and with A^T
   bool cached = false;       // values and columns read with cached loads
+  // Diagonal layout (dia.k > 0): a copy of the values as n_brows x dia.k blocks on the
+  // block diagonals dia.o, used by every product with A (not A^T) in its place.
+  void* dval = nullptr;
+  DiaOffs dia{};
 };
+
+// Block diagonals of a square operator for the diagonal layout: at most DIA_MAX distinct
+// block offsets j - i, and the padded layout at most max_pad times the stored blocks
+// (the zero blocks it adds are read like stored ones).  Returns false otherwise.
+inline bool dia_offsets(const HBsr& A, DiaOffs& of, double max_pad) {
+  of = DiaOffs{};
+  if (A.br != A.bc || A.nbr != A.nbc || A.nbr == 0) return false;
+  int k = 0;
+  for (int32_t i = 0; i < A.nbr; ++i)
+    for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
+      const int off = A.col[q] - i;
+      int p = 0;
+      while (p < k && of.o[p] < off) ++p;
+      if (p < k && of.o[p] == off) continue;
+      if (k == DIA_MAX) return false;
+      for (int t = k; t > p; --t) of.o[t] = of.o[t - 1];
+      of.o[p] = off;
+      ++k;
+    }
+  of.k = k;
+  if ((double)A.nbr * k > max_pad * (double)A.nnzb()) {
+    of = DiaOffs{};
+    return false;
+  }
+  return true;
+}
 
 // Value and column loads of the block-row kernels: the preconditioner's operators
 // (every level, prolongator and restriction, in any storage precision) are read with
@@ -130,7 +160,26 @@ inline bool operator_cached(int storage, bool outer) {
   return (mask & (storage == MGK_BF16 ? 1 : storage == MGK_F32 ? 2 : 4)) != 0;
 }
 
-inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index) {
+// Values in storage precision (FP64, FP32, or BF16 rounded through FP32).
+inline void* upload_values(Device& D, const std::vector<double>& val, int storage) {
+  const size_t nv = val.size();
+  if (storage == MGK_F64) return D.upload(val.data(), nv);
+  if (storage == MGK_F32) {
+    std::vector<float> v(nv);
+    for (size_t i = 0; i < nv; ++i) v[i] = (float)val[i];
+    void* d = D.upload(v.data(), nv);
+    HIPCK(hipStreamSynchronize(D.stream));
+    return d;
+  }
+  std::vector<uint16_t> v(nv);
+  for (size_t i = 0; i < nv; ++i) v[i] = f32_to_bf16((float)val[i]);
+  void* d = D.upload(v.data(), nv);
+  HIPCK(hipStreamSynchronize(D.stream));
+  return d;
+}
+
+inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_index,
+                       int dia_mode = 0) {
   DMat M;
   M.br = A.br;
   M.bc = A.bc;
@@ -154,6 +203,20 @@ inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_ind
   }
   M.cached = operator_cached(storage, false);
   M.avg_row = A.nbr ? (double)M.nnzb / A.nbr : 0.0;
+  DiaOffs of;
+  if (dia_mode && (A.br == 3 || A.br == 4) &&
+      dia_offsets(A, of, dia_mode == 1 ? 1.15 : 1e300)) {
+    const int bb = A.br * A.bc;
+    std::vector<double> dv((size_t)A.nbr * of.k * bb, 0.0);
+    for (int32_t i = 0; i < A.nbr; ++i)
+      for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
+        int d = 0;
+        while (of.o[d] != A.col[q] - i) ++d;
+        std::copy(A.blk(q), A.blk(q) + bb, dv.begin() + ((size_t)i * of.k + d) * bb);
+      }
+    M.dval = upload_values(D, dv, storage);
+    M.dia = of;
+  }
   if (transpose_index) {
     std::vector<int> tp(A.nbc + 1, 0), tr(M.nnzb), tb(M.nnzb);
     for (int64_t k = 0; k < M.nnzb; ++k) tp[A.col[k] + 1]++;
@@ -191,16 +254,24 @@ using AccOf = typename std::conditional<std::is_same<TV, double>::value, double,
 #define MGK_TILES_B(CASE) \
   CASE(1, 4) CASE(1, 8) CASE(2, 2) CASE(2, 4) CASE(2, 8) CASE(4, 2) CASE(4, 4) CASE(8, 4) CASE(16, 2)
 #define MGK_TILES_1(CASE) CASE(1, 8) CASE(2, 4) CASE(4, 4) CASE(8, 4) CASE(16, 2) CASE(32, 2)
-// Wide-lane tiles (S, U, RPL) for BF16 4x4 blocks: a lane owns RPL adjacent rows
-// of a block and reads them with 16-byte loads (a single BF16 block row is 8 bytes).
+// Wide-lane tiles (S, U, RPL) for 4x4 blocks: a lane owns RPL adjacent rows of a
+// block, reads them with 16-byte loads and gathers the block's x entries once for
+// all of them (a BF16 block row is only 8 bytes; for FP32 and FP64 the point is the
+// x gather, shared by fewer lanes).
 #define MGK_TILES_W(CASE) \
   CASE(2, 4, 2) CASE(4, 2, 2) CASE(4, 4, 2) CASE(8, 2, 2) CASE(16, 2, 2) CASE(4, 2, 4) \
   CASE(8, 1, 4) CASE(16, 1, 4)
 
-// Products that may use the wide-lane tiles.
+// Products that may read the diagonal layout (square 3x3 and 4x4 blocks).
+template <int BR, int BC>
+constexpr bool dia_ok() {
+  return BR == BC && (BR == 3 || BR == 4);
+}
+
+// Products that may use the wide-lane tiles (square 4x4 blocks in any storage).
 template <int BR, int BC, class TV>
 constexpr bool wide_ok() {
-  return BR == 4 && BC == 4 && sizeof(TV) == 2;
+  return BR == 4 && BC == 4;
 }
 
 template <int BR, class F>
@@ -256,24 +327,37 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, 
       constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
       const int g = nwg_rows<BR, S_>(nrows);
       k_spmv<BR, BC, S_, U_, true, TV, TX, TY, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
-                                                                     (TA)alpha, (TA)beta);
+                                                                     (TA)alpha, (TA)beta,
+                                                                     DiaOffs{});
     });
     return;
   }
   tile_switch_r<BR, wide_ok<BR, BC, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
     const int g = nwg_rows<BR, S_, R_>(nrows);
+    if constexpr (dia_ok<BR, BC>()) {
+      if (M.dia.k) {
+        const TV* dv = (const TV*)M.dval;
+        if (M.cached)
+          k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_, true, true><<<g, WG, 0, st>>>(
+              nrows, p, c, b, dv, x, y, (TA)alpha, (TA)beta, M.dia);
+        else
+          k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_, false, true><<<g, WG, 0, st>>>(
+              nrows, p, c, b, dv, x, y, (TA)alpha, (TA)beta, M.dia);
+        return;
+      }
+    }
     if (M.cached)
       k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_, true><<<g, WG, 0, st>>>(
-          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta);
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, DiaOffs{});
     else
-      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v, x, y,
-                                                                          (TA)alpha, (TA)beta);
+      k_spmv<BR, BC, S_, U_, false, TV, TX, TY, TA, R_><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, x, y, (TA)alpha, (TA)beta, DiaOffs{});
   });
 }
 
 // y = A x (FP64) with the fused partials of <w1, y> and, when two, <y, y>;
-// returns the number of partials written per dot.
+// returns the number of partials written per dot (one per group of dot_rows block rows).
 template <int BR, int BC>
 static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile,
                       const double* x, double* y, int two, const double* w1, double* part) {
@@ -282,20 +366,41 @@ static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& til
   const int* c = trans ? M.trow : M.col;
   const int* b = trans ? M.tblk : nullptr;
   const double* v = (const double*)M.val;
-  const int g = std::max(1, (nrows + dot_rows<BR>() - 1) / dot_rows<BR>());
-  tile_switch<BR>(tile, [&](auto SS, auto UU) {
-    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
-    if (trans)
+  if (trans) {
+    tile_switch<BR>(tile, [&](auto SS, auto UU) {
+      constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
+      constexpr int WR = dot_wg_rows<BR, S_, 1>();
+      const int g = std::max(1, (nrows + WR - 1) / WR);
       k_spmv_dot<BR, BC, S_, U_, true, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
-                                                                         y, two, w1, part);
-    else if (M.cached)
-      k_spmv_dot<BR, BC, S_, U_, false, double, double, true><<<g, WG, 0, st>>>(
-          nrows, p, c, b, v, x, y, two, w1, part);
-    else
-      k_spmv_dot<BR, BC, S_, U_, false, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
-                                                                          y, two, w1, part);
-  });
-  return g;
+                                                                         y, two, w1, part,
+                                                                         DiaOffs{});
+    });
+  } else {
+    tile_switch_r<BR, wide_ok<BR, BC, double>()>(tile, [&](auto SS, auto UU, auto RR) {
+      constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
+      constexpr int WR = dot_wg_rows<BR, S_, R_>();
+      const int g = std::max(1, (nrows + WR - 1) / WR);
+      if constexpr (dia_ok<BR, BC>()) {
+        if (M.dia.k) {
+          const double* dv = (const double*)M.dval;
+          if (M.cached)
+            k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, true, true><<<g, WG, 0, st>>>(
+                nrows, p, c, b, dv, x, y, two, w1, part, M.dia);
+          else
+            k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, false, true><<<g, WG, 0, st>>>(
+                nrows, p, c, b, dv, x, y, two, w1, part, M.dia);
+          return;
+        }
+      }
+      if (M.cached)
+        k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, true><<<g, WG, 0, st>>>(
+            nrows, p, c, b, v, x, y, two, w1, part, DiaOffs{});
+      else
+        k_spmv_dot<BR, BC, S_, U_, false, double, double, R_><<<g, WG, 0, st>>>(
+            nrows, p, c, b, v, x, y, two, w1, part, DiaOffs{});
+    });
+  }
+  return std::max(1, (nrows + dot_rows<BR>() - 1) / dot_rows<BR>());
 }
 
 template <int BR, int BC, class TV, class TX, class TF>
@@ -312,19 +417,31 @@ static void residual_s(hipStream_t st, const DMat& M, bool trans, const Tile& ti
       constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
       const int g = nwg_rows<BR, S_>(nrows);
       k_residual<BR, BC, S_, U_, true, TV, TX, TF, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, f,
-                                                                          z, t);
+                                                                          z, t, DiaOffs{});
     });
     return;
   }
   tile_switch_r<BR, wide_ok<BR, BC, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
     const int g = nwg_rows<BR, S_, R_>(nrows);
+    if constexpr (dia_ok<BR, BC>()) {
+      if (M.dia.k) {
+        const TV* dv = (const TV*)M.dval;
+        if (M.cached)
+          k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_, true, true><<<g, WG, 0, st>>>(
+              nrows, p, c, b, dv, f, z, t, M.dia);
+        else
+          k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_, false, true><<<g, WG, 0, st>>>(
+              nrows, p, c, b, dv, f, z, t, M.dia);
+        return;
+      }
+    }
     if (M.cached)
       k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_, true><<<g, WG, 0, st>>>(
-          nrows, p, c, b, v, f, z, t);
+          nrows, p, c, b, v, f, z, t, DiaOffs{});
     else
-      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
-                                                                               f, z, t);
+      k_residual<BR, BC, S_, U_, false, TV, TX, TF, TA, R_><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, f, z, t, DiaOffs{});
   });
 }
 
@@ -342,19 +459,32 @@ static void smooth_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile
       constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
       const int g = nwg_rows<B, S_>(nrows);
       k_smooth<B, S_, U_, true, TV, TX, TF, TO, TM, TA><<<g, WG, 0, st>>>(nrows, p, c, b, v, Mb,
-                                                                           f, z, zout);
+                                                                           f, z, zout,
+                                                                           DiaOffs{});
     });
     return;
   }
   tile_switch_r<B, wide_ok<B, B, TV>()>(tile, [&](auto SS, auto UU, auto RR) {
     constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
     const int g = nwg_rows<B, S_, R_>(nrows);
+    if constexpr (dia_ok<B, B>()) {
+      if (M.dia.k) {
+        const TV* dv = (const TV*)M.dval;
+        if (M.cached)
+          k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_, true, true><<<g, WG, 0, st>>>(
+              nrows, p, c, b, dv, Mb, f, z, zout, M.dia);
+        else
+          k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_, false, true><<<g, WG, 0, st>>>(
+              nrows, p, c, b, dv, Mb, f, z, zout, M.dia);
+        return;
+      }
+    }
     if (M.cached)
       k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_, true><<<g, WG, 0, st>>>(
-          nrows, p, c, b, v, Mb, f, z, zout);
+          nrows, p, c, b, v, Mb, f, z, zout, DiaOffs{});
     else
-      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_><<<g, WG, 0, st>>>(nrows, p, c, b, v,
-                                                                                Mb, f, z, zout);
+      k_smooth<B, S_, U_, false, TV, TX, TF, TO, TM, TA, R_><<<g, WG, 0, st>>>(
+          nrows, p, c, b, v, Mb, f, z, zout, DiaOffs{});
   });
 }
 

@@ -68,13 +68,20 @@ __device__ __forceinline__ T ld_val(const T* p) {
 // block rows for the wide BF16 lanes).
 template <int BC, class TV, class TA, bool CACHED = false>
 __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
-  if constexpr (sizeof(TV) == 8 && BC == 4) {
-    const d2v a = ld_val<CACHED>(reinterpret_cast<const d2v*>(p));
-    const d2v b = ld_val<CACHED>(reinterpret_cast<const d2v*>(p) + 1);
-    out[0] = a.x; out[1] = a.y; out[2] = b.x; out[3] = b.y;
-  } else if constexpr (sizeof(TV) == 4 && BC == 4) {
-    const f4v a = ld_val<CACHED>(reinterpret_cast<const f4v*>(p));
-    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  if constexpr (sizeof(TV) == 8 && BC % 2 == 0) {
+    // 16-byte loads of two values each (one block row is two of them)
+#pragma unroll
+    for (int q = 0; q < BC / 2; ++q) {
+      const d2v a = ld_val<CACHED>(reinterpret_cast<const d2v*>(p) + q);
+      out[2 * q] = a.x;
+      out[2 * q + 1] = a.y;
+    }
+  } else if constexpr (sizeof(TV) == 4 && BC % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < BC / 4; ++q) {
+      const f4v a = ld_val<CACHED>(reinterpret_cast<const f4v*>(p) + q);
+      out[4 * q] = a.x; out[4 * q + 1] = a.y; out[4 * q + 2] = a.z; out[4 * q + 3] = a.w;
+    }
   } else if constexpr (sizeof(TV) == 2 && BC % 8 == 0) {
     // several consecutive block rows: 16-byte loads of eight values each
 #pragma unroll
@@ -172,6 +179,25 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
   return L;
 }
 
+// Diagonal layout of a square block operator whose blocks lie on at most DIA_MAX block
+// diagonals: block row i stores DIA_MAX' = k blocks, slot d holding A(i, i + o[d]) (o
+// ascending, so a full row's slots are its stored blocks in ascending column order); an
+// absent block is a zero block, its column clamped into range.  No row pointers and no
+// column indices are read: the x gather no longer waits for them.
+constexpr int DIA_MAX = 8;
+struct DiaOffs {
+  int k;
+  int o[DIA_MAX];
+};
+
+__device__ __forceinline__ int dia_col(const DiaOffs& of, int i, int d, int n) {
+  int off = of.o[0];
+#pragma unroll
+  for (int q = 1; q < DIA_MAX; ++q) off = d == q ? of.o[q] : off;   // no dynamic indexing
+  const int c = i + off;
+  return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
 // Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
 // (BR/RPL)*S lanes.
 //
@@ -189,13 +215,14 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
 // block).  When T > U the stripe accumulators rotate by U after each step so
 // that block u of a step always lands in accumulator u.
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA, int RPL,
-          bool CACHED = false>
+          bool CACHED = false, bool DIA = false>
 __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
                                               const int* __restrict__ ptr,
                                               const int* __restrict__ col,
                                               const int* __restrict__ blk,
                                               const TV* __restrict__ val,
-                                              const TX* __restrict__ x, TA (&out)[RPL]) {
+                                              const TX* __restrict__ x, TA (&out)[RPL],
+                                              const DiaOffs& of = DiaOffs{}) {
   constexpr int NS = BR == 1 ? 32 : 16;
   constexpr int T = NS / S;
   constexpr int LB = BR / RPL;
@@ -207,7 +234,8 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[q][t] = 0;
   if (L.active && L.i < nbr) {
-    const int k0 = ptr[L.i], k1 = ptr[L.i + 1];
+    // diagonal layout: the row's blocks are slots i*k .. i*k + k - 1, columns implied
+    const int k0 = DIA ? L.i * of.k : ptr[L.i], k1 = DIA ? k0 + of.k : ptr[L.i + 1];
     int steps = 0;
     for (int kb = k0 + L.s; kb < k1; kb += S * U, ++steps) {
       int j[U], kk[U];
@@ -216,7 +244,8 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
       for (int u = 0; u < U; ++u) {
         const int k = kb + u * S;
         ok[u] = k < k1;
-        j[u] = ok[u] ? ld_val<CACHED>(col + k) : 0;
+        if constexpr (DIA) j[u] = ok[u] ? dia_col(of, L.i, k - k0, nbr) : 0;
+        else j[u] = ok[u] ? ld_val<CACHED>(col + k) : 0;
         kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
       }
       TA v[U][RPL * BC], xv[U][BC];
@@ -325,13 +354,13 @@ __device__ __forceinline__ void wg_sum2(T& a, T& b) {
 
 // y = alpha A x + beta y   (beta == 0: y is not read).
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TY, class TA,
-          int RPL = 1, bool CACHED = false>
+          int RPL = 1, bool CACHED = false, bool DIA = false>
 __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ ptr,
                                              const int* __restrict__ col,
                                              const int* __restrict__ blk,
                                              const TV* __restrict__ val,
                                              const TX* __restrict__ x, TY* __restrict__ y,
-                                             TA alpha, TA beta) {
+                                             TA alpha, TA beta, DiaOffs of) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
@@ -341,8 +370,8 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
 #pragma unroll
   for (int q = 0; q < RPL; ++q) yv[q] = (own && beta != TA(0)) ? (TA)y[row0 + q] : TA(0);
   TA acc[RPL];
-  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, blk, val, x,
-                                                               acc);
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
+                                                                    x, acc, of);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -354,18 +383,28 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
 }
 
 // y = A x fused with the partial dot products <w1, y> and (two) <y, y> of the
-// Krylov iteration (FP64 outer operator).  Every workgroup owns the same
-// DOT_ROWS block rows whatever the tile: the per-row products are staged in LDS
-// by scalar row and summed by one fixed tree, so the partials (and the whole
-// solve) do not depend on the tile.  16 block rows are one pass of the
-// four-lane split (S = 4) tile that suits short 3x3 / 4x4 block rows; scalar
-// rows use 64.
+// Krylov iteration (FP64 outer operator).  The partials have a fixed partition
+// whatever the tile: one per group of DOT_ROWS consecutive block rows, summed over
+// the group's scalar rows staged in LDS by one fixed tree, so the partials (and the
+// whole solve) do not depend on the tile.  A workgroup covers max(DOT_ROWS, rows per
+// pass of its tile) block rows, i.e. one or several groups, and writes one partial per
+// group.  16 block rows are one pass of the four-lane split (S = 4) tile that suits
+// short 3x3 / 4x4 block rows; scalar rows use 64.
 template <int BR>
 constexpr int dot_rows() {
   return BR == 1 ? 64 : 16;
 }
 
-template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, bool CACHED = false>
+// Block rows per workgroup of the fused kernel for a tile: whole groups covering at
+// least one pass of the tile.
+template <int BR, int S, int RPL>
+constexpr int dot_wg_rows() {
+  constexpr int D = dot_rows<BR>(), R = RowMap<BR, S, RPL>::ROWS;
+  return D * ((R + D - 1) / D);
+}
+
+template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, int RPL = 1,
+          bool CACHED = false, bool DIA = false>
 __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const int* __restrict__ blk,
@@ -373,64 +412,80 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
                                                  const TX* __restrict__ x,
                                                  double* __restrict__ y, int two,
                                                  const double* __restrict__ w1,
-                                                 double* __restrict__ part) {
-  using M = RowMap<BR, S>;
+                                                 double* __restrict__ part, DiaOffs of) {
+  using M = RowMap<BR, S, RPL>;
   constexpr int DOT_ROWS = dot_rows<BR>();
-  constexpr int NR = DOT_ROWS * BR < 128 ? 64 : (DOT_ROWS * BR <= 128 ? 128 : 256);
-  static_assert(DOT_ROWS * BR <= NR, "dot staging");
-  __shared__ double sd1[NR], sd2[NR];
-  for (int t = threadIdx.x; t < NR; t += WG) {
+  constexpr int WROWS = dot_wg_rows<BR, S, RPL>();   // block rows of the workgroup
+  constexpr int NG = WROWS / DOT_ROWS;                // partial groups of the workgroup
+  constexpr int GR = DOT_ROWS * BR;                   // scalar rows of a group
+  constexpr int NR = GR < 64 ? 64 : (GR <= 128 ? 128 : 256);   // slots per group
+  static_assert(WROWS % DOT_ROWS == 0 && GR <= NR, "dot staging");
+  __shared__ double sd1[NG * NR], sd2[NG * NR];
+  for (int t = threadIdx.x; t < NG * NR; t += WG) {
     sd1[t] = 0.0;
     sd2[t] = 0.0;
   }
   __syncthreads();
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const int rb0 = lw * DOT_ROWS, rb1 = min(nbr, rb0 + DOT_ROWS);
+  const int rb0 = lw * WROWS, rb1 = min(nbr, rb0 + WROWS);
   const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x >> 6;
   for (int base = rb0; base < rb1; base += M::ROWS) {
     LaneInfo L;
     const int g = lane / M::G, w = lane - g * M::G;
     L.active = g < M::GPW;
-    L.s = w / BR;
-    L.r = w - L.s * BR;
+    L.s = w / M::LB;
+    L.r = (w - L.s * M::LB) * RPL;
     L.gbase = g * M::G;
     L.i = base + wave * M::GPW + g;
     const int lim = L.i < rb1 ? nbr : 0;   // rows past this workgroup's range idle
     const bool own = L.active && L.s == 0 && L.i < rb1;
     const size_t row = (size_t)L.i * BR + L.r;
-    const double wv = own ? __builtin_nontemporal_load(w1 + row) : 0.0;   // ahead of the product
-    const double acc = row_product<BR, BC, S, U, TRANS, TV, TX, double, CACHED>(L, lim, ptr, col,
-                                                                                blk, val, x);
+    double wv[RPL];   // ahead of the product
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) wv[q] = own ? __builtin_nontemporal_load(w1 + row + q) : 0.0;
+    double acc[RPL];
+    row_product_r<BR, BC, S, U, TRANS, TV, TX, double, RPL, CACHED, DIA>(L, lim, ptr, col, blk,
+                                                                          val, x, acc, of);
     if (own) {
-      __builtin_nontemporal_store(acc, y + row);
-      const int q = (L.i - rb0) * BR + L.r;
-      sd1[q] = wv * acc;
-      sd2[q] = acc * acc;
+      const int rl = L.i - rb0;
+      const int q0 = (rl / DOT_ROWS) * NR + (rl % DOT_ROWS) * BR + L.r;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        __builtin_nontemporal_store(acc[q], y + row + q);
+        sd1[q0 + q] = wv[q] * acc[q];
+        sd2[q0 + q] = acc[q] * acc[q];
+      }
     }
   }
   __syncthreads();
-  for (int h = NR / 2; h >= 1; h >>= 1) {   // NR is a power of two
-    for (int t = threadIdx.x; t < h; t += WG) {
-      sd1[t] += sd1[t + h];
-      sd2[t] += sd2[t + h];
+  for (int h = NR / 2; h >= 1; h >>= 1) {   // NR is a power of two; every group alike
+    for (int t = threadIdx.x; t < NG * h; t += WG) {
+      const int q = (t / h) * NR + t % h;
+      sd1[q] += sd1[q + h];
+      sd2[q] += sd2[q + h];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    part[lw] = sd1[0];
-    if (two) part[gridDim.x + lw] = sd2[0];
+  const int ngroups = (nbr + DOT_ROWS - 1) / DOT_ROWS;
+  if (threadIdx.x < NG) {
+    const int gi = lw * NG + threadIdx.x;
+    if (gi < ngroups) {
+      part[gi] = sd1[threadIdx.x * NR];
+      if (two) part[ngroups + gi] = sd2[threadIdx.x * NR];
+    }
   }
 }
 
 // t = f - A z  (A may be rectangular: BR x BC blocks).
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TF, class TA,
-          int RPL = 1, bool CACHED = false>
+          int RPL = 1, bool CACHED = false, bool DIA = false>
 __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const int* __restrict__ blk,
                                                  const TV* __restrict__ val,
                                                  const TF* __restrict__ f,
-                                                 const TX* __restrict__ z, TX* __restrict__ t) {
+                                                 const TX* __restrict__ z, TX* __restrict__ t,
+                                                 DiaOffs of) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
@@ -439,8 +494,8 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
 #pragma unroll
   for (int q = 0; q < RPL; ++q) fv[q] = own ? (TA)f[row0 + q] : TA(0);
   TA acc[RPL];
-  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, blk, val, z,
-                                                               acc);
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
+                                                                    z, acc, of);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)(fv[q] - acc[q]);
@@ -449,14 +504,15 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
 
 // Post-smoothing: zout = z + M (f - A z), M block diagonal (M^T when TRANS).
 template <int BR, int S, int U, bool TRANS, class TV, class TX, class TF, class TO, class TM,
-          class TA, int RPL = 1, bool CACHED = false>
+          class TA, int RPL = 1, bool CACHED = false, bool DIA = false>
 static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __restrict__ ptr,
                                                const int* __restrict__ col,
                                                const int* __restrict__ blk,
                                                const TV* __restrict__ val,
                                                const TM* __restrict__ M,
                                                const TF* __restrict__ f,
-                                               const TX* __restrict__ z, TO* __restrict__ zout) {
+                                               const TX* __restrict__ z, TO* __restrict__ zout,
+                                               DiaOffs of) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
@@ -473,8 +529,8 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
     for (int c = 0; c < BR; ++c) mv[q][c] = own ? (TA)(TRANS ? m[c * BR + r] : m[r * BR + c]) : TA(0);
   }
   TA acc[RPL];
-  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, blk, val, z,
-                                                               acc);
+  row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
+                                                                    z, acc, of);
   TA res[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) res[q] = own ? fv[q] - acc[q] : TA(0);

@@ -94,8 +94,8 @@ static Tile autotune(Device& D, const DMat& M, bool trans) {
   const int nrows = trans ? M.nbc : M.nbr, ncols = trans ? M.nbr : M.nbc;
   if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4, 1} : Tile{1, 4, 1};
   char key[200];
-  snprintf(key, sizeof key, "b%dx%d_v%d_x%d_t%d_r%d_nnz%lld", BR, BC, (int)sizeof(TV),
-           (int)sizeof(TX), (int)trans, nrows, (long long)M.nnzb);
+  snprintf(key, sizeof key, "b%dx%d_v%d_x%d_t%d_r%d_nnz%lld_dia%d", BR, BC, (int)sizeof(TV),
+           (int)sizeof(TX), (int)trans, nrows, (long long)M.nnzb, trans ? 0 : M.dia.k);
   TuneCache& C = TuneCache::get();
   {
     std::lock_guard<std::mutex> g(C.mu);
@@ -181,7 +181,7 @@ static void fill_desc(const HHierarchy& H, std::vector<mgk_level_desc>& desc) {
     ds.block = H.b;
     ds.nnzb = h.A.nnzb();
     ds.n_agg = h.n_agg;
-    ds.pad = 0;
+    ds.dia = 0;
     ds.p_nnzb = h.P.nnzb();
     ds.r_nnzb = h.R.nnzb();
     ds.omega = h.omega;
@@ -191,7 +191,7 @@ static void fill_desc(const HHierarchy& H, std::vector<mgk_level_desc>& desc) {
 static void describe(DHier& H) { fill_desc(H.host, H.desc); }
 
 static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_transpose,
-                             DHier& out, const DMat* share_level0) {
+                             DHier& out, const DMat* share_level0, int dia_mode) {
   out.b = H.b;
   out.storage = storage;
   out.trans_ready = with_transpose;
@@ -208,7 +208,7 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
     if (l == 0 && share_level0 && storage == MGK_F64 && (!with_transpose || share_level0->tptr))
       d.A = *share_level0;
     else if (!last)
-      d.A = upload_mat(D, h.A, storage, with_transpose);
+      d.A = upload_mat(D, h.A, storage, with_transpose, dia_mode);
     if (!last) {
       d.P = upload_mat(D, h.P, storage, false);
       d.R = upload_mat(D, h.R, storage, false);
@@ -246,6 +246,7 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
     out.sz = D.alloc(n0 * xs);
   }
   fill_desc(H, out.desc);
+  for (int l = 0; l < L; ++l) out.desc[l].dia = out.lv[l].A.dia.k;
   out.nc = H.nc;
   out.cinv = D.upload(H.coarse_inv.data(), H.coarse_inv.size());
   if (with_transpose) {
@@ -668,6 +669,9 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     throw Error(MGK_E_INVALID, "ilu_sweeps must be in 0..64");
   if (prm->ilu_smoother & ~1) throw Error(MGK_E_INVALID, "ilu_smoother is 0 or 1");
   if (prm->ilu_kind & ~1) throw Error(MGK_E_INVALID, "ilu_kind is 0 (ILU(k)) or 1 (ILUT)");
+  if (prm->layout < 0 || prm->layout > 2)
+    throw Error(MGK_E_INVALID, "layout is 0 (automatic), 1 (BSR only) or 2 (diagonal layout "
+                               "whatever the padding)");
   if (prm->ilu_kind == 1 && !(prm->ilut_p >= 0.0 && prm->ilut_p <= 1e6 && prm->ilut_tau >= 0.0 &&
                               std::isfinite(prm->ilut_tau)))
     throw Error(MGK_E_INVALID, "ILUT needs 0 <= ilut_p <= 1e6 and finite ilut_tau >= 0");
@@ -736,7 +740,9 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return;
   }
-  S->A = upload_mat(S->dev, H, MGK_F64, tr);
+  // diagonal layout: 1 with the padding limit, 2 whatever the padding, 0 never
+  const int dia = prm->layout == 0 ? 1 : prm->layout == 2 ? 2 : 0;
+  S->A = upload_mat(S->dev, H, MGK_F64, tr, dia);
   S->A.cached = operator_cached(MGK_F64, true);
   tune_mat(S->dev, S->A, MGK_F64, tr);
   const SetupParams sp = setup_params(*prm, kind);
@@ -772,7 +778,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
     if (prm->schur_scalar_u) parts.Auu = scalar_form(parts.Auu);
     HHierarchy hu, hp;
     if ((rc = build_hierarchy(parts.Auu, sp, hu, err))) throw Error(rc, err);
-    upload_hierarchy(S->dev, hu, prm->hier, false, S->H, nullptr);
+    upload_hierarchy(S->dev, hu, prm->hier, false, S->H, nullptr, dia);
     S->H.ilu_sweeps = prm->ilu_sweeps;
     if (prm->schur_spai0) {
       std::vector<double> m;
@@ -786,7 +792,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
       HIPCK(hipStreamSynchronize(S->dev.stream));
     } else {
       if ((rc = build_hierarchy(parts.S, sp, hp, err))) throw Error(rc, err);
-      upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr);
+      upload_hierarchy(S->dev, hp, prm->hier, false, S->Hp, nullptr, dia);
       S->Hp.ilu_sweeps = prm->ilu_sweeps;
     }
     S->Blo = upload_mat(S->dev, parts.Blo, prm->hier, false);
@@ -808,7 +814,7 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   } else {
     HHierarchy hh;
     if ((rc = build_hierarchy(H, sp, hh, err))) throw Error(rc, err);
-    upload_hierarchy(S->dev, hh, prm->hier, tr, S->H, &S->A);
+    upload_hierarchy(S->dev, hh, prm->hier, tr, S->H, &S->A, dia);
     S->H.ilu_sweeps = prm->ilu_sweeps;
     if (prm->keep_host) {
       S->H.host = std::move(hh);
@@ -971,6 +977,7 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     info->precond_calls = (int32_t)(s->pev_used / 2);
     const mgk::Tile& ot = s->A.tile;
     info->outer_tile = 10000 * ot.rpl + 100 * ot.s + ot.u;
+    info->outer_dia = s->A.dia.k;
     return rc;
   });
 }

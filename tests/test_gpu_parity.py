@@ -298,7 +298,7 @@ def test_edge_cases():
         s2.solve(bx.float(), x, 1e-8)
 
 
-@pytest.mark.parametrize("storage", ["f64", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_results_independent_of_kernel_tile(storage):
     """Every engine tile sums in the same fixed order, so SpMV and whole solves are bitwise
     identical whatever tile the autotuner (or force_tile) selects."""
@@ -307,7 +307,8 @@ def test_results_independent_of_kernel_tile(storage):
     b = dev(S.mms_rhs(n))
     x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
     outs = []
-    # 10000*RPL + 100*S + U; the RPL 2 / 4 tiles are the wide BF16 lanes
+    # 10000*RPL + 100*S + U; the RPL 2 / 4 tiles are the wide lanes of 4x4 blocks (every
+    # storage, the FP64 outer operator and its fused dots included)
     for tile in (0, 108, 202, 204, 402, 404, 804, 1602, 20204, 20402, 20404, 20802, 21602,
                  40402, 40801, 41601):
         say("tile", storage, tile)
@@ -322,9 +323,94 @@ def test_results_independent_of_kernel_tile(storage):
         assert np.array_equal(x, outs[0][1]) and it == outs[0][2]
     with pytest.raises(mgk.MgkError):
         gpu_solver(bsr, hier=storage, force_tile=303)
-    if storage == "bf16":
-        with pytest.raises(mgk.MgkError):
-            gpu_solver(bsr, hier=storage, force_tile=30402)   # no 3-row lanes of 4x4 blocks
+    with pytest.raises(mgk.MgkError):
+        gpu_solver(bsr, hier=storage, force_tile=30402)   # no 3-row lanes of 4x4 blocks
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_diagonal_layout_matches_bsr_bitwise(storage):
+    """The fine operator of the Stokes system has 7 block diagonals, so it can be read in
+    the diagonal-offset layout.  Its rows are either full (same products in the same order
+    as BSR) or a lone diagonal block (the padding adds exact +0), so SpMV, V-cycle and
+    whole solves are bitwise those of the BSR layout.  At 14^3 the Dirichlet rows pad the
+    layout by 46%, so the automatic choice keeps BSR and layout 2 forces the diagonals."""
+    n = 14
+    th, bsr, A = problem(n, 0.5, 8)
+    b = dev(S.mms_rhs(n))
+    x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
+    outs = []
+    for layout, k in ((2, 7), (1, 0), (0, 0)):
+        say("layout", storage, layout)
+        s = gpu_solver(bsr, hier=storage, coarse_enough=200, layout=layout)
+        assert s.level_info(0)["dia"] == k
+        y = torch.empty_like(b)
+        s.spmv(x0, y)
+        z = torch.empty_like(b)
+        s.precond(x0, z)
+        x = torch.zeros_like(b)
+        info = s.solve(b, x, 1e-8)
+        assert info["outer_dia"] == k
+        outs.append((y.cpu().numpy(), z.cpu().numpy(), x.cpu().numpy(), info["iters"]))
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            assert np.array_equal(a, c)
+
+
+def test_diagonal_layout_chosen_at_scale():
+    """At 40^3 the boundary rows pad the 7 diagonals by 14%: the automatic choice reads the
+    fine operator (outer and hierarchy level 0) in the diagonal layout, aggregated levels
+    in BSR."""
+    ptr, col, val = mgk.stokes_bsr(40)
+    s = gpu_solver((ptr, col, val), hier="f32", coarse_enough=2000)
+    assert s.level_info(0)["dia"] == 7
+    assert all(s.level_info(l)["dia"] == 0 for l in range(1, s.nlevels()))
+    b = torch.ones(4 * 40 ** 3, dtype=torch.float64, device=DEV)
+    x = torch.zeros_like(b)
+    info = s.solve(b, x, 1e-8)
+    assert info["outer_dia"] == 7 and info["rel_resid"] <= 1e-8
+
+
+def test_diagonal_layout_with_partial_rows():
+    """Rows with some diagonals missing are padded with zero blocks, which moves products
+    between summation stripes: SpMV stays within the FP64 bound of the oracle, and a few
+    solver iterations agree with the BSR layout to rounding."""
+    n = 12
+    th, bsr, A0 = problem(n, 0.5, 4)
+    ptr, col, val = bsr
+    rng = np.random.default_rng(5)
+    # drop about 4% of the off-diagonal blocks in mirrored pairs; 7 diagonals stay
+    nbr = ptr.size - 1
+    keep = np.ones(col.size, bool)
+    rows = np.repeat(np.arange(nbr), np.diff(ptr))
+    pos = {(int(i), int(j)): k for k, (i, j) in enumerate(zip(rows, col))}
+    for k in np.flatnonzero(rng.random(col.size) < 0.02):
+        i, j = int(rows[k]), int(col[k])
+        if i != j and (j, i) in pos:
+            keep[k] = keep[pos[(j, i)]] = False
+    nptr = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=nbr))]).astype(np.int32)
+    pbsr = (nptr, col[keep].copy(), val[keep].copy())
+    assert 0.94 * col.size < keep.sum() < 0.98 * col.size
+    import scipy.sparse as sp
+    A = sp.bsr_matrix((pbsr[2], pbsr[1], pbsr[0]), shape=A0.shape).tocsr()
+    x = np.random.default_rng(1).normal(size=A.shape[0])
+    b = dev(A @ np.ones(A.shape[0]))
+    res = []
+    for layout in (2, 1):
+        say("partial rows, layout", layout)
+        s = gpu_solver(pbsr, coarse_enough=200, layout=layout, maxiter=4)
+        assert s.level_info(0)["dia"] == (7 if layout == 2 else 0)
+        dy = torch.empty_like(b)
+        s.spmv(dev(x), dy)
+        y = dy.cpu().numpy()
+        bound = 16 * EPS * (abs(A) @ np.abs(x)) + 1e-300
+        assert np.all(np.abs(y - A @ x) <= bound)
+        z = torch.empty_like(b)
+        s.precond(dev(x), z)
+        xs = torch.zeros_like(b)
+        s.solve(b, xs, 1e-14)
+        res.append((z.cpu().numpy(), xs.cpu().numpy()))
+    for a, c in zip(res[0], res[1]):
+        assert np.linalg.norm(a - c) <= 1e-10 * np.linalg.norm(c)
 
 
 @pytest.mark.parametrize("storage", ["f64", "bf16"])
