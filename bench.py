@@ -633,6 +633,9 @@ def main():
                     default="schur64,multi64,batch8,batch32small,adjoint48,idrs96,plain96,"
                             "paper_schur64,ilu48",
                     help="other solve shapes timed after the headline (empty: none)")
+    ap.add_argument("--layout", type=int, default=0,
+                    help="operator layout of the BSR arms: 0 automatic (the fine operator in "
+                         "the diagonal-offset layout at this size), 1 BSR only")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the FP64 BSR SpMV loop")
     ap.add_argument("--counters", action="store_true",
@@ -674,7 +677,7 @@ def main():
             s.outer_bytes = spmv_bytes_of(N, int(bp[-1]), 1)
         else:
             s = mgk.Solver(ptr, col, val, 4, mgk.AMG_SPAI0, stream=stream, hier=HIER[arm],
-                           time_spmv=3)
+                           time_spmv=3, layout=args.layout)
             s.outer_bytes = spmv_bytes_of(N // 4, nnzb, 4)
         return s, time.perf_counter() - t0
 

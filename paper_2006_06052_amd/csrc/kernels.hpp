@@ -138,6 +138,22 @@ __device__ __forceinline__ void load_x(const TX* __restrict__ p, TA* out) {
   }
 }
 
+// N consecutive vector entries p[e .. e+N-1] of a lane's own rows, read ahead of its row
+// product.  Every lane issues the loads (lanes that own no rows read entries 0 .. N-1,
+// which every vector holds, all at one address), so no branch separates them from the
+// product's loads and the compiler places no wait for them before it; the caller
+// converts the raw values after the product and uses them in its owning lanes only.
+template <int N, bool NT = false, class T>
+__device__ __forceinline__ void load_ahead(const T* __restrict__ p, size_t e, bool own,
+                                           T (&raw)[N]) {
+  const T* q = p + (own ? e : 0);
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if constexpr (NT) raw[c] = __builtin_nontemporal_load(q + c);
+    else raw[c] = q[c];
+  }
+}
+
 // Logical workgroup id: XCD x (hardware places workgroup w on XCD w % 8)
 // receives one contiguous range of logical ids.
 __device__ __forceinline__ int xcd_remap(int w, int nwg) {
@@ -190,12 +206,27 @@ struct DiaOffs {
   int o[DIA_MAX];
 };
 
-__device__ __forceinline__ int dia_col(const DiaOffs& of, int i, int d, int n) {
-  int off = of.o[0];
+// Offsets of the slots L.s + m*S (m < NSLOT) that one lane of an S-way split reads.  The
+// offsets are kernel arguments; a lane-dependent index into them would be compiled into a
+// memory load from the argument segment (one dependent load, with a full wait, per
+// block), so each is first pinned to a scalar register and the lane's offsets are then
+// selected by value, once per kernel.
+template <int S, int NSLOT>
+__device__ __forceinline__ void dia_lane_offsets(const DiaOffs& of, int s, int (&out)[NSLOT]) {
+  int o[DIA_MAX];
 #pragma unroll
-  for (int q = 1; q < DIA_MAX; ++q) off = d == q ? of.o[q] : off;   // no dynamic indexing
-  const int c = i + off;
-  return c < 0 ? 0 : (c >= n ? n - 1 : c);
+  for (int q = 0; q < DIA_MAX; ++q) {
+    o[q] = of.o[q];
+    asm volatile("" : "+s"(o[q]));
+  }
+#pragma unroll
+  for (int m = 0; m < NSLOT; ++m) {
+    int v = o[m * S < DIA_MAX ? m * S : 0];
+#pragma unroll
+    for (int t = 1; t < S; ++t)
+      if (m * S + t < DIA_MAX) v = s == t ? o[m * S + t] : v;
+    out[m] = v;
+  }
 }
 
 // Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
@@ -237,15 +268,15 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
     // diagonal layout: the row's blocks are slots i*k .. i*k + k - 1, columns implied
     const int k0 = DIA ? L.i * of.k : ptr[L.i], k1 = DIA ? k0 + of.k : ptr[L.i + 1];
     int steps = 0;
-    for (int kb = k0 + L.s; kb < k1; kb += S * U, ++steps) {
+    // One step: blocks kb + u*S (u < U) of the row; colof(u, k) is block k's column.
+    auto step = [&](int kb, auto colof) {
       int j[U], kk[U];
       bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = kb + u * S;
         ok[u] = k < k1;
-        if constexpr (DIA) j[u] = ok[u] ? dia_col(of, L.i, k - k0, nbr) : 0;
-        else j[u] = ok[u] ? ld_val<CACHED>(col + k) : 0;
+        j[u] = ok[u] ? colof(u, k) : 0;
         kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
       }
       TA v[U][RPL * BC], xv[U][BC];
@@ -287,6 +318,27 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
           for (int t = 0; t < T; ++t) acc[q][t] = tmp[t];
         }
       }
+    };
+    if constexpr (DIA) {
+      // slot d = L.s + m*S of the lane holds column i + o[d] (clamped; absent blocks
+      // are zero); the steps are unrolled, so every slot's offset is a register
+      constexpr int NSLOT = (DIA_MAX + S - 1) / S, NSTEP = (NSLOT + U - 1) / U;
+      int loff[NSLOT];
+      dia_lane_offsets<S, NSLOT>(of, L.s, loff);
+#pragma unroll
+      for (int st = 0; st < NSTEP; ++st) {
+        const int kb = k0 + L.s + st * S * U;
+        if (kb >= k1) break;
+        step(kb, [&](int u, int) {
+          const int m = st * U + u;
+          const int c = L.i + loff[m < NSLOT ? m : 0];
+          return c < 0 ? 0 : (c >= nbr ? nbr - 1 : c);
+        });
+        ++steps;
+      }
+    } else {
+      for (int kb = k0 + L.s; kb < k1; kb += S * U, ++steps)
+        step(kb, [&](int, int k) { return ld_val<CACHED>(col + k); });
     }
     if constexpr (T > U) {
       // undo the rotations: acc[.][t] now holds stripe (t + steps*U) mod T
@@ -366,9 +418,8 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
   // epilogue operands are loaded before the row product so their latency overlaps it
-  TA yv[RPL];
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) yv[q] = (own && beta != TA(0)) ? (TA)y[row0 + q] : TA(0);
+  TY yr[RPL];
+  if (beta != TA(0)) load_ahead<RPL>(y, row0, own, yr);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
                                                                     x, acc, of);
@@ -376,7 +427,7 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       TA out = alpha * acc[q];
-      if (beta != TA(0)) out += beta * yv[q];
+      if (beta != TA(0)) out += beta * (TA)yr[q];
       y[row0 + q] = (TY)out;
     }
   }
@@ -441,8 +492,7 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
     const bool own = L.active && L.s == 0 && L.i < rb1;
     const size_t row = (size_t)L.i * BR + L.r;
     double wv[RPL];   // ahead of the product
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) wv[q] = own ? __builtin_nontemporal_load(w1 + row + q) : 0.0;
+    load_ahead<RPL, true>(w1, row, own, wv);
     double acc[RPL];
     row_product_r<BR, BC, S, U, TRANS, TV, TX, double, RPL, CACHED, DIA>(L, lim, ptr, col, blk,
                                                                           val, x, acc, of);
@@ -490,15 +540,14 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
-  TA fv[RPL];   // loaded ahead of the row product
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) fv[q] = own ? (TA)f[row0 + q] : TA(0);
+  TF fr[RPL];   // loaded ahead of the row product
+  load_ahead<RPL>(f, row0, own, fr);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
                                                                     z, acc, of);
   if (own) {
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)(fv[q] - acc[q]);
+    for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)((TA)fr[q] - acc[q]);
   }
 }
 
@@ -518,22 +567,33 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
   // f, z and the lane's rows of M are loaded ahead of the row product
-  TA fv[RPL], zv[RPL], mv[RPL][BR];
+  TF fr[RPL];
+  TX zr[RPL];
+  TM mr[RPL * BR];
+  load_ahead<RPL>(f, row0, own, fr);
+  load_ahead<RPL>(z, row0, own, zr);
+  const TM* m = M + (own ? (size_t)L.i * BR * BR : 0);
+  if constexpr (TRANS) {
+    // rows r of M^T are columns of M (one row per lane)
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    fv[q] = own ? (TA)f[row0 + q] : TA(0);
-    zv[q] = own ? (TA)z[row0 + q] : TA(0);
-    const TM* m = M + (size_t)L.i * BR * BR;
-    const int r = L.r + q;
-#pragma unroll
-    for (int c = 0; c < BR; ++c) mv[q][c] = own ? (TA)(TRANS ? m[c * BR + r] : m[r * BR + c]) : TA(0);
+    for (int c = 0; c < BR; ++c) mr[c] = m[c * BR + L.r];
+  } else if constexpr (BR == 4) {
+    // the lane's RPL rows of a 4x4 block are contiguous and 16-byte aligned
+    load_vals<RPL * BR, TM, TM, true>(m + (own ? L.r * BR : 0), mr);
+  } else {
+    load_ahead<RPL * BR>(m, own ? L.r * BR : 0, true, mr);
   }
   TA acc[RPL];
   row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
                                                                     z, acc, of);
-  TA res[RPL];
+  TA res[RPL], zv[RPL], mv[RPL][BR];
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) res[q] = own ? fv[q] - acc[q] : TA(0);
+  for (int q = 0; q < RPL; ++q) {
+    res[q] = own ? (TA)fr[q] - acc[q] : TA(0);
+    zv[q] = (TA)zr[q];
+#pragma unroll
+    for (int c = 0; c < BR; ++c) mv[q][c] = (TA)mr[q * BR + c];
+  }
   // Gather the BR residuals of the block row from the s == 0 lanes (row c is
   // entry c % RPL of lane c / RPL of the group).
   TA rv[BR];
