@@ -108,8 +108,10 @@ typedef struct {
                               blocks per step, RPL scalar rows per lane) for every
                               operator.  RPL 2 or 4 exists for 4x4 blocks only (and not for
                               transposed products); other products then take (S, U) if that
-                              tile exists for them, else the autotuner's tile.  An unknown tile is MGK_E_INVALID.
-                              Results are bitwise the same for every tile. */
+                              tile exists for them, else the autotuner's tile.  An unknown
+                              tile is MGK_E_INVALID.  Results are bitwise the same for every
+                              tile.  The autotuner times each candidate after clearing the
+                              caches (512 MB of transient device memory during setup) */
   int32_t coarsening;      /* mgk_coarsening, default MGK_SMOOTHED_AGGREGATION */
   int32_t schur_approx;    /* MGK_SCHUR pressure operator: 0 (default) S = C - B_lo
                               diag(A_uu)^-1 B_up assembled; 1 S = C - diag(B_lo
@@ -165,7 +167,8 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the solver */
   double spmv_ms;          /* with time_spmv bit 1: summed duration of the outer SpMVs */
   int32_t spmv_calls;      /* ... and their number */
-  int32_t outer_tile;      /* kernel tile of the outer operator, 10000*RPL + 100*S + U */
+  int32_t outer_tile;      /* kernel tile of the outer operator's fused SpMV-and-dots (the
+                              Krylov products of BiCGStab and IDR(s)), 10000*RPL + 100*S + U */
   double precond_ms;       /* with time_spmv bit 2: summed duration of the preconditioner
                               applications */
   int32_t precond_calls;   /* ... and their number */

@@ -74,10 +74,15 @@ struct Device {
     bytes += (int64_t)n;
     return p;
   }
+  // The copy has completed when upload returns, so the host buffer (often a temporary
+  // of the caller) may be released at once.
   template <class T>
   T* upload(const T* h, size_t count) {
     T* d = (T*)alloc(sizeof(T) * count);
-    if (count) HIPCK(hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, stream));
+    if (count) {
+      HIPCK(hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, stream));
+      HIPCK(hipStreamSynchronize(stream));
+    }
     return d;
   }
   ~Device() {
@@ -108,6 +113,7 @@ struct DMat {
   int *tptr = nullptr, *trow = nullptr, *tblk = nullptr;
   double avg_row = 0.0, avg_col = 0.0;
   Tile tile, ttile;          // engine tiles for products with A and with A^T
+  Tile dtile;                // tile of the fused SpMV-and-dots (outer operator)
   bool cached = false;       // values and columns read with cached loads
   // Diagonal layout (dia.k > 0): a copy of the values as n_brows x dia.k blocks on the
   // block diagonals dia.o, used by every product with A (not A^T) in its place.
@@ -208,13 +214,16 @@ inline DMat upload_mat(Device& D, const HBsr& A, int storage, bool transpose_ind
       dia_offsets(A, of, dia_mode == 1 ? 1.15 : 1e300)) {
     const int bb = A.br * A.bc;
     std::vector<double> dv((size_t)A.nbr * of.k * bb, 0.0);
+    std::vector<uint8_t> mask(A.nbr, 0);
     for (int32_t i = 0; i < A.nbr; ++i)
       for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
         int d = 0;
         while (of.o[d] != A.col[q] - i) ++d;
         std::copy(A.blk(q), A.blk(q) + bb, dv.begin() + ((size_t)i * of.k + d) * bb);
+        mask[i] |= (uint8_t)(1u << d);
       }
     M.dval = upload_values(D, dv, storage);
+    if ((int64_t)A.nbr * of.k != A.nnzb()) of.mask = D.upload(mask.data(), mask.size());
     M.dia = of;
   }
   if (transpose_index) {

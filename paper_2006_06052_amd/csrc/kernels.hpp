@@ -196,14 +196,17 @@ __device__ __forceinline__ LaneInfo lane_info(int logical_wg) {
 }
 
 // Diagonal layout of a square block operator whose blocks lie on at most DIA_MAX block
-// diagonals: block row i stores DIA_MAX' = k blocks, slot d holding A(i, i + o[d]) (o
-// ascending, so a full row's slots are its stored blocks in ascending column order); an
-// absent block is a zero block, its column clamped into range.  No row pointers and no
+// diagonals: block row i has k slots, slot d holding A(i, i + o[d]) (o ascending, so a
+// full row's slots are its stored blocks in ascending column order); a slot with no
+// stored block holds zeros and is skipped by the row mask.  No row pointers and no
 // column indices are read: the x gather no longer waits for them.
 constexpr int DIA_MAX = 8;
 struct DiaOffs {
   int k;
   int o[DIA_MAX];
+  // bit d of mask[i]: block row i stores a block on diagonal d.  Absent blocks (zero
+  // padding) are neither read nor multiplied; nullptr when every row stores all k.
+  const uint8_t* mask;
 };
 
 // Offsets of the slots L.s + m*S (m < NSLOT) that one lane of an S-way split reads.  The
@@ -268,14 +271,15 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
     // diagonal layout: the row's blocks are slots i*k .. i*k + k - 1, columns implied
     const int k0 = DIA ? L.i * of.k : ptr[L.i], k1 = DIA ? k0 + of.k : ptr[L.i + 1];
     int steps = 0;
-    // One step: blocks kb + u*S (u < U) of the row; colof(u, k) is block k's column.
-    auto step = [&](int kb, auto colof) {
+    // One step: blocks kb + u*S (u < U) of the row; colof(u, k) is block k's column,
+    // has(k) whether block k is stored.
+    auto step = [&](int kb, auto colof, auto has) {
       int j[U], kk[U];
       bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = kb + u * S;
-        ok[u] = k < k1;
+        ok[u] = k < k1 && has(k);
         j[u] = ok[u] ? colof(u, k) : 0;
         kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
       }
@@ -325,20 +329,24 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
       constexpr int NSLOT = (DIA_MAX + S - 1) / S, NSTEP = (NSLOT + U - 1) / U;
       int loff[NSLOT];
       dia_lane_offsets<S, NSLOT>(of, L.s, loff);
+      const unsigned present = of.mask ? (unsigned)of.mask[L.i] : 0xffu;
 #pragma unroll
       for (int st = 0; st < NSTEP; ++st) {
         const int kb = k0 + L.s + st * S * U;
         if (kb >= k1) break;
-        step(kb, [&](int u, int) {
-          const int m = st * U + u;
-          const int c = L.i + loff[m < NSLOT ? m : 0];
-          return c < 0 ? 0 : (c >= nbr ? nbr - 1 : c);
-        });
+        step(
+            kb,
+            [&](int u, int) {
+              const int m = st * U + u;
+              const int c = L.i + loff[m < NSLOT ? m : 0];
+              return c < 0 ? 0 : (c >= nbr ? nbr - 1 : c);
+            },
+            [&](int k) { return ((present >> (k - k0)) & 1u) != 0; });
         ++steps;
       }
     } else {
       for (int kb = k0 + L.s; kb < k1; kb += S * U, ++steps)
-        step(kb, [&](int, int k) { return ld_val<CACHED>(col + k); });
+        step(kb, [&](int, int k) { return ld_val<CACHED>(col + k); }, [](int) { return true; });
     }
     if constexpr (T > U) {
       // undo the rotations: acc[.][t] now holds stripe (t + steps*U) mod T

@@ -8,9 +8,10 @@ namespace mgk {
 // ---------------------------------------------------------------- tile autotuner
 
 // Picks the fastest engine tile for one stored operator by timing its SpMV on
-// the device (a few launches per candidate); results are cached per matrix
-// shape for the process and, when MGK_TUNE_CACHE names a file, in that JSON
-// file across processes.
+// the device (a few launches per candidate, each after the caches were cleared, as
+// in a solve, where the operator was last read a whole V-cycle or iteration ago);
+// results are cached per matrix shape for the process and, when MGK_TUNE_CACHE
+// names a file, in that JSON file across processes.
 struct TuneCache {
   std::mutex mu;
   std::map<std::string, Tile> m;
@@ -76,33 +77,78 @@ static bool tile_known(const Tile& t, bool wide) {
   return known;
 }
 
-template <int BR, int BC, class TV, class TX>
-static Tile autotune(Device& D, const DMat& M, bool trans) {
-  const bool wide = wide_ok<BR, BC, TV>() && !trans;
-  if (g_force_tile) {
-    // 10000*RPL + 100*S + U.  A wide tile (RPL > 1) applies to the products that have
-    // wide kernels; the others take (S, U) when that tile exists for them, else the
-    // autotuner's choice.  Any other unknown tile is an error.
-    const int rpl = g_force_tile / 10000;
-    const Tile t{(g_force_tile / 100) % 100, g_force_tile % 100, wide && rpl > 1 ? rpl : 1};
-    if (tile_known<BR>(t, wide)) return t;
-    if (!(rpl > 1 && !wide))
-      throw Error(MGK_E_INVALID, "force_tile " + std::to_string(g_force_tile) +
-                                     " is not a kernel tile for block rows of " +
-                                     std::to_string(BR));
+// Cache clearing for the tuner: reads a buffer twice the size of the 256 MB memory-side
+// cache, so that the timed launch finds neither its operator nor its vectors in L2 or
+// that cache (nothing is written, so no dirty lines are left to be written back during
+// the timed launch).
+static __global__ __launch_bounds__(WG) void k_evict(const u4v* __restrict__ p, size_t n,
+                                                     unsigned* __restrict__ sink) {
+  unsigned a = 0;
+  for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < n; i += (size_t)gridDim.x * WG) {
+    const u4v v = __builtin_nontemporal_load(p + i);
+    a ^= v.x ^ v.y ^ v.z ^ v.w;
   }
-  const int nrows = trans ? M.nbc : M.nbr, ncols = trans ? M.nbr : M.nbc;
-  if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4, 1} : Tile{1, 4, 1};
-  char key[200];
-  snprintf(key, sizeof key, "b%dx%d_v%d_x%d_t%d_r%d_nnz%lld_dia%d", BR, BC, (int)sizeof(TV),
-           (int)sizeof(TX), (int)trans, nrows, (long long)M.nnzb, trans ? 0 : M.dia.k);
-  TuneCache& C = TuneCache::get();
-  {
-    std::lock_guard<std::mutex> g(C.mu);
-    C.load();
-    auto it = C.m.find(key);
-    if (it != C.m.end() && tile_known<BR>(it->second, wide)) return it->second;
+  if (a == 0x9e3779b9u) sink[0] = a;   // keeps the loads; the buffer is zero, so never taken
+}
+
+struct Evictor {
+  static constexpr size_t BYTES = (size_t)512 << 20;
+  void* buf = nullptr;
+  explicit Evictor(hipStream_t st) {
+    // MGK_TUNE_WARM=1: time with warm caches (each launch right after the previous one)
+    const char* w = getenv("MGK_TUNE_WARM");
+    if (w && atoi(w) == 1) return;
+    if (hipMalloc(&buf, BYTES + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      buf = nullptr;   // tune with warm caches instead
+      return;
+    }
+    HIPCK(hipMemsetAsync(buf, 0, BYTES + 256, st));
   }
+  void run(hipStream_t st) const {
+    if (!buf) return;
+    k_evict<<<2048, WG, 0, st>>>((const u4v*)buf, BYTES / 16,
+                                 (unsigned*)((char*)buf + BYTES));
+  }
+  ~Evictor() {
+    if (buf) (void)hipFree(buf);
+  }
+};
+
+// Time `launch` for each candidate tile (three cold launches each); returns the fastest.
+template <class F>
+static Tile time_candidates(Device& D, const std::vector<Tile>& cands, F&& launch) {
+  Evictor ev(D.stream);
+  hipEvent_t e[6];
+  for (auto& x : e) HIPCK(hipEventCreate(&x));
+  Tile best = cands[0];
+  float best_ms = 1e30f;
+  for (const Tile& t : cands) {
+    launch(t);   // first launch of the instantiation
+    for (int r = 0; r < 3; ++r) {
+      ev.run(D.stream);
+      HIPCK(hipEventRecord(e[2 * r], D.stream));
+      launch(t);
+      HIPCK(hipEventRecord(e[2 * r + 1], D.stream));
+    }
+    HIPCK(hipEventSynchronize(e[5]));
+    float ms = 0;
+    for (int r = 0; r < 3; ++r) {
+      float m = 0;
+      HIPCK(hipEventElapsedTime(&m, e[2 * r], e[2 * r + 1]));
+      ms += m;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  for (auto& x : e) (void)hipEventDestroy(x);
+  return best;
+}
+
+template <int BR>
+static std::vector<Tile> tile_candidates(bool wide) {
   std::vector<Tile> cands;
 #define MGK_CAND(SS, UU) cands.push_back(Tile{SS, UU, 1});
 #define MGK_CAND_W(SS, UU, RR) cands.push_back(Tile{SS, UU, RR});
@@ -116,32 +162,97 @@ static Tile autotune(Device& D, const DMat& M, bool trans) {
   }
 #undef MGK_CAND
 #undef MGK_CAND_W
+  return cands;
+}
+
+// A forced tile (mgk_params.force_tile) when it applies to this product, else {0,0,0}.
+template <int BR>
+static Tile forced_tile(bool wide) {
+  if (!g_force_tile) return Tile{0, 0, 0};
+  // 10000*RPL + 100*S + U.  A wide tile (RPL > 1) applies to the products that have
+  // wide kernels; the others take (S, U) when that tile exists for them, else the
+  // autotuner's choice.  Any other unknown tile is an error.
+  const int rpl = g_force_tile / 10000;
+  const Tile t{(g_force_tile / 100) % 100, g_force_tile % 100, wide && rpl > 1 ? rpl : 1};
+  if (tile_known<BR>(t, wide)) return t;
+  if (!(rpl > 1 && !wide))
+    throw Error(MGK_E_INVALID, "force_tile " + std::to_string(g_force_tile) +
+                                   " is not a kernel tile for block rows of " +
+                                   std::to_string(BR));
+  return Tile{0, 0, 0};
+}
+
+template <int BR, int BC, class TV, class TX>
+static Tile autotune(Device& D, const DMat& M, bool trans) {
+  const bool wide = wide_ok<BR, BC, TV>() && !trans;
+  const Tile ft = forced_tile<BR>(wide);
+  if (ft.s) return ft;
+  const int nrows = trans ? M.nbc : M.nbr, ncols = trans ? M.nbr : M.nbc;
+  if (nrows == 0 || M.nnzb == 0) return BR == 1 ? Tile{4, 4, 1} : Tile{1, 4, 1};
+  char key[200];
+  snprintf(key, sizeof key, "b%dx%d_v%d_x%d_t%d_r%d_nnz%lld_dia%d", BR, BC, (int)sizeof(TV),
+           (int)sizeof(TX), (int)trans, nrows, (long long)M.nnzb, trans ? 0 : M.dia.k);
+  TuneCache& C = TuneCache::get();
+  {
+    std::lock_guard<std::mutex> g(C.mu);
+    C.load();
+    auto it = C.m.find(key);
+    if (it != C.m.end() && tile_known<BR>(it->second, wide)) return it->second;
+  }
+  const std::vector<Tile> cands = tile_candidates<BR>(wide);
   TX *x = nullptr, *y = nullptr;
   HIPCK(hipMalloc(&x, sizeof(TX) * (size_t)ncols * (trans ? BR : BC) + 64));
   HIPCK(hipMalloc(&y, sizeof(TX) * (size_t)nrows * (trans ? BC : BR) + 64));
   HIPCK(hipMemsetAsync(x, 0, sizeof(TX) * (size_t)ncols * (trans ? BR : BC), D.stream));
-  hipEvent_t e0, e1;
-  HIPCK(hipEventCreate(&e0));
-  HIPCK(hipEventCreate(&e1));
-  Tile best = cands[0];
-  float best_ms = 1e30f;
-  for (const Tile& t : cands) {
+  const Tile best = time_candidates(D, cands, [&](const Tile& t) {
     spmv_s<BR, BC, TV, TX, TX>(D.stream, M, trans, t, x, y, 1.0, 0.0);
-    HIPCK(hipEventRecord(e0, D.stream));
-    for (int r = 0; r < 3; ++r) spmv_s<BR, BC, TV, TX, TX>(D.stream, M, trans, t, x, y, 1.0, 0.0);
-    HIPCK(hipEventRecord(e1, D.stream));
-    HIPCK(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = t;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  });
+  HIPCK(hipStreamSynchronize(D.stream));
   (void)hipFree(x);
   (void)hipFree(y);
+  std::lock_guard<std::mutex> g(C.mu);
+  C.m[key] = best;
+  C.save();
+  return best;
+}
+
+// Tile of the fused FP64 SpMV-and-dots of the outer operator, timed as that kernel: its
+// workgroups cover whole 16-row dot groups, so its best tile can differ from the plain
+// product's.
+template <int BR>
+static Tile autotune_dot(Device& D, const DMat& M) {
+  const bool wide = wide_ok<BR, BR, double>();
+  const Tile ft = forced_tile<BR>(wide);
+  if (ft.s) return ft;
+  if (M.nbr == 0 || M.nnzb == 0) return M.tile;
+  char key[200];
+  snprintf(key, sizeof key, "dot_b%d_r%d_nnz%lld_dia%d", BR, M.nbr, (long long)M.nnzb,
+           M.dia.k);
+  TuneCache& C = TuneCache::get();
+  {
+    std::lock_guard<std::mutex> g(C.mu);
+    C.load();
+    auto it = C.m.find(key);
+    if (it != C.m.end() && tile_known<BR>(it->second, wide)) return it->second;
+  }
+  const std::vector<Tile> cands = tile_candidates<BR>(wide);
+  const size_t n = (size_t)M.nbr * BR;
+  const size_t ng = ((size_t)M.nbr + dot_rows<BR>() - 1) / dot_rows<BR>();
+  double *x = nullptr, *y = nullptr, *w = nullptr, *part = nullptr;
+  HIPCK(hipMalloc(&x, 8 * n + 64));
+  HIPCK(hipMalloc(&y, 8 * n + 64));
+  HIPCK(hipMalloc(&w, 8 * n + 64));
+  HIPCK(hipMalloc(&part, 16 * ng + 64));
+  HIPCK(hipMemsetAsync(x, 0, 8 * n, D.stream));
+  HIPCK(hipMemsetAsync(w, 0, 8 * n, D.stream));
+  const Tile best = time_candidates(D, cands, [&](const Tile& t) {
+    spmv_dot_s<BR, BR>(D.stream, M, false, t, x, y, 1, w, part);
+  });
+  HIPCK(hipStreamSynchronize(D.stream));
+  (void)hipFree(x);
+  (void)hipFree(y);
+  (void)hipFree(w);
+  (void)hipFree(part);
   std::lock_guard<std::mutex> g(C.mu);
   C.m[key] = best;
   C.save();
@@ -268,7 +379,7 @@ void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots,
   hipStream_t st = S->dev.stream;
   const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
   if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
-  const Tile sp = trans ? S->A.ttile : S->A.tile;
+  const Tile sp = trans ? S->A.ttile : (dots ? S->A.dtile : S->A.tile);
   int g = 0;
   switch (S->b) {
     case 1:
@@ -745,6 +856,11 @@ static void setup_impl(mgk_solver* S, const mgk_bsr* A, int block_size, int kind
   S->A = upload_mat(S->dev, H, MGK_F64, tr, dia);
   S->A.cached = operator_cached(MGK_F64, true);
   tune_mat(S->dev, S->A, MGK_F64, tr);
+  switch (S->b) {
+    case 1: S->A.dtile = autotune_dot<1>(S->dev, S->A); break;
+    case 3: S->A.dtile = autotune_dot<3>(S->dev, S->A); break;
+    case 4: S->A.dtile = autotune_dot<4>(S->dev, S->A); break;
+  }
   const SetupParams sp = setup_params(*prm, kind);
   int rc;
   if (kind == MGK_ILU) {
@@ -975,7 +1091,7 @@ static int solve_common(mgk_solver* s, const double* d_b, double* d_x, double rt
     }
     info->precond_ms = pc_ms;
     info->precond_calls = (int32_t)(s->pev_used / 2);
-    const mgk::Tile& ot = s->A.tile;
+    const mgk::Tile& ot = s->A.dtile;
     info->outer_tile = 10000 * ot.rpl + 100 * ot.s + ot.u;
     info->outer_dia = s->A.dia.k;
     return rc;
