@@ -753,15 +753,18 @@ def main():
         del s
         torch.cuda.empty_cache()
 
-    # HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-    # used only while it describes this kernel: the same instantiation and unchanged kernel
-    # source (a stale figure is reported as null)
-    tpath = os.path.join(ROOT, "profiles", "spmv_bsr4_f64_cube96_traffic.json")
+    # HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, per
+    # instantiation (the autotuner's trial launches measure every candidate tile), used only
+    # while it describes this kernel: the same instantiation and unchanged kernel source (a
+    # stale figure is reported as null)
+    tpath = os.path.join(ROOT, "profiles", "spmv_dot_f64_cube96_traffic.json")
     if roofline and os.path.exists(tpath):
         with open(tpath) as f:
             tr = json.load(f)
-        if tr.get("kernel") == roofline["kernel"] and tr.get("kernels_sha") == kernels_sha():
-            roofline["traffic"] = tr.get("bytes_per_launch")
+        hit = tr.get("by_instantiation", {}).get(roofline["kernel"])
+        if hit and tr.get("kernels_sha") == kernels_sha():
+            roofline["traffic"] = hit["bytes_per_launch"]
+            roofline["traffic_dispatches_measured"] = hit["dispatches"]
             roofline["traffic_what"] = tr.get("what")
 
     value = float(np.median(head_times))

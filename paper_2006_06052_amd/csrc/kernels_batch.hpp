@@ -52,14 +52,17 @@ __global__ __launch_bounds__(WG) void k_g_spmv(const GItem* __restrict__ items, 
     const GItem& g = items[find_item(items, nitems, w)];
     if (!active[g.sys]) continue;
     const LaneInfo L = lane_info<BR, S>(w - g.tile0);
+    const bool own = L.active && L.s == 0 && L.i < g.nbr;
+    const size_t row = (size_t)L.i * BR + L.r;
+    TY* y = (TY*)g.out;
+    TY yr[1];
+    if (beta != TA(0)) load_ahead<1>(y, row, own, yr);
     TA acc = row_product<BR, BC, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
                                                                   (const TV*)g.val,
                                                                   (const TX*)g.in);
-    if (L.active && L.s == 0 && L.i < g.nbr) {
-      const size_t row = (size_t)L.i * BR + L.r;
-      TY* y = (TY*)g.out;
+    if (own) {
       TA out = acc;
-      if (beta != TA(0)) out = fma_(beta, (TA)y[row], out);
+      if (beta != TA(0)) out = fma_(beta, (TA)yr[0], out);
       y[row] = (TY)out;
     }
   }
@@ -75,11 +78,12 @@ __global__ __launch_bounds__(WG) void k_g_residual(const GItem* __restrict__ ite
     const LaneInfo L = lane_info<B, S>(w - g.tile0);
     const bool own = L.active && L.s == 0 && L.i < g.nbr;
     const size_t row = (size_t)L.i * B + L.r;
-    const TA fv = own ? (TA)((const TF*)g.f)[row] : TA(0);   // ahead of the row product
+    TF fr[1];   // ahead of the row product
+    load_ahead<1>((const TF*)g.f, row, own, fr);
     TA acc = row_product<B, B, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
                                                                 (const TV*)g.val,
                                                                 (const TX*)g.in);
-    if (own) ((TX*)g.out)[row] = (TX)(fv - acc);
+    if (own) ((TX*)g.out)[row] = (TX)((TA)fr[0] - acc);
   }
 }
 
@@ -96,15 +100,19 @@ __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items
     const bool own = L.active && L.s == 0 && L.i < g.nbr;
     const size_t row = (size_t)L.i * B + L.r;
     // f, z and the row of M are loaded ahead of the row product
-    const TM* m = (const TM*)g.M + (size_t)L.i * B * B;
-    const TA fv = own ? (TA)((const TF*)g.f)[row] : TA(0);
-    const TA zv = own ? (TA)z[row] : TA(0);
-    TA mv[B];
-#pragma unroll
-    for (int c = 0; c < B; ++c) mv[c] = own ? (TA)m[L.r * B + c] : TA(0);
+    TF fr[1];
+    TX zr[1];
+    TM mr[B];
+    load_ahead<1>((const TF*)g.f, row, own, fr);
+    load_ahead<1>(z, row, own, zr);
+    load_ahead<B>((const TM*)g.M, ((size_t)L.i * B + L.r) * B, own, mr);
     TA acc = row_product<B, B, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
                                                                 (const TV*)g.val, z);
-    const TA res = own ? fv - acc : TA(0);
+    const TA res = own ? (TA)fr[0] - acc : TA(0);
+    const TA zv = (TA)zr[0];
+    TA mv[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) mv[c] = (TA)mr[c];
     TA rv[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) rv[c] = __shfl(res, L.gbase + c, WAVE);

@@ -156,6 +156,16 @@ __device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool o
   }
 }
 
+// The lane's B entries p[(i*B + r)*K + k] (r < B) of an [n][K] operand, loaded ahead of
+// the row product by every lane (lanes without a row or column read entry 0), so that no
+// branch puts a wait for them before the product's loads.
+template <int B, class T>
+__device__ __forceinline__ void load_rows_ahead(const T* __restrict__ p, bool on, int i, int k,
+                                                int K, T (&out)[B]) {
+#pragma unroll
+  for (int r = 0; r < B; ++r) out[r] = p[on ? ((size_t)i * B + r) * K + k : 0];
+}
+
 // Block M_i of a block-diagonal matrix for the lane's row, both rows' blocks
 // fetched through scalar loads.
 template <int B, class TM, class TA>
@@ -179,6 +189,8 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
   const MRow m = mrow(lw);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
+  TY yr[BR];
+  if (beta != TA(0)) load_rows_ahead<BR>(Y, on, i, k, K, yr);
   TA acc[BR];
   block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, X, acc);
   if (!on) return;
@@ -186,7 +198,7 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
   for (int r = 0; r < BR; ++r) {
     const size_t e = ((size_t)i * BR + r) * K + k;
     TA out = alpha * acc[r];
-    if (beta != TA(0)) out = fma_(beta, (TA)Y[e], out);
+    if (beta != TA(0)) out = fma_(beta, (TA)yr[r], out);
     Y[e] = (TY)out;
   }
 }
@@ -206,6 +218,8 @@ __global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __re
   const MRow m = mrow(lw);
   const bool on = m.i < nbr && m.k < K;
   double d1 = 0.0, d2 = 0.0;
+  double w[B];
+  load_rows_ahead<B>(W1, on, m.i, m.k, K, w);
   double acc[B];
   block_rows_staged<B, B, double, double, double>(lw * MROWS, nbr, m.i, on, m.k, K, ptr, col, val,
                                                   X, acc);
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __re
     for (int r = 0; r < B; ++r) {
       const size_t e = ((size_t)m.i * B + r) * K + m.k;
       Y[e] = acc[r];
-      d1 = fma_(W1[e], acc[r], d1);
+      d1 = fma_(w[r], acc[r], d1);
       d2 = fma_(acc[r], acc[r], d2);
     }
   }
@@ -275,13 +289,15 @@ __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __
   const MRow m = mrow(lw);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
+  TF fr[BR];
+  load_rows_ahead<BR>(F, on, i, k, K, fr);
   TA acc[BR];
   block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, Z, acc);
   if (!on) return;
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const size_t e = ((size_t)i * BR + r) * K + k;
-    T[e] = (TX)((TA)F[e] - acc[r]);
+    T[e] = (TX)((TA)fr[r] - acc[r]);
   }
 }
 
@@ -298,19 +314,25 @@ __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __re
   const MRow m = mrow(lw);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
+  TF fr[B];
+  TX zr[B];
+  load_rows_ahead<B>(F, on, i, k, K, fr);
+  load_rows_ahead<B>(Z, on, i, k, K, zr);
+  // M blocks ahead of the product too; a wavefront whose rows lie past nbr reads row 0's
+  MRow mc = m;
+  if (mc.i0 >= nbr) mc.i0 = 0;
+  TA mb[B * B];
+  diag_block<B, TM, TA>(mc, mc.i0 + 1 < nbr, M, mb);
   TA acc[B];
   block_rows_staged<B, B, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, Z, acc);
-  if (m.i0 >= nbr) return;
-  TA mb[B * B];
-  diag_block<B, TM, TA>(m, m.i0 + 1 < nbr, M, mb);
   if (!on) return;
   TA res[B];
 #pragma unroll
-  for (int r = 0; r < B; ++r) res[r] = (TA)F[((size_t)i * B + r) * K + k] - acc[r];
+  for (int r = 0; r < B; ++r) res[r] = (TA)fr[r] - acc[r];
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     const size_t e = ((size_t)i * B + r) * K + k;
-    TA out = (TA)Z[e];
+    TA out = (TA)zr[r];
 #pragma unroll
     for (int c = 0; c < B; ++c) out = fma_(mb[r * B + c], res[c], out);
     Zout[e] = (TO)out;

@@ -85,7 +85,7 @@ static __global__ __launch_bounds__(WG) void k_evict(const u4v* __restrict__ p, 
                                                      unsigned* __restrict__ sink) {
   unsigned a = 0;
   for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < n; i += (size_t)gridDim.x * WG) {
-    const u4v v = __builtin_nontemporal_load(p + i);
+    const u4v v = p[i];   // ordinary loads: streaming loads would not allocate in the caches
     a ^= v.x ^ v.y ^ v.z ^ v.w;
   }
   if (a == 0x9e3779b9u) sink[0] = a;   // keeps the loads; the buffer is zero, so never taken
