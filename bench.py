@@ -114,7 +114,7 @@ def vcycle_bytes(s, hier):
         A = d["nnzb"] * (b * b * sv + 4) + 4 * (nb + 1)
         P = d["p_nnzb"] * (b * b * sv + 4) + 4 * (nb + 1)
         R = d["r_nnzb"] * (b * b * sv + 4) + 4 * (d["n_agg"] + 1)
-        Mb = nb * b * b * sx
+        Mb = nb * b * b * sv   # smoother blocks in the hierarchy's value precision
         pre = Mb + n * s_in + n * sx
         res = A + n * sx + n * s_in + n * sx
         rst = R + n * sx + nc * sx

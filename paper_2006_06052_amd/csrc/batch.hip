@@ -206,7 +206,7 @@ static void tune_stage(BatchWork& W, GStage& g, int* active) {
 
 template <int B, class TV, class TX>
 struct GCycle {
-  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+  using TM = typename SmootherOf<TV>::type;
   using TA = AccOf<TV>;
   static void run(BatchWork& W, int v) {
     hipStream_t st = W.dev.stream;

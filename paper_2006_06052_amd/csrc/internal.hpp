@@ -559,7 +559,7 @@ static void ilu_sweeps(hipStream_t st, const DMat& Lf, const DMat& Uf, const voi
 
 template <int B, class TV, class TX>
 struct Cycle {
-  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+  using TM = typename SmootherOf<TV>::type;
 
   template <class TIN, class TOUT>
   static void run(hipStream_t st, DHier& H, int l, const TIN* r, TOUT* zout, bool trans) {

@@ -34,6 +34,13 @@ struct bf16 {
   uint16_t u;
 };
 
+// Storage type of the smoother blocks M of a hierarchy whose values are of type TV: the
+// same precision (FP64, FP32 or BF16).
+template <class TV>
+struct SmootherOf {
+  using type = TV;
+};
+
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
@@ -51,6 +58,13 @@ __device__ __forceinline__ float fma_(float a, float b, float c) { return __buil
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t u) {
   return __uint_as_float(((uint32_t)u) << 16);
+}
+
+// A stored value as the accumulation type (BF16 widened exactly to FP32).
+template <class TA, class T>
+__device__ __forceinline__ TA to_acc(T v) {
+  if constexpr (sizeof(T) == 2) return (TA)bf16_to_f32(reinterpret_cast<const uint16_t&>(v));
+  else return (TA)v;
 }
 
 // ---- value loads -----------------------------------------------------------
@@ -585,7 +599,7 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
     // rows r of M^T are columns of M (one row per lane)
 #pragma unroll
     for (int c = 0; c < BR; ++c) mr[c] = m[c * BR + L.r];
-  } else if constexpr (BR == 4) {
+  } else if constexpr (BR == 4 && sizeof(TM) >= 4) {
     // the lane's RPL rows of a 4x4 block are contiguous and 16-byte aligned
     load_vals<RPL * BR, TM, TM, true>(m + (own ? L.r * BR : 0), mr);
   } else {
@@ -600,7 +614,7 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
     res[q] = own ? (TA)fr[q] - acc[q] : TA(0);
     zv[q] = (TA)zr[q];
 #pragma unroll
-    for (int c = 0; c < BR; ++c) mv[q][c] = (TA)mr[q * BR + c];
+    for (int c = 0; c < BR; ++c) mv[q][c] = to_acc<TA>(mr[q * BR + c]);
   }
   // Gather the BR residuals of the block row from the s == 0 lanes (row c is
   // entry c % RPL of lane c / RPL of the group).
@@ -631,7 +645,8 @@ __global__ __launch_bounds__(WG) void k_block_diag(int nbr, int trans, const TM*
   const TF* fi = f + i * B;
   TA acc = 0;
 #pragma unroll
-  for (int c = 0; c < B; ++c) acc = fma_((TA)(trans ? m[c * B + r] : m[r * B + c]), (TA)fi[c], acc);
+  for (int c = 0; c < B; ++c)
+    acc = fma_(to_acc<TA>(trans ? m[c * B + r] : m[r * B + c]), (TA)fi[c], acc);
   z[row] = (TX)acc;
 }
 

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items
     const TA zv = (TA)zr[0];
     TA mv[B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) mv[c] = (TA)mr[c];
+    for (int c = 0; c < B; ++c) mv[c] = to_acc<TA>(mr[c]);
     TA rv[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) rv[c] = __shfl(res, L.gbase + c, WAVE);
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(WG) void k_g_block_diag(const GItem* __restrict__ i
     const TF* fi = (const TF*)g.in + i * B;
     TA acc = 0;
 #pragma unroll
-    for (int c = 0; c < B; ++c) acc = fma_((TA)m[r * B + c], (TA)fi[c], acc);
+    for (int c = 0; c < B; ++c) acc = fma_(to_acc<TA>(m[r * B + c]), (TA)fi[c], acc);
     ((TX*)g.out)[row] = (TX)acc;
   }
 }

@@ -94,7 +94,7 @@ static MultiWork* ensure_multi(mgk_solver* S) {
 
 template <int B, class TV, class TX>
 struct CycleM {
-  using TM = typename std::conditional<std::is_same<TV, double>::value, double, float>::type;
+  using TM = typename SmootherOf<TV>::type;
   using TA = AccOf<TV>;
 
   template <class TIN, class TOUT>

@@ -325,12 +325,17 @@ static void upload_hierarchy(Device& D, HHierarchy& H, int storage, bool with_tr
       d.R = upload_mat(D, h.R, storage, false);
       const bool ilu = !h.ilu.Dinv.empty();
       const std::vector<double>& Mh = ilu ? h.ilu.Dinv : h.M;
+      // smoother blocks in the hierarchy's storage precision; ILU pivots' inverses in FP32
+      // below FP64
       if (storage == MGK_F64) {
         (ilu ? d.Dinv : d.M) = D.upload(Mh.data(), Mh.size());
+      } else if (storage == MGK_BF16 && !ilu) {
+        std::vector<uint16_t> m(Mh.size());
+        for (size_t q = 0; q < Mh.size(); ++q) m[q] = f32_to_bf16((float)Mh[q]);
+        d.M = D.upload(m.data(), m.size());
       } else {
         std::vector<float> m(Mh.begin(), Mh.end());
         (ilu ? d.Dinv : d.M) = D.upload(m.data(), m.size());
-        HIPCK(hipStreamSynchronize(D.stream));
       }
       if (ilu) {
         out.ilu = true;

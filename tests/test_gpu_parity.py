@@ -422,7 +422,7 @@ def test_cached_and_streamed_value_loads_agree(storage, monkeypatch):
     b = dev(S.mms_rhs(n))
     x0 = dev(np.random.default_rng(9).normal(size=A.shape[0]))
     outs = []
-    for mode in ("0", "15"):
+    for mode in ("0", "1", "2", "4", "8", "15"):
         monkeypatch.setenv("MGK_CACHED_LOADS", mode)
         s = gpu_solver(bsr, hier=storage, coarse_enough=200)
         y = torch.empty_like(b)
@@ -432,7 +432,28 @@ def test_cached_and_streamed_value_loads_agree(storage, monkeypatch):
         x = torch.zeros_like(b)
         info = s.solve(b, x, 1e-8)
         outs.append((y.cpu().numpy(), z.cpu().numpy(), x.cpu().numpy(), info["iters"]))
-    for a, c in zip(outs[0], outs[1]):
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            assert np.array_equal(a, c)
+
+
+def test_cached_and_streamed_loads_agree_in_batches(monkeypatch):
+    """The grouped batch kernels take the same load policy: a batched solve is bitwise the
+    same with every operator streamed and every operator cached."""
+    ns = [10, 13]
+    probs = [problem(n, 0.5, 60 + k) for k, n in enumerate(ns)]
+    bs = [dev(oracle.spmv(A, S.mms_solution(n))) for n, (_, _, A) in zip(ns, probs)]
+    outs = []
+    for mode in ("0", "15"):
+        monkeypatch.setenv("MGK_CACHED_LOADS", mode)
+        bsol = mgk.BatchSolver([p[1] for p in probs], 4, mgk.AMG_SPAI0,
+                               stream=torch.cuda.current_stream(), hier="bf16",
+                               coarse_enough=300)
+        xs = [torch.zeros_like(b) for b in bs]
+        infos = bsol.solve(bs, xs, 1e-8)
+        outs.append(([x.cpu().numpy() for x in xs], [i["iters"] for i in infos]))
+    assert outs[0][1] == outs[1][1]
+    for a, c in zip(outs[0][0], outs[1][0]):
         assert np.array_equal(a, c)
 
 
