@@ -798,37 +798,46 @@ static __global__ __launch_bounds__(WG) void k_bicg_p(size_t n, const double* __
   GRID_STRIDE(i, n) p[i] = r[i] + beta * (p[i] - om * v[i]);
 }
 
-// s = r - alpha v; x += alpha phat; partials of ||s||^2.
+// s = r - alpha v; partials of ||s||^2.  (x += alpha phat is deferred to k_bicg_xr, or to
+// k_bicg_x when the iteration stops at s.)
 static __global__ __launch_bounds__(WG) void k_bicg_s(size_t n, const double* __restrict__ sc,
                                                const double* __restrict__ r,
                                                const double* __restrict__ v,
-                                               const double* __restrict__ ph,
-                                               double* __restrict__ s, double* __restrict__ x,
+                                               double* __restrict__ s,
                                                double* __restrict__ part) {
   const double al = sc[SC_ALPHA];
   double ss = 0.0, dummy = 0.0;
   GRID_STRIDE(i, n) {
     const double si = r[i] - al * v[i];
     s[i] = si;
-    x[i] += al * ph[i];
     ss += si * si;
   }
   wg_sum2(ss, dummy);
   if (threadIdx.x == 0) part[blockIdx.x] = ss;
 }
 
-// x += omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
+// x += alpha phat (the iteration stopped at s).
+static __global__ __launch_bounds__(WG) void k_bicg_x(size_t n, const double* __restrict__ sc,
+                                               const double* __restrict__ ph,
+                                               double* __restrict__ x) {
+  const double al = sc[SC_ALPHA];
+  GRID_STRIDE(i, n) x[i] += al * ph[i];
+}
+
+// x = (x + alpha phat) + omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
+// One pass over x per iteration, with the two additions in the order of the two updates.
 static __global__ __launch_bounds__(WG) void k_bicg_xr(size_t n, const double* __restrict__ sc,
                                                 const double* __restrict__ s,
                                                 const double* __restrict__ t,
+                                                const double* __restrict__ ph,
                                                 const double* __restrict__ sh,
                                                 const double* __restrict__ rh,
                                                 double* __restrict__ x, double* __restrict__ r,
                                                 double* __restrict__ part) {
-  const double om = sc[SC_OMEGA];
+  const double al = sc[SC_ALPHA], om = sc[SC_OMEGA];
   double rr = 0.0, rho = 0.0;
   GRID_STRIDE(i, n) {
-    x[i] += om * sh[i];
+    x[i] = (x[i] + al * ph[i]) + om * sh[i];
     const double ri = s[i] - om * t[i];
     r[i] = ri;
     rr += ri * ri;

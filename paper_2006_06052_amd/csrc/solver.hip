@@ -572,7 +572,7 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
         finalize(S, nw, 0, FIN_ALPHA);
       }
       pending_v = false;
-      k_bicg_s<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->ph, S->s, x, S->part);
+      k_bicg_s<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->s, S->part);
       finalize(S, g, 0, FIN_STORE1, SC_SS);
       publish(S, 0);
       // speculative: shat = M s; t = A shat (harmless if we stop after s)
@@ -581,8 +581,11 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
       outer_spmv(S, S->sh, S->t, trans, 2, S->s, &nw);  // partials (s,t), (t,t)
       finalize(S, nw, 1, FIN_OMEGA);
       wait(S, 0);
-      if (S->hsc[SC_SS] <= tol2) break;  // x already holds x + alpha phat
-      k_bicg_xr<<<g, WG, 0, st>>>(n, S->sc, S->s, S->t, S->sh, S->rh, x, S->r, S->part);
+      if (S->hsc[SC_SS] <= tol2) {   // stop at s: x + alpha phat
+        k_bicg_x<<<g, WG, 0, st>>>(n, S->sc, S->ph, x);
+        break;
+      }
+      k_bicg_xr<<<g, WG, 0, st>>>(n, S->sc, S->s, S->t, S->ph, S->sh, S->rh, x, S->r, S->part);
       finalize(S, g, 1, FIN_RHO);
       publish(S, 1);
       if (it < maxiter_of(S)) {
