@@ -126,6 +126,84 @@ __device__ __forceinline__ void load_vals(const TV* __restrict__ p, TA* out) {
   }
 }
 
+// N consecutive stored values as loaded, before any conversion: the row engine issues
+// every load of a step into these and converts afterwards, so that no conversion sits
+// between a load and the next block's loads (a conversion inside the branch that guards a
+// block makes the compiler wait for that block's loads before issuing the next ones).
+// FP32 / FP64: the values; BF16 in multiples of 4: packed pairs; other BF16: halves.
+template <int N, class TV, bool PACKED = (sizeof(TV) == 2 && N % 4 == 0)>
+struct VRaw {
+  TV v[N];
+};
+template <int N, class TV>
+struct VRaw<N, TV, true> {
+  uint32_t w[N / 2];
+};
+
+template <int N, class TV, bool CACHED>
+__device__ __forceinline__ void load_vals_raw(const TV* __restrict__ p, VRaw<N, TV>& r) {
+  if constexpr (sizeof(TV) == 2 && N % 8 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 8; ++q) {
+      const u4v a = ld_val<CACHED>(reinterpret_cast<const u4v*>(p) + q);
+      r.w[4 * q] = a.x; r.w[4 * q + 1] = a.y; r.w[4 * q + 2] = a.z; r.w[4 * q + 3] = a.w;
+    }
+  } else if constexpr (sizeof(TV) == 2 && N % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 4; ++q) {
+      const u2v a = ld_val<CACHED>(reinterpret_cast<const u2v*>(p) + q);
+      r.w[2 * q] = a.x; r.w[2 * q + 1] = a.y;
+    }
+  } else if constexpr (sizeof(TV) == 2) {
+    const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
+#pragma unroll
+    for (int c = 0; c < N; ++c) r.v[c].u = ld_val<CACHED>(q + c);
+  } else if constexpr (sizeof(TV) == 8 && N % 2 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) {
+      const d2v a = ld_val<CACHED>(reinterpret_cast<const d2v*>(p) + q);
+      r.v[2 * q] = a.x; r.v[2 * q + 1] = a.y;
+    }
+  } else if constexpr (sizeof(TV) == 4 && N % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 4; ++q) {
+      const f4v a = ld_val<CACHED>(reinterpret_cast<const f4v*>(p) + q);
+      r.v[4 * q] = a.x; r.v[4 * q + 1] = a.y; r.v[4 * q + 2] = a.z; r.v[4 * q + 3] = a.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < N; ++c) r.v[c] = ld_val<CACHED>(p + c);
+  }
+}
+
+template <int N, class TV>
+__device__ __forceinline__ void zero_raw(VRaw<N, TV>& r) {
+  if constexpr (sizeof(TV) == 2 && N % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) r.w[q] = 0u;
+  } else if constexpr (sizeof(TV) == 2) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) r.v[c].u = 0;
+  } else {
+#pragma unroll
+    for (int c = 0; c < N; ++c) r.v[c] = TV(0);
+  }
+}
+
+template <int N, class TV, class TA>
+__device__ __forceinline__ void finish_vals(const VRaw<N, TV>& r, TA* out) {
+  if constexpr (sizeof(TV) == 2 && N % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) {
+      out[2 * q] = (TA)__uint_as_float(r.w[q] << 16);
+      out[2 * q + 1] = (TA)__uint_as_float(r.w[q] & 0xffff0000u);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < N; ++c) out[c] = to_acc<TA>(r.v[c]);
+  }
+}
+
 // Single value (used by the transposed product, which reads block columns).
 template <class TV, class TA>
 __device__ __forceinline__ TA load_val(const TV* __restrict__ p) {
@@ -246,6 +324,31 @@ __device__ __forceinline__ void dia_lane_offsets(const DiaOffs& of, int s, int (
   }
 }
 
+// x source of the row engine: fetch_raw issues a block's loads, finish_x converts after
+// every load of the step is in flight.  A stored vector: block j is BC consecutive
+// entries.
+template <class XSrc, int BC>
+struct XRaw;
+template <class TX, int BC>
+struct XRaw<const TX*, BC> {
+  TX x[BC];
+};
+
+template <int BC, class TX>
+__device__ __forceinline__ void fetch_raw(const TX* __restrict__ x, int j, XRaw<const TX*, BC>& r) {
+  load_x<BC, TX, TX>(x + (size_t)j * BC, r.x);
+}
+template <int BC, class TX>
+__device__ __forceinline__ void zero_xraw(const TX*, XRaw<const TX*, BC>& r) {
+#pragma unroll
+  for (int c = 0; c < BC; ++c) r.x[c] = TX(0);
+}
+template <int BC, class TA, class TX>
+__device__ __forceinline__ void finish_x(const TX*, const XRaw<const TX*, BC>& r, TA* out) {
+#pragma unroll
+  for (int c = 0; c < BC; ++c) out[c] = (TA)r.x[c];
+}
+
 // Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
 // (BR/RPL)*S lanes.
 //
@@ -263,13 +366,13 @@ __device__ __forceinline__ void dia_lane_offsets(const DiaOffs& of, int s, int (
 // block).  When T > U the stripe accumulators rotate by U after each step so
 // that block u of a step always lands in accumulator u.
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA, int RPL,
-          bool CACHED = false, bool DIA = false>
+          bool CACHED = false, bool DIA = false, class XSrc = const TX*>
 __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
                                               const int* __restrict__ ptr,
                                               const int* __restrict__ col,
                                               const int* __restrict__ blk,
                                               const TV* __restrict__ val,
-                                              const TX* __restrict__ x, TA (&out)[RPL],
+                                              XSrc x, TA (&out)[RPL],
                                               const DiaOffs& of = DiaOffs{}) {
   constexpr int NS = BR == 1 ? 32 : 16;
   constexpr int T = NS / S;
@@ -286,46 +389,66 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
     const int k0 = DIA ? L.i * of.k : ptr[L.i], k1 = DIA ? k0 + of.k : ptr[L.i + 1];
     int steps = 0;
     // One step: blocks kb + u*S (u < U) of the row; colof(u, k) is block k's column,
-    // has(k) whether block k is stored.
-    auto step = [&](int kb, auto colof, auto has) {
+    // has(k) whether block k is stored, alt an in-range block of this row that is read
+    // anyway (a slot that is past the row's end or absent reads that block's values, at an
+    // address another lane fetches, and is masked out).  Every load of the step is issued
+    // unconditionally, so no branch forces a wait between the blocks' loads; conversions
+    // and products follow.
+    auto step = [&](int kb, auto colof, auto has, int alt) {
       int j[U], kk[U];
       bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = kb + u * S;
         ok[u] = k < k1 && has(k);
-        j[u] = ok[u] ? colof(u, k) : 0;
-        kk[u] = (ok[u] && TRANS) ? __builtin_nontemporal_load(blk + k) : k;
+        const int kc = k < k1 ? k : alt;
+        j[u] = colof(u, kc);
+        kk[u] = TRANS ? __builtin_nontemporal_load(blk + kc) : (ok[u] ? k : alt);
       }
-      TA v[U][RPL * BC], xv[U][BC];
+      VRaw<RPL * BC, TV> vr[U];
+      XRaw<XSrc, BC> xr[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (ok[u]) {
-          load_x<BC, TX, TA>(x + (size_t)j[u] * BC, xv[u]);
-          if constexpr (!TRANS) {
-            load_vals<RPL * BC, TV, TA, CACHED>(val + (size_t)kk[u] * (BR * BC) + L.r * BC,
-                                                v[u]);
-          } else {
-            // Block kk of A (BC x BR) read by columns: (A^T)[r][c] = A_kk[c][r].
-            const TV* b = val + (size_t)kk[u] * (BR * BC);
-#pragma unroll
-            for (int c = 0; c < BC; ++c) v[u][c] = load_val<TV, TA>(b + c * BR + L.r);
-          }
+        fetch_raw<BC>(x, j[u], xr[u]);
+        if constexpr (!TRANS) {
+          load_vals_raw<RPL * BC, TV, CACHED>(val + (size_t)kk[u] * (BR * BC) + L.r * BC, vr[u]);
         } else {
+          // Block kk of A (BC x BR) read by columns: (A^T)[r][c] = A_kk[c][r].
+          const TV* b = val + (size_t)kk[u] * (BR * BC);
+          if constexpr (sizeof(TV) == 2 && BC % 4 == 0) {
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(b);
 #pragma unroll
-          for (int c = 0; c < RPL * BC; ++c) v[u][c] = 0;
+            for (int c = 0; c < BC; c += 2)
+              vr[u].w[c / 2] = (uint32_t)__builtin_nontemporal_load(h + c * BR + L.r) |
+                               ((uint32_t)__builtin_nontemporal_load(h + (c + 1) * BR + L.r)
+                                << 16);
+          } else if constexpr (sizeof(TV) == 2) {
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(b);
 #pragma unroll
-          for (int c = 0; c < BC; ++c) xv[u][c] = 0;
+            for (int c = 0; c < BC; ++c) vr[u].v[c].u = __builtin_nontemporal_load(h + c * BR + L.r);
+          } else {
+#pragma unroll
+            for (int c = 0; c < BC; ++c) vr[u].v[c] = __builtin_nontemporal_load(b + c * BR + L.r);
+          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < U; ++u) {
+        TA v[RPL * BC], xv[BC];
+        finish_vals<RPL * BC, TV, TA>(vr[u], v);
+        finish_x<BC, TA>(x, xr[u], xv);
+        // masked slots contribute fma(0, 0, a) = a, as a zero block would
+#pragma unroll
+        for (int c = 0; c < RPL * BC; ++c) v[c] = ok[u] ? v[c] : TA(0);
+#pragma unroll
+        for (int c = 0; c < BC; ++c) xv[c] = ok[u] ? xv[c] : TA(0);
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
           TA& a = acc[q][u % T];
 #pragma unroll
-          for (int c = 0; c < BC; ++c) a = fma_(v[u][q * BC + c], xv[u][c], a);
+          for (int c = 0; c < BC; ++c) a = fma_(v[q * BC + c], xv[c], a);
         }
+      }
       if constexpr (T > U) {
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
@@ -344,6 +467,8 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
       int loff[NSLOT];
       dia_lane_offsets<S, NSLOT>(of, L.s, loff);
       const unsigned present = of.mask ? (unsigned)of.mask[L.i] : 0xffu;
+      // absent slots read the row's first stored block (fetched by another lane anyway)
+      const int alt = k0 + (present ? __builtin_ctz(present) : 0);
 #pragma unroll
       for (int st = 0; st < NSTEP; ++st) {
         const int kb = k0 + L.s + st * S * U;
@@ -355,12 +480,13 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
               const int c = L.i + loff[m < NSLOT ? m : 0];
               return c < 0 ? 0 : (c >= nbr ? nbr - 1 : c);
             },
-            [&](int k) { return ((present >> (k - k0)) & 1u) != 0; });
+            [&](int k) { return ((present >> (k - k0)) & 1u) != 0; }, alt);
         ++steps;
       }
     } else {
       for (int kb = k0 + L.s; kb < k1; kb += S * U, ++steps)
-        step(kb, [&](int, int k) { return ld_val<CACHED>(col + k); }, [](int) { return true; });
+        step(kb, [&](int, int k) { return ld_val<CACHED>(col + k); }, [](int) { return true; },
+             k1 > k0 ? k1 - 1 : 0);
     }
     if constexpr (T > U) {
       // undo the rotations: acc[.][t] now holds stripe (t + steps*U) mod T
