@@ -768,11 +768,20 @@ __global__ __launch_bounds__(WG) void k_block_diag(int nbr, int trans, const TM*
   const size_t i = row / B;
   const int r = (int)(row - i * B);
   const TM* m = M + i * B * B;
-  const TF* fi = f + i * B;
+  TA fv[B], mv[B];
+  load_x<B, TF, TA>(f + i * B, fv);
+  if (trans) {
+#pragma unroll
+    for (int c = 0; c < B; ++c) mv[c] = to_acc<TA>(m[c * B + r]);
+  } else if constexpr (B == 4) {
+    load_vals<B, TM, TA, true>(m + r * B, mv);   // the row, one vector load
+  } else {
+#pragma unroll
+    for (int c = 0; c < B; ++c) mv[c] = to_acc<TA>(m[r * B + c]);
+  }
   TA acc = 0;
 #pragma unroll
-  for (int c = 0; c < B; ++c)
-    acc = fma_(to_acc<TA>(trans ? m[c * B + r] : m[r * B + c]), (TA)fi[c], acc);
+  for (int c = 0; c < B; ++c) acc = fma_(mv[c], fv[c], acc);
   z[row] = (TX)acc;
 }
 

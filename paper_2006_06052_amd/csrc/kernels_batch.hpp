@@ -137,10 +137,17 @@ __global__ __launch_bounds__(WG) void k_g_block_diag(const GItem* __restrict__ i
     const size_t i = row / B;
     const int r = (int)(row - i * B);
     const TM* m = (const TM*)g.M + i * B * B;
-    const TF* fi = (const TF*)g.in + i * B;
+    TA fv[B], mv[B];
+    load_x<B, TF, TA>((const TF*)g.in + i * B, fv);
+    if constexpr (B == 4) {
+      load_vals<B, TM, TA, true>(m + r * B, mv);
+    } else {
+#pragma unroll
+      for (int c = 0; c < B; ++c) mv[c] = to_acc<TA>(m[r * B + c]);
+    }
     TA acc = 0;
 #pragma unroll
-    for (int c = 0; c < B; ++c) acc = fma_(to_acc<TA>(m[r * B + c]), (TA)fi[c], acc);
+    for (int c = 0; c < B; ++c) acc = fma_(mv[c], fv[c], acc);
     ((TX*)g.out)[row] = (TX)acc;
   }
 }
