@@ -866,20 +866,39 @@ enum FinOp {
 // partials [b*RED_CHUNK, (b+1)*RED_CHUNK) of one or two arrays of length count.
 constexpr int RED_CHUNK = 4096;
 
+// Sums of part[b0 .. b1) (and of part[count + b0 .. count + b1) when two) by the fixed
+// per-thread partition: thread t adds entries b0 + t + WG*(q + 4*it) into a[q], in
+// ascending it.  b1 - b0 <= RED_CHUNK, so every load (at most 16 per array) is issued
+// before the first addition (an out-of-range entry reads a clamped in-range one and is
+// not added).
+__device__ __forceinline__ void chunk_sums(const double* __restrict__ part, int count, int two,
+                                           int b0, int b1, double (&a)[4], double (&c)[4]) {
+  constexpr int IT = RED_CHUNK / (4 * WG);
+  double va[IT][4], vc[IT][4];
+  const int last = b1 > b0 ? b1 - 1 : b0;
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kq = min(b0 + (int)threadIdx.x + (4 * it + q) * WG, last);
+      va[it][q] = part[kq];
+      vc[it][q] = two ? part[count + kq] : 0.0;
+    }
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (b0 + (int)threadIdx.x + (4 * it + q) * WG < b1) {
+        a[q] += va[it][q];
+        c[q] += vc[it][q];
+      }
+}
+
 static __global__ __launch_bounds__(WG) void k_reduce_stage(const double* __restrict__ part, int count,
                                                      int two, double* __restrict__ out) {
   const int b0 = blockIdx.x * RED_CHUNK, b1 = min(count, b0 + RED_CHUNK);
   double a[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = b0 + threadIdx.x; k < b1; k += 4 * WG) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kq = k + q * WG;
-      if (kq < b1) {
-        a[q] += part[kq];
-        if (two) c[q] += part[count + kq];
-      }
-    }
-  }
+  chunk_sums(part, count, two, b0, b1, a, c);
   double sa = (a[0] + a[1]) + (a[2] + a[3]), sc = (c[0] + c[1]) + (c[2] + c[3]);
   wg_sum2(sa, sc);
   if (threadIdx.x == 0) {
@@ -892,16 +911,7 @@ static __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict
                                                  int two, int op, int i0, int i1,
                                                  double* __restrict__ sc) {
   double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < count; k += 4 * WG) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kq = k + q * WG;
-      if (kq < count) {
-        a[q] += part[kq];
-        if (two) b[q] += part[count + kq];
-      }
-    }
-  }
+  chunk_sums(part, count, two, 0, count, a, b);   // count <= RED_CHUNK
   double sa = (a[0] + a[1]) + (a[2] + a[3]), sb = (b[0] + b[1]) + (b[2] + b[3]);
   wg_sum2(sa, sb);
   if (threadIdx.x != 0) return;

@@ -495,11 +495,14 @@ static int maxiter_of(const mgk_solver* S) { return S->prm.maxiter; }
 
 void finalize(mgk_solver* S, int count, int two, int op, int i0, int i1, double* sc) {
   if (!sc) sc = S->sc;
+  // stages of RED_CHUNK partials each until one workgroup can finish (k_finalize reads at
+  // most RED_CHUNK); later stages ping-pong between part2 and the consumed part
   const double* src = S->part;
-  if (count > RED_CHUNK) {
+  double* dst[2] = {S->part2, S->part};
+  for (int w = 0; count > RED_CHUNK; w ^= 1) {
     const int nb = (count + RED_CHUNK - 1) / RED_CHUNK;
-    k_reduce_stage<<<nb, WG, 0, S->dev.stream>>>(S->part, count, two, S->part2);
-    src = S->part2;
+    k_reduce_stage<<<nb, WG, 0, S->dev.stream>>>(src, count, two, dst[w]);
+    src = dst[w];
     count = nb;
   }
   k_finalize<<<1, WG, 0, S->dev.stream>>>(src, count, two, op, i0, i1, sc);
