@@ -349,6 +349,13 @@ __device__ __forceinline__ void finish_x(const TX*, const XRaw<const TX*, BC>& r
   for (int c = 0; c < BC; ++c) out[c] = (TA)r.x[c];
 }
 
+// Stored-block bits of block row i of a diagonal-layout operator (all bits without a row
+// mask).  Kernels load it before their own operands, so that the row product's wait for it
+// does not also wait for those (memory results arrive in issue order).
+__device__ __forceinline__ unsigned dia_present(const DiaOffs& of, int i, int nbr) {
+  return of.mask ? (unsigned)of.mask[i < nbr ? i : nbr - 1] : 0xffu;
+}
+
 // Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
 // (BR/RPL)*S lanes.
 //
@@ -373,7 +380,8 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
                                               const int* __restrict__ blk,
                                               const TV* __restrict__ val,
                                               XSrc x, TA (&out)[RPL],
-                                              const DiaOffs& of = DiaOffs{}) {
+                                              const DiaOffs& of = DiaOffs{},
+                                              unsigned present = 0xffu) {
   constexpr int NS = BR == 1 ? 32 : 16;
   constexpr int T = NS / S;
   constexpr int LB = BR / RPL;
@@ -466,7 +474,7 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
       constexpr int NSLOT = (DIA_MAX + S - 1) / S, NSTEP = (NSLOT + U - 1) / U;
       int loff[NSLOT];
       dia_lane_offsets<S, NSLOT>(of, L.s, loff);
-      const unsigned present = of.mask ? (unsigned)of.mask[L.i] : 0xffu;
+      // present: the row's stored-block bits (dia_present), loaded by the caller
       // absent slots read the row's first stored block (fetched by another lane anyway)
       const int alt = k0 + (present ? __builtin_ctz(present) : 0);
 #pragma unroll
@@ -565,12 +573,13 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
+  const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
   // epilogue operands are loaded before the row product so their latency overlaps it
   TY yr[RPL];
   if (beta != TA(0)) load_ahead<RPL>(y, row0, own, yr);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
-                                                                    x, acc, of);
+                                                                    x, acc, of, pm);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -639,11 +648,12 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
     const int lim = L.i < rb1 ? nbr : 0;   // rows past this workgroup's range idle
     const bool own = L.active && L.s == 0 && L.i < rb1;
     const size_t row = (size_t)L.i * BR + L.r;
+    const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
     double wv[RPL];   // ahead of the product
     load_ahead<RPL, true>(w1, row, own, wv);
     double acc[RPL];
     row_product_r<BR, BC, S, U, TRANS, TV, TX, double, RPL, CACHED, DIA>(L, lim, ptr, col, blk,
-                                                                          val, x, acc, of);
+                                                                          val, x, acc, of, pm);
     if (own) {
       const int rl = L.i - rb0;
       const int q0 = (rl / DOT_ROWS) * NR + (rl % DOT_ROWS) * BR + L.r;
@@ -688,11 +698,12 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
+  const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
   TF fr[RPL];   // loaded ahead of the row product
   load_ahead<RPL>(f, row0, own, fr);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
-                                                                    z, acc, of);
+                                                                    z, acc, of, pm);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)((TA)fr[q] - acc[q]);
@@ -714,6 +725,7 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
+  const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
   // f, z and the lane's rows of M are loaded ahead of the row product
   TF fr[RPL];
   TX zr[RPL];
@@ -733,7 +745,7 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
   }
   TA acc[RPL];
   row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
-                                                                    z, acc, of);
+                                                                    z, acc, of, pm);
   TA res[RPL], zv[RPL], mv[RPL][BR];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
