@@ -349,11 +349,24 @@ __device__ __forceinline__ void finish_x(const TX*, const XRaw<const TX*, BC>& r
   for (int c = 0; c < BC; ++c) out[c] = (TA)r.x[c];
 }
 
-// Stored-block bits of block row i of a diagonal-layout operator (all bits without a row
-// mask).  Kernels load it before their own operands, so that the row product's wait for it
-// does not also wait for those (memory results arrive in issue order).
-__device__ __forceinline__ unsigned dia_present(const DiaOffs& of, int i, int nbr) {
-  return of.mask ? (unsigned)of.mask[i < nbr ? i : nbr - 1] : 0xffu;
+// A lane's block row as the row product walks it: blocks [k0, k1) (positions in the BSR
+// arrays, or slots of the diagonal layout) and, for the diagonal layout, its stored-block
+// bits (all bits without a row mask).
+struct RowRange {
+  int k0, k1;
+  unsigned present;
+};
+
+// Kernels load the range before their own operands, and keep the scheduler from moving
+// those loads above it (sched_barrier), so that the row product's wait for the range does
+// not also wait for them (memory results arrive in issue order).  Lanes past the last row
+// read an in-range row's entries (the row product skips them).
+template <bool DIA>
+__device__ __forceinline__ RowRange row_range(const int* __restrict__ ptr, const DiaOffs& of,
+                                              int i, int nbr) {
+  const int ic = i < nbr ? i : (nbr > 0 ? nbr - 1 : 0);
+  if constexpr (DIA) return RowRange{ic * of.k, ic * of.k + of.k, of.mask ? (unsigned)of.mask[ic] : 0xffu};
+  else return RowRange{ptr[ic], ptr[ic + 1], 0xffu};
 }
 
 // Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
@@ -380,8 +393,7 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
                                               const int* __restrict__ blk,
                                               const TV* __restrict__ val,
                                               XSrc x, TA (&out)[RPL],
-                                              const DiaOffs& of = DiaOffs{},
-                                              unsigned present = 0xffu) {
+                                              const DiaOffs& of, const RowRange& rr) {
   constexpr int NS = BR == 1 ? 32 : 16;
   constexpr int T = NS / S;
   constexpr int LB = BR / RPL;
@@ -394,7 +406,8 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
     for (int t = 0; t < T; ++t) acc[q][t] = 0;
   if (L.active && L.i < nbr) {
     // diagonal layout: the row's blocks are slots i*k .. i*k + k - 1, columns implied
-    const int k0 = DIA ? L.i * of.k : ptr[L.i], k1 = DIA ? k0 + of.k : ptr[L.i + 1];
+    const int k0 = rr.k0, k1 = rr.k1;
+    const unsigned present = rr.present;
     int steps = 0;
     // One step: blocks kb + u*S (u < U) of the row; colof(u, k) is block k's column,
     // has(k) whether block k is stored, alt an in-range block of this row that is read
@@ -474,7 +487,6 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
       constexpr int NSLOT = (DIA_MAX + S - 1) / S, NSTEP = (NSLOT + U - 1) / U;
       int loff[NSLOT];
       dia_lane_offsets<S, NSLOT>(of, L.s, loff);
-      // present: the row's stored-block bits (dia_present), loaded by the caller
       // absent slots read the row's first stored block (fetched by another lane anyway)
       const int alt = k0 + (present ? __builtin_ctz(present) : 0);
 #pragma unroll
@@ -528,7 +540,9 @@ __device__ __forceinline__ TA row_product(const LaneInfo& L, int nbr, const int*
                                           const int* __restrict__ col, const int* __restrict__ blk,
                                           const TV* __restrict__ val, const TX* __restrict__ x) {
   TA out[1];
-  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, 1, CACHED>(L, nbr, ptr, col, blk, val, x, out);
+  const RowRange rr = row_range<false>(ptr, DiaOffs{}, L.i, nbr);
+  row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, 1, CACHED>(L, nbr, ptr, col, blk, val, x, out,
+                                                             DiaOffs{}, rr);
   return out[0];
 }
 
@@ -573,13 +587,14 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
-  const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
+  const RowRange rr = row_range<DIA>(ptr, of, L.i, nbr);
+  __builtin_amdgcn_sched_barrier(0);
   // epilogue operands are loaded before the row product so their latency overlaps it
   TY yr[RPL];
   if (beta != TA(0)) load_ahead<RPL>(y, row0, own, yr);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
-                                                                    x, acc, of, pm);
+                                                                    x, acc, of, rr);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -648,12 +663,13 @@ __global__ __launch_bounds__(WG) void k_spmv_dot(int nbr, const int* __restrict_
     const int lim = L.i < rb1 ? nbr : 0;   // rows past this workgroup's range idle
     const bool own = L.active && L.s == 0 && L.i < rb1;
     const size_t row = (size_t)L.i * BR + L.r;
-    const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
+    const RowRange rr = row_range<DIA>(ptr, of, L.i, lim);
+    __builtin_amdgcn_sched_barrier(0);
     double wv[RPL];   // ahead of the product
     load_ahead<RPL, true>(w1, row, own, wv);
     double acc[RPL];
     row_product_r<BR, BC, S, U, TRANS, TV, TX, double, RPL, CACHED, DIA>(L, lim, ptr, col, blk,
-                                                                          val, x, acc, of, pm);
+                                                                          val, x, acc, of, rr);
     if (own) {
       const int rl = L.i - rb0;
       const int q0 = (rl / DOT_ROWS) * NR + (rl % DOT_ROWS) * BR + L.r;
@@ -698,12 +714,13 @@ __global__ __launch_bounds__(WG) void k_residual(int nbr, const int* __restrict_
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
-  const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
+  const RowRange rr = row_range<DIA>(ptr, of, L.i, nbr);
+  __builtin_amdgcn_sched_barrier(0);
   TF fr[RPL];   // loaded ahead of the row product
   load_ahead<RPL>(f, row0, own, fr);
   TA acc[RPL];
   row_product_r<BR, BC, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
-                                                                    z, acc, of, pm);
+                                                                    z, acc, of, rr);
   if (own) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) t[row0 + q] = (TX)((TA)fr[q] - acc[q]);
@@ -725,7 +742,8 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
   const LaneInfo L = lane_info<BR, S, RPL>(lw);
   const bool own = L.active && L.s == 0 && L.i < nbr;
   const size_t row0 = (size_t)L.i * BR + L.r;
-  const unsigned pm = DIA ? dia_present(of, L.i, nbr) : 0xffu;
+  const RowRange rr = row_range<DIA>(ptr, of, L.i, nbr);
+  __builtin_amdgcn_sched_barrier(0);
   // f, z and the lane's rows of M are loaded ahead of the row product
   TF fr[RPL];
   TX zr[RPL];
@@ -745,7 +763,7 @@ static __global__ __launch_bounds__(WG) void k_smooth(int nbr, const int* __rest
   }
   TA acc[RPL];
   row_product_r<BR, BR, S, U, TRANS, TV, TX, TA, RPL, CACHED, DIA>(L, nbr, ptr, col, blk, val,
-                                                                    z, acc, of, pm);
+                                                                    z, acc, of, rr);
   TA res[RPL], zv[RPL], mv[RPL][BR];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
