@@ -89,7 +89,9 @@ typedef struct {
   int32_t maxiter;         /* default 1000 (FGMRES: inner steps over all cycles) */
   int32_t max_restarts;    /* BiCGStab restarts after breakdown or a final true
                               residual above rtol, default 5 */
-  int32_t hier;            /* mgk_storage, default MGK_F64 */
+  int32_t hier;            /* mgk_storage of the preconditioner: the hierarchy's A_l, P_l,
+                              R_l and smoother blocks (ILU pivot inverses FP32 below FP64),
+                              vectors FP32 below FP64; default MGK_F64 */
   int32_t coarse_enough;   /* scalar unknowns at which coarsening stops, default 3000 */
   int32_t max_levels;      /* default 20 */
   int32_t block_spai0;     /* 1: block SPAI(0) (default), 0: scalar-row SPAI(0) */

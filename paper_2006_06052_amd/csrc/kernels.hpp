@@ -372,10 +372,10 @@ __device__ __forceinline__ RowRange row_range(const int* __restrict__ ptr, const
 // Rows r .. r+RPL-1 of block row i times x, for the lane (s, r) of a group of
 // (BR/RPL)*S lanes.
 //
-// Summation order, identical for every tile (S, U): block kr (kr-th stored
-// block of the row) is added, in ascending kr, to stripe kr mod NS (NS = 16,
-// or 32 for scalar rows); the NS stripes are then combined by the fixed tree
-// (q, q + NS/2), (q, q + NS/4), ..., (q, q + 1).  Lane s owns stripes
+// Summation order, identical for every tile (S, U, RPL): block kr (kr-th stored block of
+// the row, or kr-th slot of the diagonal layout) is added, in ascending kr, to stripe
+// kr mod NS (NS = 16, or 32 for scalar rows); the NS stripes are then combined by the
+// fixed tree (q, q + NS/2), (q, q + NS/4), ..., (q, q + 1).  Lane s owns stripes
 // s + S*t, t < T = NS/S: the upper tree levels are formed inside the lane and
 // the last log2(S) levels across lanes with shuffles.  Results are therefore
 // bitwise the same whatever tile the autotuner picks.
