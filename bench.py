@@ -36,11 +36,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernels_sha():
-    """Short hash of the kernel source, tagging counter profiles to the code they measured."""
+    """Short hash of the kernel source code (comment lines and blank lines left out, so that
+    editing a comment keeps it), tagging counter profiles to the code they measured."""
     import hashlib
     path = os.path.join(ROOT, "paper_2006_06052_amd", "csrc", "kernels.hpp")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(path) as f:
+        code = [ln.strip() for ln in f if ln.strip() and not ln.strip().startswith("//")]
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def log(*a):
