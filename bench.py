@@ -15,8 +15,9 @@ the speedup figures.
 
 The roofline entry is the FP64 4x4 BSR SpMV of the outer operator fused with the next
 Krylov dot products (two launches per BiCGStab iteration, the largest single kernel of
-the solve): every launch inside the timed solves is bracketed by HIP events on the
-library's stream, and the average duration is set against the algorithmic bytes per
+the solve): every launch inside the timed solves records HIP start and stop events on the
+library's stream through its own dispatch (hipExtLaunchKernelGGL), and the average
+duration is set against the algorithmic bytes per
 launch, nnzb*(16*8 + 4) + 4*(n_brows + 1) + 2*n_brows*4*8 for y = A x plus 8*n for the
 dot weight vector the fused kernel reads.
 """

@@ -102,9 +102,10 @@ typedef struct {
                               mgk_level_export (default 0) */
   int32_t enable_transpose;/* 1: build the A^T indices for adjoint solves (default 0) */
   int32_t time_spmv;       /* bit mask: 1 times every outer-operator SpMV of a solve
-                              (mgk_info.spmv_ms), 2 every preconditioner application
-                              (mgk_info.precond_ms), with HIP events on the solver's
-                              stream around each launch sequence */
+                              (mgk_info.spmv_ms; the fused SpMV-and-dots kernels record their
+                              own start and end events through their dispatch, other products
+                              are bracketed by events), 2 every preconditioner application
+                              (mgk_info.precond_ms, bracketed), on the solver's stream */
   int32_t force_tile;      /* 0: the autotuner picks each operator's kernel tile;
                               otherwise 10000*RPL + 100*S + U (S lanes per block row, U
                               blocks per step, RPL scalar rows per lane) for every

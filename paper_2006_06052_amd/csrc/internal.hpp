@@ -19,6 +19,7 @@
 //   the Schur pressure correction: one velocity cycle, the pressure cycle on
 //     r_p - B_lo z_u, and a second velocity cycle on r_u - B_up z_p (Section 4,
 //     eqs. SchurP and SchurU).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -367,9 +368,21 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, 
 
 // y = A x (FP64) with the fused partials of <w1, y> and, when two, <y, y>;
 // returns the number of partials written per dot (one per group of dot_rows block rows).
+// Launch on WG-thread workgroups; with events, the dispatch itself records the kernel's
+// start and end in them (its execution time alone, as a kernel trace reports it).
+template <class K, class... Args>
+static void launch_ev(K kernel, int g, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                      Args... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kernel, dim3(g), dim3(WG), 0, st, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, dim3(g), dim3(WG), 0, st, args...);
+}
+
 template <int BR, int BC>
 static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile,
-                      const double* x, double* y, int two, const double* w1, double* part) {
+                      const double* x, double* y, int two, const double* w1, double* part,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int nrows = trans ? M.nbc : M.nbr;
   const int* p = trans ? M.tptr : M.ptr;
   const int* c = trans ? M.trow : M.col;
@@ -380,9 +393,8 @@ static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& til
       constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value;
       constexpr int WR = dot_wg_rows<BR, S_, 1>();
       const int g = std::max(1, (nrows + WR - 1) / WR);
-      k_spmv_dot<BR, BC, S_, U_, true, double, double><<<g, WG, 0, st>>>(nrows, p, c, b, v, x,
-                                                                         y, two, w1, part,
-                                                                         DiaOffs{});
+      launch_ev(k_spmv_dot<BR, BC, S_, U_, true, double, double>, g, st, e0, e1, nrows, p, c, b,
+                v, x, y, two, w1, part, DiaOffs{});
     });
   } else {
     tile_switch_r<BR, wide_ok<BR, BC, double>()>(tile, [&](auto SS, auto UU, auto RR) {
@@ -393,20 +405,20 @@ static int spmv_dot_s(hipStream_t st, const DMat& M, bool trans, const Tile& til
         if (M.dia.k) {
           const double* dv = (const double*)M.dval;
           if (M.cached)
-            k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, true, true><<<g, WG, 0, st>>>(
-                nrows, p, c, b, dv, x, y, two, w1, part, M.dia);
+            launch_ev(k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, true, true>, g, st,
+                      e0, e1, nrows, p, c, b, dv, x, y, two, w1, part, M.dia);
           else
-            k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, false, true><<<g, WG, 0, st>>>(
-                nrows, p, c, b, dv, x, y, two, w1, part, M.dia);
+            launch_ev(k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, false, true>, g, st,
+                      e0, e1, nrows, p, c, b, dv, x, y, two, w1, part, M.dia);
           return;
         }
       }
       if (M.cached)
-        k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, true><<<g, WG, 0, st>>>(
-            nrows, p, c, b, v, x, y, two, w1, part, DiaOffs{});
+        launch_ev(k_spmv_dot<BR, BC, S_, U_, false, double, double, R_, true>, g, st, e0, e1,
+                  nrows, p, c, b, v, x, y, two, w1, part, DiaOffs{});
       else
-        k_spmv_dot<BR, BC, S_, U_, false, double, double, R_><<<g, WG, 0, st>>>(
-            nrows, p, c, b, v, x, y, two, w1, part, DiaOffs{});
+        launch_ev(k_spmv_dot<BR, BC, S_, U_, false, double, double, R_>, g, st, e0, e1, nrows, p,
+                  c, b, v, x, y, two, w1, part, DiaOffs{});
     });
   }
   return std::max(1, (nrows + dot_rows<BR>() - 1) / dot_rows<BR>());

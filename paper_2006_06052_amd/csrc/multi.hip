@@ -169,15 +169,18 @@ static int outer_spmm_dot(mgk_solver* S, int K, const double* X, double* Y, int 
   const int g = (S->nbr + MROWS - 1) / MROWS;
   const DMat& A = S->A;
   double* part = S->multi->part;
+  // with time_spmv, the kernel's dispatch records its own start and end
   const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
-  if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
+  hipEvent_t e0 = timed ? S->tev[S->tev_used] : nullptr;
+  hipEvent_t e1 = timed ? S->tev[S->tev_used + 1] : nullptr;
+  const double* v = (const double*)A.val;
   switch (S->b) {
-    case 1: k_spmm_dot<1><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
-    case 3: k_spmm_dot<3><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
-    case 4: k_spmm_dot<4><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, X, Y, two, W1, part); break;
+    case 1: launch_ev(k_spmm_dot<1>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part); break;
+    case 3: launch_ev(k_spmm_dot<3>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part); break;
+    case 4: launch_ev(k_spmm_dot<4>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part); break;
   }
   if (timed) {
-    HIPCK(hipEventRecord(S->tev[S->tev_used + 1], st));
+    HIPCK(hipGetLastError());
     S->tev_used += 2;
   }
   return g;

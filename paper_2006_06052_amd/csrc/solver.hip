@@ -383,26 +383,31 @@ void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots,
                 const double* w1, int* nwg) {
   hipStream_t st = S->dev.stream;
   const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
-  if (timed) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
+  // the fused kernel's own dispatch records its start and end; the plain product (one or
+  // more launches) is bracketed by event records on the stream
+  hipEvent_t e0 = timed && dots ? S->tev[S->tev_used] : nullptr;
+  hipEvent_t e1 = timed && dots ? S->tev[S->tev_used + 1] : nullptr;
+  if (timed && !dots) HIPCK(hipEventRecord(S->tev[S->tev_used], st));
   const Tile sp = trans ? S->A.ttile : (dots ? S->A.dtile : S->A.tile);
   int g = 0;
   switch (S->b) {
     case 1:
-      if (dots) g = spmv_dot_s<1, 1>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part);
+      if (dots) g = spmv_dot_s<1, 1>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part, e0, e1);
       else spmv_s<1, 1, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0);
       break;
     case 3:
-      if (dots) g = spmv_dot_s<3, 3>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part);
+      if (dots) g = spmv_dot_s<3, 3>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part, e0, e1);
       else spmv_s<3, 3, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0);
       break;
     case 4:
-      if (dots) g = spmv_dot_s<4, 4>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part);
+      if (dots) g = spmv_dot_s<4, 4>(st, S->A, trans, sp, x, y, dots == 2, w1, S->part, e0, e1);
       else spmv_s<4, 4, double, double, double>(st, S->A, trans, sp, x, y, 1.0, 0.0);
       break;
   }
   if (nwg) *nwg = g;
   if (timed) {
-    HIPCK(hipEventRecord(S->tev[S->tev_used + 1], st));
+    if (!dots) HIPCK(hipEventRecord(S->tev[S->tev_used + 1], st));
+    HIPCK(hipGetLastError());
     S->tev_used += 2;
   }
 }
