@@ -41,6 +41,30 @@ __device__ __forceinline__ MRow mrow(int lw) {
   return m;
 }
 
+// Order in which the workgroups of a product over a structured-grid operator take their
+// 8-row blocks.  With the largest block-diagonal offset P (a grid plane: rows i and i +- P
+// read the same x rows), the linear order reuses an x row only after about P further rows,
+// which for K right-hand sides of FP64 is far more than one XCD's L2 holds, so x would be
+// fetched three times.  Instead the rows of every plane are cut into 8 tiles of tb blocks,
+// and XCD t takes tile t of plane 0, 1, 2, ... in turn: a row's z-neighbours are read a few
+// hundred rows apart.  pb = P / 8 blocks per plane, np planes; tb = 0 keeps the linear
+// order.  Only the schedule changes: each row's sums and the per-block dot partials (stored
+// by block index) are the same.
+struct MSched {
+  int pb, tb, np;
+};
+
+// Row block of logical workgroup lw (after the XCD remap over the 8 * np * tb workgroups,
+// XCD t holds the contiguous range of tile t), or -1 for a slot past a plane's last tile.
+__device__ __forceinline__ int msched_block(int lw, const MSched& ms) {
+  if (ms.tb == 0) return lw;
+  const int per = ms.np * ms.tb;
+  const int t = lw / per, rem = lw - t * per;
+  const int p = rem / ms.tb, u = rem - p * ms.tb;
+  const int q = t * ms.tb + u;
+  return q < ms.pb ? p * ms.pb + q : -1;
+}
+
 template <int B, class TV, class TA>
 __device__ __forceinline__ void load_block(const TV* __restrict__ p, TA* out) {
   if constexpr (sizeof(TV) == 2) {
@@ -156,14 +180,104 @@ __device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool o
   }
 }
 
-// The lane's B entries p[(i*B + r)*K + k] (r < B) of an [n][K] operand, loaded ahead of
-// the row product by every lane (lanes without a row or column read entry 0), so that no
-// branch puts a wait for them before the product's loads.
-template <int B, class T>
-__device__ __forceinline__ void load_rows_ahead(const T* __restrict__ p, bool on, int i, int k,
-                                                int K, T (&out)[B]) {
+// The same product on the diagonal layout (DiaOffs; val holds n_brows x of.k blocks).
+// The workgroup's 8 rows own one contiguous range of of.k blocks per row, staged in LDS.
+// Every load is issued up front and unconditionally, in this order: the row's stored-slot
+// mask, the values, the x rows of all DIA_MAX slots (the column i + o[d] is known without
+// reading anything; a slot past the row's count or the matrix edge reads row i's own x),
+// then the caller's epilogue operands (pre()).  Memory results return in issue order, so
+// the wait that lets the values reach LDS leaves every x and epilogue load in flight.  A
+// slot the row does not store is skipped at the FMA, so the row sums its stored blocks in
+// ascending column order, as the walk over its BSR row does: the two are bitwise equal.
+template <int BR, class TV, class TX, class TA, class Pre>
+__device__ __forceinline__ void block_rows_dia(int r0, int nbr, int i, bool on, int k, int K,
+                                               const DiaOffs& of, const TV* __restrict__ val,
+                                               const TX* __restrict__ X, TA* acc, Pre&& pre) {
+  constexpr int BB = BR * BR;
+  constexpr int CAP = MROWS * DIA_MAX * BB;
+  constexpr int NV = (CAP + WG - 1) / WG;
+  typedef typename std::conditional<sizeof(TV) == 2, uint16_t, TV>::type TS;
+  // every lane stores all NV of its loads (entries past the range hold copies of entry 0
+  // and are never read), so no load is sunk into a branch after the x loads
+  __shared__ TS s_val[NV * WG];
+  const int kd = of.k;
+  const int ic = i < nbr ? i : nbr - 1;
+  const int kk = k < K ? k : 0;
+  const int nrow = min(MROWS, nbr - r0);
+  const int cnt = nrow * kd * BB;
+  const TS* g = reinterpret_cast<const TS*>(val) + (size_t)r0 * kd * BB;
+  // with no mask every row stores every slot; the byte is then read from the values
+  const uint8_t* mp = of.mask ? of.mask + ic : reinterpret_cast<const uint8_t*>(g);
+  const unsigned mbyte = *mp;
+  TS tv[NV];
 #pragma unroll
-  for (int r = 0; r < B; ++r) out[r] = p[on ? ((size_t)i * B + r) * K + k : 0];
+  for (int u = 0; u < NV; ++u) {
+    const int q = threadIdx.x + u * WG;
+    tv[u] = g[q < cnt ? q : 0];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  TX xr[DIA_MAX][BR];
+#pragma unroll
+  for (int d = 0; d < DIA_MAX; ++d) {
+    const int j = ic + of.o[d];
+    const int jc = (d < kd && j >= 0 && j < nbr) ? j : ic;
+#pragma unroll
+    for (int c = 0; c < BR; ++c) xr[d][c] = X[((size_t)jc * BR + c) * K + kk];
+  }
+  pre();
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < NV; ++u) s_val[threadIdx.x + u * WG] = tv[u];
+  __syncthreads();
+  const unsigned present = of.mask ? mbyte : 0xffu;
+#pragma unroll
+  for (int r = 0; r < BR; ++r) acc[r] = 0;
+  const TS* rowv = s_val + (i - r0 < nrow ? i - r0 : 0) * kd * BB;
+#pragma unroll
+  for (int d = 0; d < DIA_MAX; ++d) {
+    if (d < kd) {
+      TA a[BB];
+      load_block<BR, TV, TA>(reinterpret_cast<const TV*>(rowv + d * BB), a);
+      const bool use = on && ((present >> d) & 1u);
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        TA t = acc[r];
+#pragma unroll
+        for (int c = 0; c < BR; ++c) t = fma_(a[r * BR + c], (TA)xr[d][c], t);
+        acc[r] = use ? t : acc[r];
+      }
+    }
+  }
+}
+
+// Row product of a square operator in either layout (DIA: val is the diagonal layout's);
+// pre() issues the caller's epilogue loads (first for the BSR walk, whose x loads wait for
+// column indices anyway; after the x loads on the diagonal layout).
+template <int B, class TV, class TX, class TA, bool DIA, class Pre>
+__device__ __forceinline__ void block_rows(int r0, int nbr, int i, bool on, int k, int K,
+                                           const int* __restrict__ ptr,
+                                           const int* __restrict__ col,
+                                           const TV* __restrict__ val, const DiaOffs& of,
+                                           const TX* __restrict__ X, TA* acc, Pre&& pre) {
+  if constexpr (DIA) {
+    block_rows_dia<B, TV, TX, TA>(r0, nbr, i, on, k, K, of, val, X, acc, pre);
+  } else {
+    pre();
+    block_rows_staged<B, B, TV, TX, TA>(r0, nbr, i, on, k, K, ptr, col, val, X, acc);
+  }
+}
+
+// The lane's B entries p[(i*B + r)*K + k] (r < B) of an [n][K] operand, loaded ahead of
+// the row product by every lane (a lane past the last row or right-hand side reads the
+// last row's or column 0's entries: no branch and no constant address, so no wait for
+// these loads is put before the product's loads).
+template <int B, class T>
+__device__ __forceinline__ void load_rows_ahead(const T* __restrict__ p, int nbr, int i, int k,
+                                                int K, T (&out)[B]) {
+  const int ic = i < nbr ? i : nbr - 1;
+  const int kk = k < K ? k : 0;
+#pragma unroll
+  for (int r = 0; r < B; ++r) out[r] = p[((size_t)ic * B + r) * K + kk];
 }
 
 // Block M_i of a block-diagonal matrix for the lane's row, both rows' blocks
@@ -190,7 +304,7 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
   TY yr[BR];
-  if (beta != TA(0)) load_rows_ahead<BR>(Y, on, i, k, K, yr);
+  if (beta != TA(0)) load_rows_ahead<BR>(Y, nbr, i, k, K, yr);
   TA acc[BR];
   block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, X, acc);
   if (!on) return;
@@ -204,25 +318,28 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
 }
 
 // Y = A X (FP64) with per-column partials of <W1_k, Y_k> and (two) <Y_k, Y_k>:
-// part[w * KL + k] and part[(G + w) * KL + k] for workgroup w of G (the
-// workgroup's 8 rows summed in order).
-template <int B>
+// part[w * KL + k] and part[(G + w) * KL + k] for row block w of G = ceil(nbr / 8) (the
+// block's 8 rows summed in order).
+template <int B, bool DIA>
 __global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const double* __restrict__ val,
                                                  const double* __restrict__ X,
                                                  double* __restrict__ Y, int two,
                                                  const double* __restrict__ W1,
-                                                 double* __restrict__ part) {
-  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+                                                 double* __restrict__ part, DiaOffs of,
+                                                 MSched ms) {
+  const int lw = msched_block(xcd_remap(blockIdx.x, gridDim.x), ms);
+  if (lw < 0 || lw * MROWS >= nbr) return;
+  const int G = (nbr + MROWS - 1) / MROWS;
   const MRow m = mrow(lw);
   const bool on = m.i < nbr && m.k < K;
   double d1 = 0.0, d2 = 0.0;
   double w[B];
-  load_rows_ahead<B>(W1, on, m.i, m.k, K, w);
   double acc[B];
-  block_rows_staged<B, B, double, double, double>(lw * MROWS, nbr, m.i, on, m.k, K, ptr, col, val,
-                                                  X, acc);
+  block_rows<B, double, double, double, DIA>(lw * MROWS, nbr, m.i, on, m.k, K, ptr, col, val,
+                                             of, X, acc,
+                                             [&] { load_rows_ahead<B>(W1, nbr, m.i, m.k, K, w); });
   if (on) {
 #pragma unroll
     for (int r = 0; r < B; ++r) {
@@ -244,23 +361,35 @@ __global__ __launch_bounds__(WG) void k_spmm_dot(int nbr, int K, const int* __re
       y += sb[q * KL + threadIdx.x];
     }
     part[(size_t)lw * KL + threadIdx.x] = x;
-    if (two) part[(size_t)(gridDim.x + lw) * KL + threadIdx.x] = y;
+    if (two) part[(size_t)(G + lw) * KL + threadIdx.x] = y;
   }
 }
 
 // First reduction stage for per-column partials: workgroup b sums partial rows
-// [b*1024, (b+1)*1024) of one or two arrays of `count` rows (32 lanes per column,
-// 8 row slots, fixed order).
-constexpr int MRED_CHUNK = 1024;
+// [b*128, (b+1)*128) of one or two arrays of `count` rows (32 lanes per column,
+// 8 row slots each summing 16 rows in ascending order with every load issued first,
+// then the 8 slots in order).
+constexpr int MRED_CHUNK = 128;
 
 static __global__ __launch_bounds__(WG) void k_reduce_stage_m(const double* __restrict__ part, int count,
                                                        int two, double* __restrict__ out) {
+  constexpr int PER = MRED_CHUNK / MROWS;
   const int k = threadIdx.x % KL, q0 = threadIdx.x / KL;
-  const int b0 = blockIdx.x * MRED_CHUNK, b1 = min(count, b0 + MRED_CHUNK);
+  const int b0 = blockIdx.x * MRED_CHUNK;
+  double va[PER], vc[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = b0 + q0 + u * MROWS;
+    va[u] = q < count ? part[(size_t)q * KL + k] : 0.0;
+    vc[u] = (two && q < count) ? part[(size_t)(count + q) * KL + k] : 0.0;
+  }
   double a = 0.0, c = 0.0;
-  for (int q = b0 + q0; q < b1; q += MROWS) {
-    a += part[(size_t)q * KL + k];
-    if (two) c += part[(size_t)(count + q) * KL + k];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (b0 + q0 + u * MROWS < count) {
+      a += va[u];
+      c += vc[u];
+    }
   }
   __shared__ double sa[WG], sb[WG];
   sa[threadIdx.x] = a;
@@ -278,53 +407,57 @@ static __global__ __launch_bounds__(WG) void k_reduce_stage_m(const double* __re
 }
 
 // T = F - A Z.
-template <int BR, int BC, class TV, class TX, class TF, class TA>
+template <int B, class TV, class TX, class TF, class TA, bool DIA>
 __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __restrict__ ptr,
                                                    const int* __restrict__ col,
                                                    const TV* __restrict__ val,
                                                    const TF* __restrict__ F,
                                                    const TX* __restrict__ Z,
-                                                   TX* __restrict__ T) {
-  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+                                                   TX* __restrict__ T, DiaOffs of, MSched ms) {
+  const int lw = msched_block(xcd_remap(blockIdx.x, gridDim.x), ms);
+  if (lw < 0 || lw * MROWS >= nbr) return;
   const MRow m = mrow(lw);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
-  TF fr[BR];
-  load_rows_ahead<BR>(F, on, i, k, K, fr);
-  TA acc[BR];
-  block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, Z, acc);
+  TF fr[B];
+  TA acc[B];
+  block_rows<B, TV, TX, TA, DIA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, of, Z, acc,
+                                 [&] { load_rows_ahead<B>(F, nbr, i, k, K, fr); });
   if (!on) return;
 #pragma unroll
-  for (int r = 0; r < BR; ++r) {
-    const size_t e = ((size_t)i * BR + r) * K + k;
+  for (int r = 0; r < B; ++r) {
+    const size_t e = ((size_t)i * B + r) * K + k;
     T[e] = (TX)((TA)fr[r] - acc[r]);
   }
 }
 
 // Zout = Z + M (F - A Z), M block diagonal.
-template <int B, class TV, class TX, class TF, class TO, class TM, class TA>
+template <int B, class TV, class TX, class TF, class TO, class TM, class TA, bool DIA>
 __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const TV* __restrict__ val,
                                                  const TM* __restrict__ M,
                                                  const TF* __restrict__ F,
                                                  const TX* __restrict__ Z,
-                                                 TO* __restrict__ Zout) {
-  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+                                                 TO* __restrict__ Zout, DiaOffs of, MSched ms) {
+  const int lw = msched_block(xcd_remap(blockIdx.x, gridDim.x), ms);
+  if (lw < 0 || lw * MROWS >= nbr) return;
   const MRow m = mrow(lw);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
   TF fr[B];
   TX zr[B];
-  load_rows_ahead<B>(F, on, i, k, K, fr);
-  load_rows_ahead<B>(Z, on, i, k, K, zr);
-  // M blocks ahead of the product too; a wavefront whose rows lie past nbr reads row 0's
+  // M blocks (scalar loads) ahead of the product too; a wavefront whose rows lie past nbr
+  // reads row 0's
   MRow mc = m;
   if (mc.i0 >= nbr) mc.i0 = 0;
   TA mb[B * B];
   diag_block<B, TM, TA>(mc, mc.i0 + 1 < nbr, M, mb);
   TA acc[B];
-  block_rows_staged<B, B, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, Z, acc);
+  block_rows<B, TV, TX, TA, DIA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, of, Z, acc, [&] {
+    load_rows_ahead<B>(F, nbr, i, k, K, fr);
+    load_rows_ahead<B>(Z, nbr, i, k, K, zr);
+  });
   if (!on) return;
   TA res[B];
 #pragma unroll
@@ -362,29 +495,43 @@ __global__ __launch_bounds__(WG) void k_block_diag_m(int nbr, int K, const TM* _
   }
 }
 
-// Z = Cinv R for the dense FP64 coarsest inverse (n x n), R and Z [n][K]:
-// 8 rows of Z per workgroup, lane k per right-hand side, j ascending.
+// Z = Cinv R for the dense FP64 coarsest inverse (n x n), R and Z [n][K]: one
+// workgroup per row i of Z.  Half-wavefront q of 8 takes the contiguous slice
+// [q c, (q + 1) c) of the row (c = ceil(n / 8)) and sums it in ascending order for
+// right-hand side k = lane & 31, eight entries' loads issued per step; the 8 slice
+// sums are then added in slice order.
 template <class TI, class TO>
 __global__ __launch_bounds__(WG) void k_coarse_gemm(int n, int K, const double* __restrict__ Cinv,
                                                     const TI* __restrict__ R,
                                                     TO* __restrict__ Z) {
-  const int i = blockIdx.x * MROWS + threadIdx.x / KL;
-  const int k = threadIdx.x % KL;
-  if (i >= n || k >= K) return;
+  constexpr int U = 8;
+  const int i = blockIdx.x;
+  const int k = threadIdx.x % KL, q = threadIdx.x / KL;
+  const int kk = k < K ? k : 0;
+  const int c = (n + MROWS - 1) / MROWS;
+  const int j0 = min(n, q * c), j1 = min(n, j0 + c);
   const double* a = Cinv + (size_t)i * n;
   double acc = 0.0;
-  int j = 0;
-  for (; j + 4 <= n; j += 4) {
-    const double a0 = a[j], a1 = a[j + 1], a2 = a[j + 2], a3 = a[j + 3];
-    const double r0 = (double)R[(size_t)j * K + k], r1 = (double)R[(size_t)(j + 1) * K + k];
-    const double r2 = (double)R[(size_t)(j + 2) * K + k], r3 = (double)R[(size_t)(j + 3) * K + k];
-    acc = fma_(a0, r0, acc);
-    acc = fma_(a1, r1, acc);
-    acc = fma_(a2, r2, acc);
-    acc = fma_(a3, r3, acc);
+  int j = j0;
+  for (; j + U <= j1; j += U) {
+    double av[U], rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = a[j + u];
+      rv[u] = (double)R[(size_t)(j + u) * K + kk];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = fma_(av[u], rv[u], acc);
   }
-  for (; j < n; ++j) acc = fma_(a[j], (double)R[(size_t)j * K + k], acc);
-  Z[(size_t)i * K + k] = (TO)acc;
+  for (; j < j1; ++j) acc = fma_(a[j], (double)R[(size_t)j * K + kk], acc);
+  __shared__ double sq[WG];
+  sq[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < KL && k < K) {
+    double z = 0.0;
+    for (int t = 0; t < MROWS; ++t) z += sq[t * KL + threadIdx.x];
+    Z[(size_t)i * K + k] = (TO)z;
+  }
 }
 
 // ---- per-column Krylov kernels (FP64) ----------------------------------------
@@ -488,13 +635,13 @@ static __global__ __launch_bounds__(WG) void k_bicg_p_m(size_t n, int K, const i
   }
 }
 
-// s = r - alpha v; x += alpha phat (active columns); partials of ||s||^2.
+// s = r - alpha v (active columns); partials of ||s||^2.  (x += alpha phat is deferred to
+// k_bicg_xr_m, or to k_bicg_x_m for the columns that stop at s.)
 static __global__ __launch_bounds__(WG) void k_bicg_s_m(size_t n, int K, const int* __restrict__ active,
                                                  const double* __restrict__ scm,
                                                  const double* __restrict__ r,
                                                  const double* __restrict__ v,
-                                                 const double* __restrict__ ph,
-                                                 double* __restrict__ s, double* __restrict__ x,
+                                                 double* __restrict__ s,
                                                  double* __restrict__ part) {
   const int k = threadIdx.x % KL;
   double ss = 0.0;
@@ -504,18 +651,33 @@ static __global__ __launch_bounds__(WG) void k_bicg_s_m(size_t n, int K, const i
       const size_t e = row * K + k;
       const double si = r[e] - al * v[e];
       s[e] = si;
-      x[e] += al * ph[e];
       ss = fma_(si, si, ss);
     }
   }
   col_sum2(ss, 0.0, 0, part, blockIdx.x, gridDim.x);
 }
 
-// x += omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
+// x += alpha phat for the columns flagged in mask (they stopped at s).
+static __global__ __launch_bounds__(WG) void k_bicg_x_m(size_t n, int K, const int* __restrict__ mask,
+                                                 const double* __restrict__ scm,
+                                                 const double* __restrict__ ph,
+                                                 double* __restrict__ x) {
+  const int k = threadIdx.x % KL;
+  if (k >= K || !mask[k]) return;
+  const double al = scm[SM_ALPHA * KL + k];
+  MROW_STRIDE(row, n) {
+    const size_t e = row * K + k;
+    x[e] += al * ph[e];
+  }
+}
+
+// x = (x + alpha phat) + omega shat; r = s - omega t; partials of ||r||^2 and (rhat, r).
+// One pass over x per iteration, with the two additions in the order of the two updates.
 static __global__ __launch_bounds__(WG) void k_bicg_xr_m(size_t n, int K, const int* __restrict__ active,
                                                   const double* __restrict__ scm,
                                                   const double* __restrict__ s,
                                                   const double* __restrict__ t,
+                                                  const double* __restrict__ ph,
                                                   const double* __restrict__ sh,
                                                   const double* __restrict__ rh,
                                                   double* __restrict__ x, double* __restrict__ r,
@@ -523,10 +685,10 @@ static __global__ __launch_bounds__(WG) void k_bicg_xr_m(size_t n, int K, const 
   const int k = threadIdx.x % KL;
   double rr = 0.0, rho = 0.0;
   if (k < K && active[k]) {
-    const double om = scm[SM_OMEGA * KL + k];
+    const double al = scm[SM_ALPHA * KL + k], om = scm[SM_OMEGA * KL + k];
     MROW_STRIDE(row, n) {
       const size_t e = row * K + k;
-      x[e] += om * sh[e];
+      x[e] = (x[e] + al * ph[e]) + om * sh[e];
       const double ri = s[e] - om * t[e];
       r[e] = ri;
       rr = fma_(ri, ri, rr);

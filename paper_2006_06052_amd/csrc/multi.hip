@@ -90,6 +90,22 @@ static MultiWork* ensure_multi(mgk_solver* S) {
   return W;
 }
 
+// Plane-tiled workgroup order for a diagonal-layout operator whose largest offset P (a
+// grid plane) is a multiple of 8 rows and at least 1024; the linear order otherwise.
+// Returns the grid size (8 tiles x planes x tile width, holes included).
+static int msched_of(const DMat& A, MSched& ms) {
+  ms = MSched{0, 0, 0};
+  const int g = (A.nbr + MROWS - 1) / MROWS;
+  if (A.dia.k == 0) return g;
+  int P = 0;
+  for (int d = 0; d < A.dia.k; ++d) P = std::max(P, std::abs(A.dia.o[d]));
+  if (P % MROWS != 0 || P < 1024) return g;
+  ms.pb = P / MROWS;
+  ms.tb = (ms.pb + 7) / 8;
+  ms.np = (g + ms.pb - 1) / ms.pb;
+  return 8 * ms.np * ms.tb;
+}
+
 // ---------------------------------------------------------------- multi V-cycle
 
 template <int B, class TV, class TX>
@@ -103,8 +119,7 @@ struct CycleM {
     DLevel& L = H.lv[l];
     const int nl = (int)H.lv.size();
     if (l == nl - 1) {
-      k_coarse_gemm<TIN, TOUT><<<(H.nc + MROWS - 1) / MROWS, WG, 0, st>>>(H.nc, K, H.cinv, r,
-                                                                          zout);
+      k_coarse_gemm<TIN, TOUT><<<H.nc, WG, 0, st>>>(H.nc, K, H.cinv, r, zout);
       return;
     }
     TX* z = (TX*)W.lv[l].z;
@@ -112,9 +127,19 @@ struct CycleM {
     MLevel& C = W.lv[l + 1];
     const int g = (L.nbr + MROWS - 1) / MROWS;
     const int gr = (L.R.nbr + MROWS - 1) / MROWS;
+    // a square operator stored in the diagonal layout is read in it (same sums, bitwise),
+    // its row blocks taken in the plane-tiled order
+    const bool dia = (B == 3 || B == 4) && L.A.dia.k > 0;
+    const TV* av = (const TV*)(dia ? L.A.dval : L.A.val);
+    MSched ms;
+    const int gd = msched_of(L.A, ms);
     k_block_diag_m<B, TM, TIN, TX, TA><<<g, WG, 0, st>>>(L.nbr, K, (const TM*)L.M, r, z);
-    k_residual_m<B, B, TV, TX, TIN, TA><<<g, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col,
-                                                           (const TV*)L.A.val, r, z, t);
+    if (dia)
+      k_residual_m<B, TV, TX, TIN, TA, true><<<gd, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col, av,
+                                                                r, z, t, L.A.dia, ms);
+    else
+      k_residual_m<B, TV, TX, TIN, TA, false><<<g, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col, av,
+                                                                r, z, t, DiaOffs{}, MSched{});
     k_spmm<B, B, TV, TX, TX, TA><<<gr, WG, 0, st>>>(L.R.nbr, K, L.R.ptr, L.R.col,
                                                     (const TV*)L.R.val, t, (TX*)C.r, TA(1),
                                                     TA(0));
@@ -122,8 +147,12 @@ struct CycleM {
     run<TX, TX>(st, H, W, l + 1, K, (const TX*)C.r, zc);
     k_spmm<B, B, TV, TX, TX, TA><<<g, WG, 0, st>>>(L.P.nbr, K, L.P.ptr, L.P.col,
                                                    (const TV*)L.P.val, zc, z, TA(1), TA(1));
-    k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA><<<g, WG, 0, st>>>(
-        L.nbr, K, L.A.ptr, L.A.col, (const TV*)L.A.val, (const TM*)L.M, r, z, zout);
+    if (dia)
+      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, true><<<gd, WG, 0, st>>>(
+          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, L.A.dia, ms);
+    else
+      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, false><<<g, WG, 0, st>>>(
+          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, DiaOffs{}, MSched{});
   }
 };
 
@@ -155,10 +184,22 @@ static void outer_residual_m(mgk_solver* S, int K, const double* B, const double
   hipStream_t st = S->dev.stream;
   const int g = (S->nbr + MROWS - 1) / MROWS;
   const DMat& A = S->A;
+  const double* v = (const double*)A.val;
+  const double* dv = (const double*)A.dval;
+  const bool dia = A.dia.k > 0;
+  MSched ms;
+  const int gd = msched_of(A, ms);
+  const MSched lin{};
   switch (S->b) {
-    case 1: k_residual_m<1, 1, double, double, double, double><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, B, X, R); break;
-    case 3: k_residual_m<3, 3, double, double, double, double><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, B, X, R); break;
-    case 4: k_residual_m<4, 4, double, double, double, double><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, (const double*)A.val, B, X, R); break;
+    case 1: k_residual_m<1, double, double, double, double, false><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin); break;
+    case 3:
+      if (dia) k_residual_m<3, double, double, double, double, true><<<gd, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, dv, B, X, R, A.dia, ms);
+      else k_residual_m<3, double, double, double, double, false><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin);
+      break;
+    case 4:
+      if (dia) k_residual_m<4, double, double, double, double, true><<<gd, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, dv, B, X, R, A.dia, ms);
+      else k_residual_m<4, double, double, double, double, false><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin);
+      break;
   }
 }
 
@@ -174,10 +215,22 @@ static int outer_spmm_dot(mgk_solver* S, int K, const double* X, double* Y, int 
   hipEvent_t e0 = timed ? S->tev[S->tev_used] : nullptr;
   hipEvent_t e1 = timed ? S->tev[S->tev_used + 1] : nullptr;
   const double* v = (const double*)A.val;
+  const double* dv = (const double*)A.dval;
+  const DiaOffs no{};
+  const bool dia = A.dia.k > 0;
+  MSched ms;
+  const int gd = msched_of(A, ms);
+  const MSched lin{};
   switch (S->b) {
-    case 1: launch_ev(k_spmm_dot<1>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part); break;
-    case 3: launch_ev(k_spmm_dot<3>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part); break;
-    case 4: launch_ev(k_spmm_dot<4>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part); break;
+    case 1: launch_ev(k_spmm_dot<1, false>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part, no, lin); break;
+    case 3:
+      if (dia) launch_ev(k_spmm_dot<3, true>, gd, st, e0, e1, S->nbr, K, A.ptr, A.col, dv, X, Y, two, W1, part, A.dia, ms);
+      else launch_ev(k_spmm_dot<3, false>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part, no, lin);
+      break;
+    case 4:
+      if (dia) launch_ev(k_spmm_dot<4, true>, gd, st, e0, e1, S->nbr, K, A.ptr, A.col, dv, X, Y, two, W1, part, A.dia, ms);
+      else launch_ev(k_spmm_dot<4, false>, g, st, e0, e1, S->nbr, K, A.ptr, A.col, v, X, Y, two, W1, part, no, lin);
+      break;
   }
   if (timed) {
     HIPCK(hipGetLastError());
@@ -308,22 +361,27 @@ static int bicgstab_multi(mgk_solver* S, int K, const double* B, double* X, doub
       vcycle_m(S, K, W.p, W.ph);
       int g1 = outer_spmm_dot(S, K, W.ph, W.v, 0, W.rh);
       finalize_m(S, K, g1, 0, FINM_ALPHA);
-      k_bicg_s_m<<<gv, WG, 0, st>>>(n, K, W.active, W.scm, W.r, W.v, W.ph, W.s, X, W.part);
+      k_bicg_s_m<<<gv, WG, 0, st>>>(n, K, W.active, W.scm, W.r, W.v, W.s, W.part);
       finalize_m(S, K, gv, 0, FINM_STORE1, SM_SS);
       publish_m(S);
       changed = false;
-      for (int k = 0; k < K; ++k)
-        if (act[k] && sc(SM_SS, k) <= tol2[k]) {
-          act[k] = 0;   // x_k already holds x_k + alpha_k phat_k
+      for (int k = 0; k < K; ++k) {
+        msk[k] = act[k] && sc(SM_SS, k) <= tol2[k];
+        if (msk[k]) {
+          act[k] = 0;   // stops at s: x_k += alpha_k phat_k below
           changed = true;
         }
-      if (changed) push_flags(S);
+      }
+      if (changed) {
+        push_flags(S);
+        k_bicg_x_m<<<gv, WG, 0, st>>>(n, K, W.mask, W.scm, W.ph, X);
+      }
       if (!any_active()) break;
       vcycle_m(S, K, W.s, W.sh);
       int g2 = outer_spmm_dot(S, K, W.sh, W.t, 1, W.s);
       finalize_m(S, K, g2, 1, FINM_OMEGA);
-      k_bicg_xr_m<<<gv, WG, 0, st>>>(n, K, W.active, W.scm, W.s, W.t, W.sh, W.rh, X, W.r,
-                                      W.part);
+      k_bicg_xr_m<<<gv, WG, 0, st>>>(n, K, W.active, W.scm, W.s, W.t, W.ph, W.sh, W.rh, X,
+                                      W.r, W.part);
       finalize_m(S, K, gv, 1, FINM_RHO);
       publish_m(S);
       changed = false;

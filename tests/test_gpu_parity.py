@@ -394,15 +394,11 @@ def test_diagonal_layout_chosen_at_scale():
     assert info["outer_dia"] == 7 and info["rel_resid"] <= 1e-8
 
 
-def test_diagonal_layout_with_partial_rows():
-    """Rows with some diagonals missing are padded with zero blocks, which moves products
-    between summation stripes: SpMV stays within the FP64 bound of the oracle, and a few
-    solver iterations agree with the BSR layout to rounding."""
-    n = 12
-    th, bsr, A0 = problem(n, 0.5, 4)
+def drop_mirrored_pairs(bsr, seed):
+    """The BSR operator with about 4% of its off-diagonal blocks dropped in mirrored pairs
+    (every block diagonal keeps some blocks, so the diagonal layout still has 7 slots)."""
     ptr, col, val = bsr
-    rng = np.random.default_rng(5)
-    # drop about 4% of the off-diagonal blocks in mirrored pairs; 7 diagonals stay
+    rng = np.random.default_rng(seed)
     nbr = ptr.size - 1
     keep = np.ones(col.size, bool)
     rows = np.repeat(np.arange(nbr), np.diff(ptr))
@@ -412,8 +408,17 @@ def test_diagonal_layout_with_partial_rows():
         if i != j and (j, i) in pos:
             keep[k] = keep[pos[(j, i)]] = False
     nptr = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=nbr))]).astype(np.int32)
-    pbsr = (nptr, col[keep].copy(), val[keep].copy())
     assert 0.94 * col.size < keep.sum() < 0.98 * col.size
+    return nptr, col[keep].copy(), val[keep].copy()
+
+
+def test_diagonal_layout_with_partial_rows():
+    """Rows with some diagonals missing are padded with zero blocks, which moves products
+    between summation stripes: SpMV stays within the FP64 bound of the oracle, and a few
+    solver iterations agree with the BSR layout to rounding."""
+    n = 12
+    th, bsr, A0 = problem(n, 0.5, 4)
+    pbsr = drop_mirrored_pairs(bsr, 5)
     import scipy.sparse as sp
     A = sp.bsr_matrix((pbsr[2], pbsr[1], pbsr[0]), shape=A0.shape).tocsr()
     x = np.random.default_rng(1).normal(size=A.shape[0])
@@ -515,6 +520,76 @@ def test_multi_rhs_lockstep(storage):
     with pytest.raises(mgk.MgkError):
         s.solve_multi(torch.zeros((A.shape[0], 33), dtype=torch.float64, device=DEV),
                       torch.zeros((A.shape[0], 33), dtype=torch.float64, device=DEV))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_multi_rhs_diagonal_layout_bitwise(storage):
+    """The multi-RHS kernels read a diagonal-layout operator (the outer FP64 operator and
+    hierarchy level 0) with the same ascending per-row sums as the walk over its BSR rows,
+    skipping the slots a row does not store, so lockstep solves are bitwise the same in
+    both layouts: on the Stokes operator (a full solve, every column checked by oracle
+    SpMV) and on one with about 4% of its off-diagonal blocks dropped (five iterations).
+    13^3 leaves a ragged last workgroup (2197 block rows) and 9 columns leave lanes idle."""
+    n, K = 13, 9
+    th, bsr, A = problem(n, 0.5, 22)
+    Bm = S.body_forces(n, K, 4)
+    Bm[:, 3] = 0.0
+    dB = dev(Bm)
+    full = None
+    for op, maxiter in ((bsr, 1000), (drop_mirrored_pairs(bsr, 6), 5)):
+        outs = []
+        for layout in (2, 1):
+            say("multi layout", storage, layout, maxiter)
+            s = gpu_solver(op, hier=storage, coarse_enough=200, layout=layout, maxiter=maxiter)
+            assert s.level_info(0)["dia"] == (7 if layout == 2 else 0)
+            dX = torch.zeros_like(dB)
+            infos = s.solve_multi(dB, dX, 1e-8)
+            outs.append((dX.cpu().numpy(), [i["iters"] for i in infos]))
+        assert outs[0][1] == outs[1][1]
+        assert np.array_equal(outs[0][0], outs[1][0])
+        full = outs[0][0] if full is None else full
+    assert not np.any(full[:, 3])
+    for k in range(K):
+        if k != 3:
+            b = Bm[:, k]
+            res = np.linalg.norm(b - oracle.spmv(A, full[:, k])) / np.linalg.norm(b)
+            assert res <= 1e-8, (k, res)
+
+
+def leading_block(bsr, m):
+    """The leading m x m block rows and columns of a BSR operator."""
+    ptr, col, val = bsr
+    rows = np.repeat(np.arange(ptr.size - 1), np.diff(ptr))
+    keep = (rows < m) & (col < m)
+    nptr = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=m)[:m])])
+    return nptr.astype(np.int32), col[keep].copy(), val[keep].copy()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_multi_rhs_plane_tiled_order_bitwise(storage):
+    """At 36^3 the largest diagonal offset (a grid plane, 1296 block rows) makes the
+    multi-RHS kernels take their 8-row blocks plane by plane in 8 tiles of 21 blocks, the
+    last tile of each plane with holes (8 x 21 > 162).  The schedule changes no sum, so
+    lockstep iterations are bitwise those of the BSR layout's linear order; also on the
+    leading 46,556 block rows (a partial last plane and a ragged last block)."""
+    n, K = 36, 5
+    th, bsr, A = problem(n, 0.5, 23)
+    nb = A.shape[0] // 4
+    for op in (bsr, leading_block(bsr, nb - 100)):
+        m = op[0].size - 1
+        Bm = S.body_forces(n, K, 4)[: 4 * m]
+        dB = dev(Bm)
+        outs = []
+        for layout in (2, 1):
+            say("tiled order", storage, m, layout)
+            s = gpu_solver(op, hier=storage, layout=layout, maxiter=3)
+            assert s.level_info(0)["dia"] == (7 if layout == 2 else 0)
+            dX = torch.zeros_like(dB)
+            infos = s.solve_multi(dB, dX, 1e-8)
+            outs.append((dX.cpu().numpy(), [i["iters"] for i in infos]))
+        assert outs[0][1] == outs[1][1]
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert np.all(np.isfinite(outs[0][0])) and np.any(outs[0][0])
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
