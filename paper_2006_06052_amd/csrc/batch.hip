@@ -13,6 +13,8 @@
 //   system exactly its own V-cycle.
 // The engine tile of each grouped stage is picked by timing the grouped launch
 // at setup.  A system whose iteration has stopped is skipped by every launch.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "kernels_batch.hpp"
 
@@ -29,6 +31,7 @@ struct GStage {
   Tile tile;
   int cap = PERSIST;               // workgroups per launch (tuned for row stages)
   bool cached = false;             // operator loads cached (the operators' own policy)
+  bool dia = false;                // every item's operator read in its diagonal layout
 };
 
 struct BatchWork {
@@ -120,17 +123,31 @@ static int pgrid(int total, int cap = PERSIST) { return std::max(1, std::min(tot
 
 // ---------------------------------------------------------------- grouped launches
 
+// The (cached, diagonal-layout) variant of a grouped kernel as compile-time flags; the
+// diagonal layout exists for 3x3 and 4x4 blocks only.
+template <int B, class F>
+static void g_variant(const GStage& g, F&& f) {
+  using T = std::true_type;
+  using N = std::false_type;
+  if (B != 1 && g.dia) {
+    if (g.cached) f(T(), T());
+    else f(N(), T());
+  } else {
+    if (g.cached) f(T(), N());
+    else f(N(), N());
+  }
+}
+
 template <int B, class TV, class TX, class TY>
 static void g_spmv(hipStream_t st, const GStage& g, const int* active, double beta) {
   if (g.h.empty()) return;
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
-    if (g.cached)
-      k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA, true>
+    g_variant<B>(g, [&](auto C, auto D) {
+      k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA,
+               decltype(C)::value, B != 1 && decltype(D)::value>
           <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
-    else
-      k_g_spmv<B, B, decltype(SS)::value, decltype(UU)::value, TV, TX, TY, TA>
-          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active, (TA)beta);
+    });
   });
 }
 
@@ -139,12 +156,11 @@ static void g_residual(hipStream_t st, const GStage& g, const int* active) {
   if (g.h.empty()) return;
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
-    if (g.cached)
-      k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA, true>
+    g_variant<B>(g, [&](auto C, auto D) {
+      k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA,
+                   decltype(C)::value, B != 1 && decltype(D)::value>
           <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
-    else
-      k_g_residual<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TA>
-          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+    });
   });
 }
 
@@ -153,12 +169,11 @@ static void g_smooth(hipStream_t st, const GStage& g, const int* active) {
   if (g.h.empty()) return;
   using TA = AccOf<TV>;
   tile_switch<B>(g.tile, [&](auto SS, auto UU) {
-    if (g.cached)
-      k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA, true>
+    g_variant<B>(g, [&](auto C, auto D) {
+      k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA,
+                 decltype(C)::value, B != 1 && decltype(D)::value>
           <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
-    else
-      k_g_smooth<B, decltype(SS)::value, decltype(UU)::value, TV, TX, TF, TO, TM, TA>
-          <<<pgrid(g.total, g.cap), WG, 0, st>>>(g.d, (int)g.h.size(), g.total, active);
+    });
   });
 }
 
@@ -284,6 +299,20 @@ static void build_stages(BatchWork& W) {
   W.R.assign(L, GStage());
   W.P.assign(L, GStage());
   W.coarse = GStage();
+  // the fine operators (outer, hierarchy level 0) are read in their diagonal layout when
+  // every system has one; a stage is one kernel instantiation, so it is all or none
+  bool dia_outer = W.b != 1, dia_l0 = W.b != 1;
+  for (mgk_solver* S : W.sys) {
+    dia_outer = dia_outer && S->A.dia.k > 0;
+    dia_l0 = dia_l0 && S->H.lv[0].A.dia.k > 0;
+  }
+  auto op = [](GItem it, const DMat& A, bool dia) {
+    if (dia) {
+      it.val = A.dval;
+      it.dia = A.dia;
+    }
+    return it;
+  };
   for (int s = 0; s < W.nsys; ++s) {
     mgk_solver* S = W.sys[s];
     DHier& H = S->H;
@@ -296,11 +325,13 @@ static void build_stages(BatchWork& W) {
         void* zout = l == 0 ? (v == 0 ? (void*)S->ph : (void*)S->sh) : Lv.z2;
         W.bd[v][l].h.push_back(GItem{nullptr, nullptr, nullptr, Lv.M, rin, nullptr, Lv.z,
                                      Lv.nbr, 0, s, 0});
-        W.res[v][l].h.push_back(GItem{Lv.A.ptr, Lv.A.col, Lv.A.val, nullptr, Lv.z, rin, Lv.t,
-                                      Lv.nbr, 0, s, 0});
-        W.sm[v][l].h.push_back(GItem{Lv.A.ptr, Lv.A.col, Lv.A.val, Lv.M, Lv.z, rin, zout,
-                                     Lv.nbr, 0, s, 0});
+        const bool dl = l == 0 && dia_l0;
+        W.res[v][l].h.push_back(op(GItem{Lv.A.ptr, Lv.A.col, Lv.A.val, nullptr, Lv.z, rin,
+                                         Lv.t, Lv.nbr, 0, s, 0}, Lv.A, dl));
+        W.sm[v][l].h.push_back(op(GItem{Lv.A.ptr, Lv.A.col, Lv.A.val, Lv.M, Lv.z, rin, zout,
+                                        Lv.nbr, 0, s, 0}, Lv.A, dl));
         W.res[v][l].cached = W.sm[v][l].cached = Lv.A.cached;
+        W.res[v][l].dia = W.sm[v][l].dia = dl;
       }
       W.R[l].h.push_back(GItem{Lv.R.ptr, Lv.R.col, Lv.R.val, nullptr, Lv.t, nullptr, C.r,
                                Lv.R.nbr, 0, s, 0});
@@ -313,13 +344,14 @@ static void build_stages(BatchWork& W) {
     DLevel& Cl = H.lv[nl - 1];
     W.coarse.h.push_back(GItem{nullptr, nullptr, nullptr, H.cinv, Cl.r, nullptr, Cl.z, H.nc, 0,
                                s, 0});
-    W.outer_spmv[0].h.push_back(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, S->ph, nullptr,
-                                      S->v, S->nbr, 0, s, 0});
-    W.outer_spmv[1].h.push_back(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, S->sh, nullptr,
-                                      S->t, S->nbr, 0, s, 0});
-    W.outer_res.h.push_back(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, nullptr, nullptr,
-                                  S->r, S->nbr, 0, s, 0});
+    W.outer_spmv[0].h.push_back(op(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, S->ph,
+                                         nullptr, S->v, S->nbr, 0, s, 0}, S->A, dia_outer));
+    W.outer_spmv[1].h.push_back(op(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, S->sh,
+                                         nullptr, S->t, S->nbr, 0, s, 0}, S->A, dia_outer));
+    W.outer_res.h.push_back(op(GItem{S->A.ptr, S->A.col, S->A.val, nullptr, nullptr, nullptr,
+                                     S->r, S->nbr, 0, s, 0}, S->A, dia_outer));
     W.outer_spmv[0].cached = W.outer_spmv[1].cached = W.outer_res.cached = S->A.cached;
+    W.outer_spmv[0].dia = W.outer_spmv[1].dia = W.outer_res.dia = dia_outer;
   }
   finish_fixed(W, W.coarse, 1);
   for (int l = 0; l < L; ++l)
@@ -360,9 +392,10 @@ static void batch_setup_impl(mgk_solver* S, int nsys, const mgk_bsr* const* A, i
   S->kind = kind;
   S->b = block_size;
   S->dev.stream = (hipStream_t)stream;
-  // the grouped kernels read the BSR arrays only: no diagonal-layout copies
+  // every fine operator with at most 8 block diagonals gets a diagonal-layout copy (its
+  // row masks skip the padding, so small systems lose nothing to it); layout 1 keeps BSR
   mgk_params sub_prm = *prm;
-  sub_prm.layout = 1;
+  sub_prm.layout = prm->layout == 1 ? 1 : 2;
   for (int s = 0; s < nsys; ++s) {
     mgk_solver* sub = nullptr;
     const int rc = mgk_setup(A[s], block_size, (mgk_precond_kind)kind, &sub_prm, stream, &sub);
@@ -455,7 +488,7 @@ static int batch_bicgstab(mgk_solver* S, const double* const* b, double* const* 
       GVec& g = W.hvec[(size_t)q * ns + s];
       int i = 0;
       for (double* p : ptrs) g.a[i++] = p;
-      for (; i < 6; ++i) g.a[i] = nullptr;
+      for (; i < 7; ++i) g.a[i] = nullptr;
     };
     double* bs = const_cast<double*>(b[s]);
     set(VS_B, {bs, bs});
@@ -467,7 +500,7 @@ static int batch_bicgstab(mgk_solver* S, const double* const* b, double* const* 
     set(VS_RV, {T->rh, T->v});
     set(VS_S, {T->r, T->v, T->ph, T->s, x[s]});
     set(VS_TS, {T->t, T->s, T->t, T->t});
-    set(VS_XR, {T->s, T->t, T->sh, T->rh, x[s], T->r});
+    set(VS_XR, {T->s, T->t, T->sh, T->rh, x[s], T->r, T->ph});
     set(VS_TRUE, {T->r, T->r});
     set(VS_ZERO_X, {x[s]});
     W.outer_res.h[s].in = x[s];
@@ -540,9 +573,14 @@ static int batch_bicgstab(mgk_solver* S, const double* const* b, double* const* 
       gfin(W, VS_S, GF_STORE1, SC_SS);
       gpublish(W);
       ch = false;
+      std::vector<int> stop(ns, 0);
       for (int s = 0; s < ns; ++s)
-        if (act[s] && sc(s, SC_SS) <= tol2[s]) act[s] = 0, ch = true;
-      if (ch) push_active(W, act);
+        if (act[s] && sc(s, SC_SS) <= tol2[s]) act[s] = 0, stop[s] = 1, ch = true;
+      if (ch) {
+        push_active(W, stop);
+        gvec(W, VS_S, GV_X, false);   // x += alpha phat for the systems that stop at s
+        push_active(W, act);
+      }
       if (!any()) break;
       gvcycle(W, 1);
       gouter(W, W.outer_spmv[1]);

@@ -386,7 +386,7 @@ __device__ __forceinline__ RowRange row_range(const int* __restrict__ ptr, const
 // block).  When T > U the stripe accumulators rotate by U after each step so
 // that block u of a step always lands in accumulator u.
 template <int BR, int BC, int S, int U, bool TRANS, class TV, class TX, class TA, int RPL,
-          bool CACHED = false, bool DIA = false, class XSrc = const TX*>
+          bool CACHED = false, bool DIA = false, class XSrc = const TX*, bool FENCE = false>
 __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
                                               const int* __restrict__ ptr,
                                               const int* __restrict__ col,
@@ -453,6 +453,9 @@ __device__ __forceinline__ void row_product_r(const LaneInfo& L, int nbr,
           }
         }
       }
+      // FENCE: the step's loads all leave before the first conversion or mask uses one of
+      // them (a product inside a loop is otherwise free to interleave them)
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         TA v[RPL * BC], xv[BC];

@@ -26,6 +26,7 @@ struct GItem {
   int tile0;          // first tile of this item
   int sys;            // system index
   int pad;
+  DiaOffs dia;        // diagonal layout of a square operator (val then holds its blocks)
 };
 
 __device__ __forceinline__ int find_item(const GItem* __restrict__ items, int nitems, int w) {
@@ -35,6 +36,35 @@ __device__ __forceinline__ int find_item(const GItem* __restrict__ items, int ni
   return it;
 }
 
+// A pointer read from memory is a generic (flat) address to the compiler, and flat loads
+// count against both the vector-memory and the scalar-memory counters, so every wait for a
+// scalar load would also wait for them.  The item lists are written by the host before the
+// launch and only read by the kernels, so they are read through the constant address
+// space: the pointers read from it are known to be global, and their loads are global ones.
+#define MGK_CONST const __attribute__((address_space(4)))
+
+// The item of tile w, copied member by member through the constant address space.
+__device__ __forceinline__ GItem item_of(const GItem* __restrict__ items, int nitems, int w) {
+  MGK_CONST GItem* q = (MGK_CONST GItem*)items + find_item(items, nitems, w);
+  GItem g;
+  g.ptr = q->ptr;
+  g.col = q->col;
+  g.val = q->val;
+  g.M = q->M;
+  g.in = q->in;
+  g.f = q->f;
+  g.out = q->out;
+  g.nbr = q->nbr;
+  g.tile0 = q->tile0;
+  g.sys = q->sys;
+  g.pad = 0;
+  g.dia.k = q->dia.k;
+#pragma unroll
+  for (int d = 0; d < DIA_MAX; ++d) g.dia.o[d] = q->dia.o[d];
+  g.dia.mask = q->dia.mask;
+  return g;
+}
+
 // Tile walk of a grouped launch.  gridDim.x >= total: one tile per workgroup,
 // remapped so that each XCD takes one contiguous range of tiles; gridDim.x <
 // total: a persistent grid striding through the tile space.
@@ -42,24 +72,39 @@ __device__ __forceinline__ int find_item(const GItem* __restrict__ items, int ni
   for (int w = (int)gridDim.x >= (total) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
        w < (total); w += (int)gridDim.x)
 
+// Row product of item g for lane L, in the diagonal layout when DIA (every item of the
+// launch then has one); the row range is loaded first, as in the single-system kernels.
+template <int BR, int BC, int S, int U, class TV, class TX, class TA, bool CACHED, bool DIA,
+          class Pre>
+__device__ __forceinline__ TA g_row_product(const LaneInfo& L, const GItem& g, const TX* x,
+                                            Pre&& pre) {
+  const RowRange rr = row_range<DIA>(g.ptr, g.dia, L.i, g.nbr);
+  __builtin_amdgcn_sched_barrier(0);
+  pre();
+  TA acc[1];
+  row_product_r<BR, BC, S, U, false, TV, TX, TA, 1, CACHED, DIA, const TX*, true>(
+      L, g.nbr, g.ptr, g.col, nullptr, (const TV*)g.val, x, acc, g.dia, rr);
+  return acc[0];
+}
+
 // y = A x + beta y
 template <int BR, int BC, int S, int U, class TV, class TX, class TY, class TA,
-          bool CACHED = false>
+          bool CACHED = false, bool DIA = false>
 __global__ __launch_bounds__(WG) void k_g_spmv(const GItem* __restrict__ items, int nitems,
                                                int total, const int* __restrict__ active,
                                                TA beta) {
   GROUP_TILES(w, total) {
-    const GItem& g = items[find_item(items, nitems, w)];
+    const GItem g = item_of(items, nitems, w);
     if (!active[g.sys]) continue;
     const LaneInfo L = lane_info<BR, S>(w - g.tile0);
     const bool own = L.active && L.s == 0 && L.i < g.nbr;
     const size_t row = (size_t)L.i * BR + L.r;
     TY* y = (TY*)g.out;
     TY yr[1];
-    if (beta != TA(0)) load_ahead<1>(y, row, own, yr);
-    TA acc = row_product<BR, BC, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
-                                                                  (const TV*)g.val,
-                                                                  (const TX*)g.in);
+    const TA acc = g_row_product<BR, BC, S, U, TV, TX, TA, CACHED, DIA>(
+        L, g, (const TX*)g.in, [&] {
+          if (beta != TA(0)) load_ahead<1>(y, row, own, yr);
+        });
     if (own) {
       TA out = acc;
       if (beta != TA(0)) out = fma_(beta, (TA)yr[0], out);
@@ -69,31 +114,30 @@ __global__ __launch_bounds__(WG) void k_g_spmv(const GItem* __restrict__ items, 
 }
 
 // t = f - A z
-template <int B, int S, int U, class TV, class TX, class TF, class TA, bool CACHED = false>
+template <int B, int S, int U, class TV, class TX, class TF, class TA, bool CACHED = false,
+          bool DIA = false>
 __global__ __launch_bounds__(WG) void k_g_residual(const GItem* __restrict__ items, int nitems,
                                                    int total, const int* __restrict__ active) {
   GROUP_TILES(w, total) {
-    const GItem& g = items[find_item(items, nitems, w)];
+    const GItem g = item_of(items, nitems, w);
     if (!active[g.sys]) continue;
     const LaneInfo L = lane_info<B, S>(w - g.tile0);
     const bool own = L.active && L.s == 0 && L.i < g.nbr;
     const size_t row = (size_t)L.i * B + L.r;
     TF fr[1];   // ahead of the row product
-    load_ahead<1>((const TF*)g.f, row, own, fr);
-    TA acc = row_product<B, B, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
-                                                                (const TV*)g.val,
-                                                                (const TX*)g.in);
+    const TA acc = g_row_product<B, B, S, U, TV, TX, TA, CACHED, DIA>(
+        L, g, (const TX*)g.in, [&] { load_ahead<1>((const TF*)g.f, row, own, fr); });
     if (own) ((TX*)g.out)[row] = (TX)((TA)fr[0] - acc);
   }
 }
 
 // z_out = z + M (f - A z)
 template <int B, int S, int U, class TV, class TX, class TF, class TO, class TM, class TA,
-          bool CACHED = false>
+          bool CACHED = false, bool DIA = false>
 __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items, int nitems,
                                                  int total, const int* __restrict__ active) {
   GROUP_TILES(w, total) {
-    const GItem& g = items[find_item(items, nitems, w)];
+    const GItem g = item_of(items, nitems, w);
     if (!active[g.sys]) continue;   // uniform per workgroup: the whole tile skips
     const LaneInfo L = lane_info<B, S>(w - g.tile0);
     const TX* z = (const TX*)g.in;
@@ -103,11 +147,11 @@ __global__ __launch_bounds__(WG) void k_g_smooth(const GItem* __restrict__ items
     TF fr[1];
     TX zr[1];
     TM mr[B];
-    load_ahead<1>((const TF*)g.f, row, own, fr);
-    load_ahead<1>(z, row, own, zr);
-    load_ahead<B>((const TM*)g.M, ((size_t)L.i * B + L.r) * B, own, mr);
-    TA acc = row_product<B, B, S, U, false, TV, TX, TA, CACHED>(L, g.nbr, g.ptr, g.col, nullptr,
-                                                                (const TV*)g.val, z);
+    const TA acc = g_row_product<B, B, S, U, TV, TX, TA, CACHED, DIA>(L, g, z, [&] {
+      load_ahead<1>((const TF*)g.f, row, own, fr);
+      load_ahead<1>(z, row, own, zr);
+      load_ahead<B>((const TM*)g.M, ((size_t)L.i * B + L.r) * B, own, mr);
+    });
     const TA res = own ? (TA)fr[0] - acc : TA(0);
     const TA zv = (TA)zr[0];
     TA mv[B];
@@ -130,7 +174,7 @@ template <int B, class TM, class TF, class TX, class TA>
 __global__ __launch_bounds__(WG) void k_g_block_diag(const GItem* __restrict__ items, int nitems,
                                                      int total, const int* __restrict__ active) {
   GROUP_TILES(w, total) {
-    const GItem& g = items[find_item(items, nitems, w)];
+    const GItem g = item_of(items, nitems, w);
     if (!active[g.sys]) continue;
     const size_t row = (size_t)(w - g.tile0) * WG + threadIdx.x;
     if (row >= (size_t)g.nbr * B) continue;
@@ -157,7 +201,7 @@ template <class TI, class TO>
 __global__ __launch_bounds__(WG) void k_g_coarse(const GItem* __restrict__ items, int nitems,
                                                  int total, const int* __restrict__ active) {
   GROUP_TILES(w, total) {
-    const GItem& g = items[find_item(items, nitems, w)];
+    const GItem g = item_of(items, nitems, w);
     const int i = w - g.tile0;
     double s = 0.0, dummy = 0.0;
     const bool on = active[g.sys] != 0;   // uniform per workgroup
@@ -177,7 +221,7 @@ __global__ __launch_bounds__(WG) void k_g_coarse(const GItem* __restrict__ items
 constexpr int VTILE = 16 * WG;   // elements per vector tile
 
 struct GVec {
-  double* a[6];
+  double* a[7];
   long long n;
   int tile0, ntiles, sys, pad;
 };
@@ -192,10 +236,13 @@ __device__ __forceinline__ int find_vec(const GVec* __restrict__ v, int nv, int 
 enum GVOp {
   GV_DOT = 0,    // part = <a0, a1>, part2 = <a2, a3> (a2 may be null)
   GV_P = 1,      // a2 (p) = a0 (r) + beta (p - omega a1 (v))
-  GV_S = 2,      // a3 (s) = a0 (r) - alpha a1 (v); a4 (x) += alpha a2 (ph); part = ||s||^2
-  GV_XR = 3,     // a4 (x) += omega a2 (sh); a5 (r) = a0 (s) - omega a1 (t); part = ||r||^2, part2 = (a3 rh, r)
+  GV_S = 2,      // a3 (s) = a0 (r) - alpha a1 (v); part = ||s||^2
+  GV_XR = 3,     // a4 (x) = (x + alpha a6 (ph)) + omega a2 (sh); a5 (r) = a0 (s) - omega a1 (t);
+                 // part = ||r||^2, part2 = (a3 rh, r): one pass over x per iteration, the
+                 // two additions in the order of the two updates
   GV_COPY = 4,   // a1 = a0
-  GV_ZERO = 5    // a0 = 0
+  GV_ZERO = 5,   // a0 = 0
+  GV_X = 6       // a4 (x) += alpha a2 (ph) (the iteration stopped at s)
 };
 
 __global__ __launch_bounds__(WG) void k_g_vec(const GVec* __restrict__ vs, int nv, int total,
@@ -203,7 +250,13 @@ __global__ __launch_bounds__(WG) void k_g_vec(const GVec* __restrict__ vs, int n
                                               const double* __restrict__ scb,
                                               double* __restrict__ part) {
   GROUP_TILES(w, total) {
-    const GVec& v = vs[find_vec(vs, nv, w)];
+    MGK_CONST GVec* vq = (MGK_CONST GVec*)vs + find_vec(vs, nv, w);
+    GVec v;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v.a[q] = vq->a[q];
+    v.n = vq->n;
+    v.tile0 = vq->tile0;
+    v.sys = vq->sys;
     double d1 = 0.0, d2 = 0.0;
     const bool on = active[v.sys] != 0;
     if (on) {
@@ -225,13 +278,15 @@ __global__ __launch_bounds__(WG) void k_g_vec(const GVec* __restrict__ vs, int n
         for (long long e = e0 + threadIdx.x; e < e1; e += WG) {
           const double si = v.a[0][e] - al * v.a[1][e];
           v.a[3][e] = si;
-          v.a[4][e] += al * v.a[2][e];
           d1 = fma_(si, si, d1);
         }
+      } else if (op == GV_X) {
+        const double al = sc[SC_ALPHA];
+        for (long long e = e0 + threadIdx.x; e < e1; e += WG) v.a[4][e] += al * v.a[2][e];
       } else if (op == GV_XR) {
-        const double om = sc[SC_OMEGA];
+        const double al = sc[SC_ALPHA], om = sc[SC_OMEGA];
         for (long long e = e0 + threadIdx.x; e < e1; e += WG) {
-          v.a[4][e] += om * v.a[2][e];
+          v.a[4][e] = (v.a[4][e] + al * v.a[6][e]) + om * v.a[2][e];
           const double ri = v.a[0][e] - om * v.a[1][e];
           v.a[5][e] = ri;
           d1 = fma_(ri, ri, d1);

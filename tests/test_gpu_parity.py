@@ -466,6 +466,29 @@ def test_cached_and_streamed_value_loads_agree(storage, monkeypatch):
             assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_batch_diagonal_layout_bitwise(storage):
+    """The grouped kernels read every system's fine operator (outer and hierarchy level 0)
+    in its diagonal layout, with row masks for the Dirichlet rows (the 10^3 system pads its
+    7 diagonals by 58%): a batched solve is bitwise the one with every operator in BSR."""
+    ns = [10, 13, 16]
+    probs = [problem(n, 0.5, 70 + k) for k, n in enumerate(ns)]
+    bs = [dev(oracle.spmv(A, S.mms_solution(n))) for n, (_, _, A) in zip(ns, probs)]
+    outs = []
+    for layout in (0, 1):
+        say("batch layout", storage, layout)
+        bsol = mgk.BatchSolver([p[1] for p in probs], 4, mgk.AMG_SPAI0,
+                               stream=torch.cuda.current_stream(), hier=storage,
+                               coarse_enough=300, layout=layout)
+        xs = [torch.zeros_like(b) for b in bs]
+        infos = bsol.solve(bs, xs, 1e-8)
+        assert all(i["status"] == 0 for i in infos)
+        outs.append(([x.cpu().numpy() for x in xs], [i["iters"] for i in infos]))
+    assert outs[0][1] == outs[1][1]
+    for a, c in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, c)
+
+
 def test_cached_and_streamed_loads_agree_in_batches(monkeypatch):
     """The grouped batch kernels take the same load policy: a batched solve is bitwise the
     same with every operator streamed and every operator cached."""
