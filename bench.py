@@ -36,13 +36,14 @@ METRIC = "solve time to rtol 1e-8 (s) + BSR SpMV HBM GB/s; mixed-precision vs FP
 HBM_PEAK_GBS = 8000.0
 
 
-def kernels_sha():
-    """Short hash of the kernel source code (comment lines and blank lines left out, so that
+def kernels_sha(*files):
+    """Short hash of kernel source code (comment lines and blank lines left out, so that
     editing a comment keeps it), tagging counter profiles to the code they measured."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2006_06052_amd", "csrc", "kernels.hpp")
-    with open(path) as f:
-        code = [ln.strip() for ln in f if ln.strip() and not ln.strip().startswith("//")]
+    code = []
+    for name in files or ("kernels.hpp",):
+        with open(os.path.join(ROOT, "paper_2006_06052_amd", "csrc", name)) as f:
+            code += [ln.strip() for ln in f if ln.strip() and not ln.strip().startswith("//")]
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
@@ -286,12 +287,20 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
             return its
         t1, its1 = _median_solve(run1, torch)
         seq = t1 / len(cols) * K
-        out["multi64_32rhs"] = {"solve_s": t, "rhs": K,
-                                "spmm": {"kernel": "mgk::k_spmm_dot<4>", "bytes_per_launch":
-                                         spmm_bytes, "avg_launch_us": spmm_us,
-                                         "launches": infos[0]["spmv_calls"],
-                                         "achieved_gbs": spmm_bytes / spmm_us / 1e3,
-                                         "frac": spmm_bytes / spmm_us / 1e3 / HBM_PEAK_GBS},
+        spmm = {"kernel": "mgk::k_spmm_dot<4, true>", "bytes_per_launch": spmm_bytes,
+                "avg_launch_us": spmm_us, "launches": infos[0]["spmv_calls"],
+                "achieved_gbs": spmm_bytes / spmm_us / 1e3,
+                "frac": spmm_bytes / spmm_us / 1e3 / HBM_PEAK_GBS, "traffic": None}
+        # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)
+        # while the profile describes this kernel's source
+        tpath = os.path.join(ROOT, "profiles", "spmm_dot_f64_cube64x32_traffic.json")
+        if os.path.exists(tpath):
+            with open(tpath) as f:
+                tr = json.load(f)
+            hit = tr.get("by_instantiation", {}).get(spmm["kernel"])
+            if hit and tr.get("kernels_sha") == kernels_sha("kernels.hpp", "kernels_multi.hpp"):
+                spmm["traffic"] = hit["bytes_per_launch"]
+        out["multi64_32rhs"] = {"solve_s": t, "rhs": K, "spmm": spmm,
                                 "iters": [i["iters"] for i in infos],
                                 "all_converged": all(i["status"] == 0 for i in infos),
                                 "single_rhs_s_x32": seq, "speedup_vs_single": seq / t,
@@ -644,6 +653,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="one FP32-hierarchy solve, then three 1 GiB device copies (a short "
                          "program for rocprofv3 --pmc runs)")
+    ap.add_argument("--counters-workload", default="cube96", choices=["cube96", "multi64"],
+                    help="the solve of --counters: the headline system, or 20 lockstep "
+                         "iterations of the 64^3 system with 32 right-hand sides")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
@@ -691,12 +703,22 @@ def main():
         log(f"spmv: {t * 1e6:.1f} us, {spmv_bytes / t / 1e9:.0f} GB/s")
         return
 
-    if args.counters:
+    if args.counters and args.counters_workload == "multi64":
+        m, K = 64, 32
+        mp, mc, mv = mgk.stokes_bsr(m)
+        s = mgk.Solver(mp, mc, mv, 4, mgk.AMG_SPAI0, stream=stream, hier=mgk.F32, maxiter=20)
+        B = torch.from_numpy(np.ascontiguousarray(S.body_forces(m, K, 4))).cuda()
+        X = torch.zeros_like(B)
+        infos = s.solve_multi(B, X, 1e-8)
+        torch.cuda.synchronize()
+        log(f"counters: multi-RHS solve, {infos[0]['iters']} lockstep iterations")
+    elif args.counters:
         s, _ = make("bsr_f32")
         dx = torch.zeros_like(db)
         info = s.solve(db, dx, 1e-8)
         torch.cuda.synchronize()
         log(f"counters: solve {info['iters']} iterations, outer tile {info['outer_tile']}")
+    if args.counters:
         x = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
         for _ in range(3):
