@@ -155,7 +155,10 @@ typedef struct {
                               a structured grid); 1: BSR only; 2: the diagonal layout for
                               every such operator whatever its padding.  Results agree to
                               rounding (bit for bit when every block row holds either all the
-                              operator's block diagonals or only its diagonal block). */
+                              operator's block diagonals or only its diagonal block; always
+                              bit for bit in mgk_solve_multi).  mgk_batch_setup takes 0 and 2
+                              alike (every system's eligible fine operator in the diagonal
+                              layout), 1 keeps BSR. */
   int32_t reserved;
 } mgk_params;
 
