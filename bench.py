@@ -223,7 +223,7 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
     ilu48    - 48^3 manufactured-plus-noise system: IDR(5) with block ILU(1) (3 Jacobi
                sweeps per factor; FP64 and FP32 factors) against IDR(5) with the AMG.
     All hierarchies are FP32 unless stated; rtol 1e-8 (adjoint workload 1e-10, paper_schur64
-    1e-9)."""
+    and multi64 1e-9)."""
     import numpy as np
     stream = torch.cuda.current_stream()
     out = {}
@@ -266,10 +266,14 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
         B = torch.from_numpy(np.ascontiguousarray(S.body_forces(n, K, 4))).cuda()
         s = solver(ptr, col, val, hier=mgk.F32, time_spmv=1)
         X = torch.zeros_like(B)
+        # rtol 1e-9: random body forces excite the operator's slow modes, and at 1e-8 a
+        # column's solution error can reach 1.5e-6; at 1e-9 every column meets both the
+        # residual and the 1e-6 solution bar
+        rtol = 1e-9
 
         def run():
             X.zero_()
-            return s.solve_multi(B, X, 1e-8)
+            return s.solve_multi(B, X, rtol)
         t, infos = _median_solve(run, torch)
         # the outer FP64 SpMM fused with the per-column dots: the matrix once, X and Y with
         # K columns, and the K-column dot weights
@@ -283,7 +287,7 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
             its = []
             for c in cols:
                 xc.zero_()
-                its.append(s.solve(c, xc, 1e-8)["iters"])
+                its.append(s.solve(c, xc, rtol)["iters"])
             return its
         t1, its1 = _median_solve(run1, torch)
         seq = t1 / len(cols) * K
@@ -300,7 +304,7 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
             hit = tr.get("by_instantiation", {}).get(spmm["kernel"])
             if hit and tr.get("kernels_sha") == kernels_sha("kernels.hpp", "kernels_multi.hpp"):
                 spmm["traffic"] = hit["bytes_per_launch"]
-        out["multi64_32rhs"] = {"solve_s": t, "rhs": K, "spmm": spmm,
+        out["multi64_32rhs"] = {"solve_s": t, "rhs": K, "rtol": rtol, "spmm": spmm,
                                 "iters": [i["iters"] for i in infos],
                                 "all_converged": all(i["status"] == 0 for i in infos),
                                 "single_rhs_s_x32": seq, "speedup_vs_single": seq / t,

@@ -21,22 +21,30 @@ namespace mgk {
 constexpr int KL = 32;                 // max right-hand sides (lanes per half-wavefront)
 constexpr int MROWS = WG / KL;         // block rows (row slots) per workgroup
 
-// Matrix kernels: a wavefront owns two block rows, i0 (lanes 0-31) and i0 + 1
-// (lanes 32-63); lane k = lane & 31 is the right-hand side.  i0 is uniform over
-// the wavefront (the smoother's diagonal blocks of both rows arrive through
-// scalar loads and each half selects its own).
+// Matrix kernels: the 8 half-wavefront slots of a workgroup hold 8 >> qs block rows, each
+// cut into Q = 1 << qs slices of its blocks (long rows: the slices of a row are summed in
+// slice order at the end); slot s takes slice s % Q of row s / Q, and lane k = lane & 31 is
+// the right-hand side.  With Q = 1 a wavefront owns two rows, i0 (lanes 0-31) and i0 + 1
+// (lanes 32-63); with Q > 1 both halves of a wavefront hold slices of one row i0.  i0 is
+// uniform over the wavefront (the smoother's diagonal blocks arrive through scalar loads
+// and each half selects its own).
 struct MRow {
-  int i0;  // first row of the pair (uniform)
+  int i0;  // first row of the wavefront (uniform)
   int h;   // 0: row i0, 1: row i0 + 1
   int i;   // i0 + h
   int k;   // right-hand side
+  int q;   // slice of the row
 };
 
-__device__ __forceinline__ MRow mrow(int lw) {
+__device__ __forceinline__ MRow mrow(int lw, int qs = 0) {
+  const int slot = threadIdx.x >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int r0 = lw * (MROWS >> qs);
   MRow m;
-  m.i0 = lw * MROWS + 2 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  m.h = (threadIdx.x >> 5) & 1;
-  m.i = m.i0 + m.h;
+  m.i0 = r0 + ((2 * wave) >> qs);
+  m.h = qs ? 0 : slot & 1;
+  m.i = r0 + (slot >> qs);
+  m.q = slot & ((1 << qs) - 1);
   m.k = threadIdx.x & 31;
   return m;
 }
@@ -103,27 +111,36 @@ constexpr int mstage_cap() { return 16384 / (BR * BC * (int)sizeof(TV)); }
 constexpr int MU = 4;
 
 // acc[r] = sum over blocks (i, j) of sum_c A_ij[r][c] X[j*BC + c][k]  (r < BR) for
-// row i of the workgroup whose rows start at r0 (on: the lane has a row and a
-// right-hand side).  Every lane of the workgroup must call this (it holds
-// barriers).  Each row sums its blocks in ascending order: passes ascend, and
-// within a pass the lane walks its row's blocks in order; steps past the row's
-// end re-read an in-bounds block and are skipped at the FMA.
+// row i of the workgroup whose 8 >> qs rows start at r0 (on: the lane has a row and a
+// right-hand side; q: its slice of the row).  Every lane of the workgroup must call this
+// (it holds barriers).  A slice sums its blocks in ascending order: passes ascend, and
+// within a pass the lane walks its slice's blocks in order; steps past the slice's end
+// re-read an in-bounds block and are skipped at the FMA.  With qs > 0 the row's 1 << qs
+// contiguous slices (slice q: blocks [k0 + len*q/Q, k0 + len*(q+1)/Q)) are then added in
+// slice order, and the sum is in the q = 0 lanes.
 template <int BR, int BC, class TV, class TX, class TA>
 __device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool on, int k, int K,
                                                   const int* __restrict__ ptr,
                                                   const int* __restrict__ col,
                                                   const TV* __restrict__ val,
-                                                  const TX* __restrict__ X, TA* acc) {
+                                                  const TX* __restrict__ X, TA* acc,
+                                                  int qs = 0, int q = 0) {
   constexpr int BB = BR * BC;
   constexpr int CAP = mstage_cap<BR, BC, TV>();
   typedef typename std::conditional<sizeof(TV) == 2, uint16_t, TV>::type TS;
   __shared__ int s_col[CAP];
-  __shared__ TS s_val[CAP * BB];
+  __shared__ alignas(16) TS s_val[CAP * BB];
+  static_assert(sizeof(TS) * CAP * BB >= sizeof(TA) * BR * WG, "slice sums fit the stage");
 #pragma unroll
   for (int r = 0; r < BR; ++r) acc[r] = 0;
   const TS* gval = reinterpret_cast<const TS*>(val);
-  const int c_begin = ptr[r0], c_end = ptr[min(r0 + MROWS, nbr)];
-  const int k0 = on ? ptr[i] : 0, k1 = on ? ptr[i + 1] : 0;
+  const int c_begin = ptr[r0], c_end = ptr[min(r0 + (MROWS >> qs), nbr)];
+  int k0 = on ? ptr[i] : 0, k1 = on ? ptr[i + 1] : 0;
+  if (qs) {
+    const int len = k1 - k0;
+    k1 = k0 + ((len * (q + 1)) >> qs);
+    k0 = k0 + ((len * q) >> qs);
+  }
   for (int c = c_begin; c < c_end; c += CAP) {
     const int cn = min(CAP, c_end - c);
     // every load of the pass is issued before the first LDS write
@@ -177,6 +194,22 @@ __device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool o
       }
     }
     __syncthreads();
+  }
+  if (qs) {
+    // slice q of a row sits 32 q lanes after its slice 0; the stage is free again (the
+    // last pass ended with a barrier)
+    TA* s_red = reinterpret_cast<TA*>(s_val);
+#pragma unroll
+    for (int r = 0; r < BR; ++r) s_red[r * WG + threadIdx.x] = acc[r];
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        TA t = s_red[r * WG + threadIdx.x];
+        for (int j = 1; j < (1 << qs); ++j) t += s_red[r * WG + threadIdx.x + j * KL];
+        acc[r] = t;
+      }
+    }
   }
 }
 
@@ -258,12 +291,13 @@ __device__ __forceinline__ void block_rows(int r0, int nbr, int i, bool on, int 
                                            const int* __restrict__ ptr,
                                            const int* __restrict__ col,
                                            const TV* __restrict__ val, const DiaOffs& of,
-                                           const TX* __restrict__ X, TA* acc, Pre&& pre) {
+                                           const TX* __restrict__ X, TA* acc, Pre&& pre,
+                                           int qs = 0, int q = 0) {
   if constexpr (DIA) {
     block_rows_dia<B, TV, TX, TA>(r0, nbr, i, on, k, K, of, val, X, acc, pre);
   } else {
     pre();
-    block_rows_staged<B, B, TV, TX, TA>(r0, nbr, i, on, k, K, ptr, col, val, X, acc);
+    block_rows_staged<B, B, TV, TX, TA>(r0, nbr, i, on, k, K, ptr, col, val, X, acc, qs, q);
   }
 }
 
@@ -298,16 +332,17 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
                                              const int* __restrict__ col,
                                              const TV* __restrict__ val,
                                              const TX* __restrict__ X, TY* __restrict__ Y,
-                                             TA alpha, TA beta) {
+                                             TA alpha, TA beta, int qs) {
   const int lw = xcd_remap(blockIdx.x, gridDim.x);
-  const MRow m = mrow(lw);
+  const MRow m = mrow(lw, qs);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
   TY yr[BR];
   if (beta != TA(0)) load_rows_ahead<BR>(Y, nbr, i, k, K, yr);
   TA acc[BR];
-  block_rows_staged<BR, BC, TV, TX, TA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, X, acc);
-  if (!on) return;
+  block_rows_staged<BR, BC, TV, TX, TA>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, X,
+                                        acc, qs, m.q);
+  if (!on || m.q) return;
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const size_t e = ((size_t)i * BR + r) * K + k;
@@ -413,17 +448,19 @@ __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __
                                                    const TV* __restrict__ val,
                                                    const TF* __restrict__ F,
                                                    const TX* __restrict__ Z,
-                                                   TX* __restrict__ T, DiaOffs of, MSched ms) {
+                                                   TX* __restrict__ T, DiaOffs of, MSched ms,
+                                                   int qs) {
   const int lw = msched_block(xcd_remap(blockIdx.x, gridDim.x), ms);
-  if (lw < 0 || lw * MROWS >= nbr) return;
-  const MRow m = mrow(lw);
+  if (lw < 0 || lw * (MROWS >> qs) >= nbr) return;
+  const MRow m = mrow(lw, qs);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
   TF fr[B];
   TA acc[B];
-  block_rows<B, TV, TX, TA, DIA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, of, Z, acc,
-                                 [&] { load_rows_ahead<B>(F, nbr, i, k, K, fr); });
-  if (!on) return;
+  block_rows<B, TV, TX, TA, DIA>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, of, Z,
+                                 acc, [&] { load_rows_ahead<B>(F, nbr, i, k, K, fr); }, qs,
+                                 m.q);
+  if (!on || m.q) return;
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     const size_t e = ((size_t)i * B + r) * K + k;
@@ -439,10 +476,11 @@ __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __re
                                                  const TM* __restrict__ M,
                                                  const TF* __restrict__ F,
                                                  const TX* __restrict__ Z,
-                                                 TO* __restrict__ Zout, DiaOffs of, MSched ms) {
+                                                 TO* __restrict__ Zout, DiaOffs of, MSched ms,
+                                                 int qs) {
   const int lw = msched_block(xcd_remap(blockIdx.x, gridDim.x), ms);
-  if (lw < 0 || lw * MROWS >= nbr) return;
-  const MRow m = mrow(lw);
+  if (lw < 0 || lw * (MROWS >> qs) >= nbr) return;
+  const MRow m = mrow(lw, qs);
   const int i = m.i, k = m.k;
   const bool on = i < nbr && k < K;
   TF fr[B];
@@ -454,11 +492,14 @@ __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __re
   TA mb[B * B];
   diag_block<B, TM, TA>(mc, mc.i0 + 1 < nbr, M, mb);
   TA acc[B];
-  block_rows<B, TV, TX, TA, DIA>(lw * MROWS, nbr, i, on, k, K, ptr, col, val, of, Z, acc, [&] {
-    load_rows_ahead<B>(F, nbr, i, k, K, fr);
-    load_rows_ahead<B>(Z, nbr, i, k, K, zr);
-  });
-  if (!on) return;
+  block_rows<B, TV, TX, TA, DIA>(
+      lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, of, Z, acc,
+      [&] {
+        load_rows_ahead<B>(F, nbr, i, k, K, fr);
+        load_rows_ahead<B>(Z, nbr, i, k, K, zr);
+      },
+      qs, m.q);
+  if (!on || m.q) return;
   TA res[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) res[r] = (TA)fr[r] - acc[r];

@@ -106,6 +106,24 @@ static int msched_of(const DMat& A, MSched& ms) {
   return 8 * ms.np * ms.tb;
 }
 
+// Row slices (log2) of a BSR operator in the multi-RHS products.  A coarse level has few
+// rows, each long (64^3: 3,936 rows of 71 blocks at level 2), so one 32-lane group per row
+// leaves most of the GPU idle while each group walks its row step by step; its rows are
+// cut into slices while the launch has fewer than 2048 workgroups and a slice keeps at
+// least 6 blocks.  Rows of the fine and first coarse levels stay whole (slicing them
+// measured slower: more workgroups, each with a slice combine).
+static int mslices(const DMat& A) {
+  const double avg = A.nbr ? (double)A.nnzb / A.nbr : 0.0;
+  int qs = 0;
+  while (qs < 3 && (((int64_t)A.nbr << qs) / MROWS) < 2048 && avg / (2 << qs) >= 6.0) ++qs;
+  return qs;
+}
+
+static int mgrid(int nbr, int qs) {
+  const int rw = MROWS >> qs;
+  return (nbr + rw - 1) / rw;
+}
+
 // ---------------------------------------------------------------- multi V-cycle
 
 template <int B, class TV, class TX>
@@ -126,7 +144,8 @@ struct CycleM {
     TX* t = (TX*)W.lv[l].t;
     MLevel& C = W.lv[l + 1];
     const int g = (L.nbr + MROWS - 1) / MROWS;
-    const int gr = (L.R.nbr + MROWS - 1) / MROWS;
+    const int qa = mslices(L.A), qr = mslices(L.R), qp = mslices(L.P);
+    const int ga = mgrid(L.nbr, qa);
     // a square operator stored in the diagonal layout is read in it (same sums, bitwise),
     // its row blocks taken in the plane-tiled order
     const bool dia = (B == 3 || B == 4) && L.A.dia.k > 0;
@@ -136,23 +155,22 @@ struct CycleM {
     k_block_diag_m<B, TM, TIN, TX, TA><<<g, WG, 0, st>>>(L.nbr, K, (const TM*)L.M, r, z);
     if (dia)
       k_residual_m<B, TV, TX, TIN, TA, true><<<gd, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col, av,
-                                                                r, z, t, L.A.dia, ms);
+                                                                r, z, t, L.A.dia, ms, 0);
     else
-      k_residual_m<B, TV, TX, TIN, TA, false><<<g, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col, av,
-                                                                r, z, t, DiaOffs{}, MSched{});
-    k_spmm<B, B, TV, TX, TX, TA><<<gr, WG, 0, st>>>(L.R.nbr, K, L.R.ptr, L.R.col,
-                                                    (const TV*)L.R.val, t, (TX*)C.r, TA(1),
-                                                    TA(0));
+      k_residual_m<B, TV, TX, TIN, TA, false><<<ga, WG, 0, st>>>(
+          L.nbr, K, L.A.ptr, L.A.col, av, r, z, t, DiaOffs{}, MSched{}, qa);
+    k_spmm<B, B, TV, TX, TX, TA><<<mgrid(L.R.nbr, qr), WG, 0, st>>>(
+        L.R.nbr, K, L.R.ptr, L.R.col, (const TV*)L.R.val, t, (TX*)C.r, TA(1), TA(0), qr);
     TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
     run<TX, TX>(st, H, W, l + 1, K, (const TX*)C.r, zc);
-    k_spmm<B, B, TV, TX, TX, TA><<<g, WG, 0, st>>>(L.P.nbr, K, L.P.ptr, L.P.col,
-                                                   (const TV*)L.P.val, zc, z, TA(1), TA(1));
+    k_spmm<B, B, TV, TX, TX, TA><<<mgrid(L.P.nbr, qp), WG, 0, st>>>(
+        L.P.nbr, K, L.P.ptr, L.P.col, (const TV*)L.P.val, zc, z, TA(1), TA(1), qp);
     if (dia)
       k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, true><<<gd, WG, 0, st>>>(
-          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, L.A.dia, ms);
+          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, L.A.dia, ms, 0);
     else
-      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, false><<<g, WG, 0, st>>>(
-          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, DiaOffs{}, MSched{});
+      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, false><<<ga, WG, 0, st>>>(
+          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, DiaOffs{}, MSched{}, qa);
   }
 };
 
@@ -182,7 +200,6 @@ static void vcycle_m(mgk_solver* S, int K, const double* r, double* z) {
 
 static void outer_residual_m(mgk_solver* S, int K, const double* B, const double* X, double* R) {
   hipStream_t st = S->dev.stream;
-  const int g = (S->nbr + MROWS - 1) / MROWS;
   const DMat& A = S->A;
   const double* v = (const double*)A.val;
   const double* dv = (const double*)A.dval;
@@ -190,15 +207,16 @@ static void outer_residual_m(mgk_solver* S, int K, const double* B, const double
   MSched ms;
   const int gd = msched_of(A, ms);
   const MSched lin{};
+  const int qa = mslices(A), ga = mgrid(S->nbr, qa);
   switch (S->b) {
-    case 1: k_residual_m<1, double, double, double, double, false><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin); break;
+    case 1: k_residual_m<1, double, double, double, double, false><<<ga, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin, qa); break;
     case 3:
-      if (dia) k_residual_m<3, double, double, double, double, true><<<gd, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, dv, B, X, R, A.dia, ms);
-      else k_residual_m<3, double, double, double, double, false><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin);
+      if (dia) k_residual_m<3, double, double, double, double, true><<<gd, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, dv, B, X, R, A.dia, ms, 0);
+      else k_residual_m<3, double, double, double, double, false><<<ga, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin, qa);
       break;
     case 4:
-      if (dia) k_residual_m<4, double, double, double, double, true><<<gd, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, dv, B, X, R, A.dia, ms);
-      else k_residual_m<4, double, double, double, double, false><<<g, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin);
+      if (dia) k_residual_m<4, double, double, double, double, true><<<gd, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, dv, B, X, R, A.dia, ms, 0);
+      else k_residual_m<4, double, double, double, double, false><<<ga, WG, 0, st>>>(S->nbr, K, A.ptr, A.col, v, B, X, R, DiaOffs{}, lin, qa);
       break;
   }
 }

@@ -180,25 +180,35 @@ def test_cube48_adjoint_gradient():
     assert relfd <= 1e-6
 
 
+# Random interior body forces excite the slow modes of the 64^3 operator: at rtol 1e-8 a
+# column's solution error lands anywhere up to about 1.5e-6 (1.49e-6 measured for column 0),
+# depending on how far below 1e-8 its last iteration takes the residual.  The benchmark
+# therefore solves this workload to rtol 1e-9, where both bars hold on the same solve.
+MULTI64_RTOL = 1e-9
+
+
 def test_cube64_32rhs_lockstep_vs_oracle():
-    """All 32 columns meet 1e-8 (oracle SpMV); columns 0 and 17 match oracle solves."""
+    """The solve the benchmark times (rtol 1e-9): all 32 columns meet ||b - A x|| <= 1e-8 ||b||
+    (oracle SpMV); columns 0, 9, 17 and 31 match oracle solves to 1e-6."""
     n, K = 64, 32
     ptr, col, val = mgk.stokes_bsr(n)
     Bm = S.body_forces(n, K, 4)
     s = solver(ptr, col, val, hier=mgk.F32)
     dB = dev(Bm)
     dX = torch.zeros_like(dB)
-    infos = s.solve_multi(dB, dX, 1e-8)
+    infos = s.solve_multi(dB, dX, MULTI64_RTOL)
     X = dX.cpu().numpy()
     say("multi64", [i["iters"] for i in infos])
     A = oracle.stokes_matrix(n)
     AX = np.column_stack([oracle.spmv(A, np.ascontiguousarray(X[:, k])) for k in range(K)])
     res = np.linalg.norm(Bm - AX, axis=0) / np.linalg.norm(Bm, axis=0)
-    assert all(i["status"] == 0 for i in infos) and res.max() <= 1e-8, res.max()
+    assert all(i["status"] == 0 for i in infos) and res.max() <= MULTI64_RTOL, res.max()
     so = oracle.Solver(A, 4)
-    for k in (0, 17):
+    for k in (0, 9, 17, 31):
         xo, _ = so.solve(np.ascontiguousarray(Bm[:, k]), 1e-11)
-        assert np.linalg.norm(X[:, k] - xo) <= 1e-6 * np.linalg.norm(xo), k
+        err = np.linalg.norm(X[:, k] - xo) / np.linalg.norm(xo)
+        say("multi64 column", k, "error", err)
+        assert err <= 1e-6, (k, err)
 
 
 def test_batch_eight_systems_vs_oracle():
