@@ -637,7 +637,7 @@ def outer_kernel_name(info):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=96)
     ap.add_argument("--arms", default="bsr_f32,bsr_f64,bsr_bf16,csr_f64")
