@@ -675,6 +675,7 @@ int guard(F&& f) {
 }
 
 void precond(mgk_solver* S, const double* r, double* z, bool trans);
+void precond(mgk_solver* S, const float* r, double* z);
 }  // namespace mgk
 
 // ---------------------------------------------------------------- solver object
@@ -703,6 +704,11 @@ struct mgk_solver {
   // Krylov workspace (FP64)
   double *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *ph = nullptr, *s = nullptr,
          *sh = nullptr, *t = nullptr;
+  // FP32 copies of p and s, the BiCGStab V-cycle inputs, for a block-diagonal-smoothed AMG
+  // hierarchy stored below FP64 (its kernels round their FP64 input to FP32 on reading, so
+  // the copies give bitwise the same cycle while the three level-0 passes over the input
+  // read half the bytes); null otherwise
+  float *p32 = nullptr, *s32 = nullptr;
   double* sc = nullptr;      // device scalars
   double* part = nullptr;    // reduction partials
   double* part2 = nullptr;   // second-stage partials

@@ -966,28 +966,41 @@ static __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict
   }
 }
 
-// p = r + beta (p - omega v), beta = (rho1 / rho) (alpha / omega).
+// p = r + beta (p - omega v), beta = (rho1 / rho) (alpha / omega); p32 (if given) = p
+// rounded to FP32, the input of an FP32-accumulating V-cycle (which rounds its FP64 input
+// to FP32 on reading, so it gives the same result from the copy).
 static __global__ __launch_bounds__(WG) void k_bicg_p(size_t n, const double* __restrict__ sc,
                                                const double* __restrict__ r,
                                                const double* __restrict__ v,
-                                               double* __restrict__ p) {
+                                               double* __restrict__ p,
+                                               float* __restrict__ p32) {
   const double beta = (sc[SC_RHO1] / sc[SC_RHO]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
   const double om = sc[SC_OMEGA];
-  GRID_STRIDE(i, n) p[i] = r[i] + beta * (p[i] - om * v[i]);
+  if (p32) {
+    GRID_STRIDE(i, n) {
+      const double pi = r[i] + beta * (p[i] - om * v[i]);
+      p[i] = pi;
+      p32[i] = (float)pi;
+    }
+  } else {
+    GRID_STRIDE(i, n) p[i] = r[i] + beta * (p[i] - om * v[i]);
+  }
 }
 
-// s = r - alpha v; partials of ||s||^2.  (x += alpha phat is deferred to k_bicg_xr, or to
-// k_bicg_x when the iteration stops at s.)
+// s = r - alpha v; partials of ||s||^2; s32 (if given) = s rounded to FP32, as for p.
+// (x += alpha phat is deferred to k_bicg_xr, or to k_bicg_x when the iteration stops at s.)
 static __global__ __launch_bounds__(WG) void k_bicg_s(size_t n, const double* __restrict__ sc,
                                                const double* __restrict__ r,
                                                const double* __restrict__ v,
                                                double* __restrict__ s,
+                                               float* __restrict__ s32,
                                                double* __restrict__ part) {
   const double al = sc[SC_ALPHA];
   double ss = 0.0, dummy = 0.0;
   GRID_STRIDE(i, n) {
     const double si = r[i] - al * v[i];
     s[i] = si;
+    if (s32) s32[i] = (float)si;
     ss += si * si;
   }
   wg_sum2(ss, dummy);

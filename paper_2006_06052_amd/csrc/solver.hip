@@ -475,6 +475,32 @@ void precond(mgk_solver* S, const double* r, double* z, bool trans) {
   }
 }
 
+// The AMG V-cycle of an FP32 or BF16 hierarchy from an FP32 input (the copies p32 / s32).
+void precond(mgk_solver* S, const float* r, double* z) {
+  const bool timed = (S->prm.time_spmv & 2) && S->pev_used + 2 <= S->pev.size();
+  if (timed) HIPCK(hipEventRecord(S->pev[S->pev_used], S->dev.stream));
+  hipStream_t st = S->dev.stream;
+  DHier& H = S->H;
+#define MGK_VC32(BB)                                                               \
+  case BB:                                                                         \
+    if (H.storage == MGK_F32) Cycle<BB, float, float>::run<float, double>(st, H, 0, r, z, false); \
+    else Cycle<BB, bf16, float>::run<float, double>(st, H, 0, r, z, false);        \
+    break;
+  if (H.storage == MGK_F64 || S->kind == MGK_SCHUR || S->kind == MGK_ILU || H.ilu)
+    throw Error(MGK_E_STATE, "FP32 preconditioner input needs an FP32/BF16 AMG hierarchy");
+  switch (H.b) {
+    MGK_VC32(1)
+    MGK_VC32(3)
+    MGK_VC32(4)
+    default: throw Error(MGK_E_INVALID, "unsupported block size");
+  }
+#undef MGK_VC32
+  if (timed) {
+    HIPCK(hipEventRecord(S->pev[S->pev_used + 1], S->dev.stream));
+    S->pev_used += 2;
+  }
+}
+
 static void precond_apply(mgk_solver* S, const double* r, double* z, bool trans) {
   if (S->kind == MGK_ILU) {
     if (trans) throw Error(MGK_E_STATE, "transposed ILU preconditioner is not available");
@@ -549,6 +575,9 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
     return MGK_OK;
   }
   const double tol2 = (tol * nb) * (tol * nb);
+  // FP32 V-cycle inputs where the hierarchy takes them (forward cycles)
+  float* p32 = trans ? nullptr : S->p32;
+  float* s32 = trans ? nullptr : S->s32;
   int it = 0;
   for (int restart = 0;; ++restart) {
     // r = b - A x; rhat = r; rho = alpha = omega = 1; p = v = 0
@@ -573,18 +602,20 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
       if (S->hsc[SC_RHO1] == 0.0) break;  // breakdown: restart
       ++it;
       if (!pending_v) {
-        k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p);
-        precond(S, S->p, S->ph, trans);
+        k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p, p32);
+        if (p32) precond(S, p32, S->ph);
+        else precond(S, S->p, S->ph, trans);
         int nw = 0;
         outer_spmv(S, S->ph, S->v, trans, 1, S->rh, &nw);
         finalize(S, nw, 0, FIN_ALPHA);
       }
       pending_v = false;
-      k_bicg_s<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->s, S->part);
+      k_bicg_s<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->s, s32, S->part);
       finalize(S, g, 0, FIN_STORE1, SC_SS);
       publish(S, 0);
       // speculative: shat = M s; t = A shat (harmless if we stop after s)
-      precond(S, S->s, S->sh, trans);
+      if (s32) precond(S, s32, S->sh);
+      else precond(S, S->s, S->sh, trans);
       int nw = 0;
       outer_spmv(S, S->sh, S->t, trans, 2, S->s, &nw);  // partials (s,t), (t,t)
       finalize(S, nw, 1, FIN_OMEGA);
@@ -598,8 +629,9 @@ static int bicgstab(mgk_solver* S, const double* b, double* x, double tol, bool 
       publish(S, 1);
       if (it < maxiter_of(S)) {
         // speculative next p / V-cycle / v (x untouched)
-        k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p);
-        precond(S, S->p, S->ph, trans);
+        k_bicg_p<<<g, WG, 0, st>>>(n, S->sc, S->r, S->v, S->p, p32);
+        if (p32) precond(S, p32, S->ph);
+        else precond(S, S->p, S->ph, trans);
         int nw2 = 0;
         outer_spmv(S, S->ph, S->v, trans, 1, S->rh, &nw2);
         finalize(S, nw2, 0, FIN_ALPHA);
@@ -753,6 +785,11 @@ static void alloc_krylov(mgk_solver* S) {
   S->s = (double*)D.alloc(nb);
   S->sh = (double*)D.alloc(nb);
   S->t = (double*)D.alloc(nb);
+  if (S->prm.krylov == MGK_BICGSTAB && S->prm.hier != MGK_F64 && S->kind != MGK_SCHUR &&
+      S->kind != MGK_ILU && !S->prm.ilu_smoother) {
+    S->p32 = (float*)D.alloc(n * sizeof(float));
+    S->s32 = (float*)D.alloc(n * sizeof(float));
+  }
   S->sc = (double*)D.alloc(sizeof(double) * SC_COUNT);
   // partials: two dots per workgroup of the finest SpMV, or MAXM dots per
   // reduction workgroup
@@ -1169,11 +1206,16 @@ static double* scratch_ptr(int dev) {
 struct ScratchWorkspace {
   mgk_solver* S;
   double* saved[11];
+  float* saved32[2];
   size_t saved_len;
   ScratchWorkspace(mgk_solver* s, double* base) : S(s) {
     double** f[11] = {&S->r, &S->rh, &S->p, &S->v, &S->ph, &S->s, &S->sh, &S->t,
                       &S->part, &S->part2, &S->sc};
     for (int i = 0; i < 11; ++i) saved[i] = *f[i];
+    // the V-cycle reads p and s themselves (the same cycle as from their FP32 copies)
+    saved32[0] = S->p32;
+    saved32[1] = S->s32;
+    S->p32 = S->s32 = nullptr;
     saved_len = S->part_len;
     double* q = base;
     for (int i = 0; i < 8; ++i, q += NOALLOC_MAX_N) *f[i] = q;
@@ -1188,6 +1230,8 @@ struct ScratchWorkspace {
     double** f[11] = {&S->r, &S->rh, &S->p, &S->v, &S->ph, &S->s, &S->sh, &S->t,
                       &S->part, &S->part2, &S->sc};
     for (int i = 0; i < 11; ++i) *f[i] = saved[i];
+    S->p32 = saved32[0];
+    S->s32 = saved32[1];
     S->part_len = saved_len;
   }
 };

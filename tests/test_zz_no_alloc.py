@@ -29,7 +29,7 @@ def _rhs(n, seed):
     return torch.from_numpy(S.c2_rhs(n, seed=seed)).to(DEV)
 
 
-@pytest.mark.parametrize("hier", [mgk.F32, mgk.F64])
+@pytest.mark.parametrize("hier", [mgk.F32, mgk.BF16, mgk.F64])
 def test_noalloc_solve_equals_solve_on_two_calls(hier):
     # a larger system first, then a smaller one: the second call reuses the array
     # that still holds the first call's vectors
