@@ -101,7 +101,8 @@ def vcycle_bytes(s, hier):
     the pre-smoothing z = M r, the residual t = r - A z, the restriction R t, the
     prolongation z += P z_c and the post-smoothing z + M (r - A z) (matrices, smoother
     blocks and vectors once per kernel), and the coarsest dense FP64 inverse applied as a
-    matrix-vector product.  Level 0 reads and writes the Krylov method's FP64 vectors."""
+    matrix-vector product.  Level 0 writes the Krylov method's FP64 output and reads its
+    input in FP64 (FP64 hierarchy) or as the FP32 copy BiCGStab writes for the V-cycle."""
     sv = {0: 8, 1: 4, 2: 2}[hier]
     sx = 8 if hier == 0 else 4
     nl = s.nlevels()
@@ -110,9 +111,10 @@ def vcycle_bytes(s, hier):
         d = s.level_info(l)
         b, nb = d["block"], d["n_brows"]
         n = nb * b
-        s_in = 8 if l == 0 else sx
+        s_in = sx            # input read (level 0: FP64, or its FP32 copy)
+        s_out = 8 if l == 0 else sx
         if l == nl - 1:
-            per.append(8 * n * n + 2 * n * s_in)
+            per.append(8 * n * n + n * s_in + n * s_out)
             continue
         nc = d["n_agg"] * b
         A = d["nnzb"] * (b * b * sv + 4) + 4 * (nb + 1)
@@ -123,7 +125,7 @@ def vcycle_bytes(s, hier):
         res = A + n * sx + n * s_in + n * sx
         rst = R + n * sx + nc * sx
         pro = P + nc * sx + 2 * n * sx
-        post = A + Mb + n * s_in + n * sx + n * s_in
+        post = A + Mb + n * s_in + n * sx + n * s_out
         per.append(pre + res + rst + pro + post)
     return sum(per), per
 
