@@ -118,7 +118,10 @@ constexpr int MU = 4;
 // re-read an in-bounds block and are skipped at the FMA.  With qs > 0 the row's 1 << qs
 // contiguous slices (slice q: blocks [k0 + len*q/Q, k0 + len*(q+1)/Q)) are then added in
 // slice order, and the sum is in the q = 0 lanes.
-template <int BR, int BC, class TV, class TX, class TA>
+// SMALL: a stage of at most 128 blocks per pass (at least what the slice sums need), for
+// operators whose workgroups own few blocks (prolongators, sliced coarse rows): every lane
+// then holds far fewer staging registers, so more wavefronts fit on a CU.
+template <int BR, int BC, class TV, class TX, class TA, bool SMALL = false>
 __device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool on, int k, int K,
                                                   const int* __restrict__ ptr,
                                                   const int* __restrict__ col,
@@ -126,8 +129,11 @@ __device__ __forceinline__ void block_rows_staged(int r0, int nbr, int i, bool o
                                                   const TX* __restrict__ X, TA* acc,
                                                   int qs = 0, int q = 0) {
   constexpr int BB = BR * BC;
-  constexpr int CAP = mstage_cap<BR, BC, TV>();
   typedef typename std::conditional<sizeof(TV) == 2, uint16_t, TV>::type TS;
+  constexpr int CAPF = mstage_cap<BR, BC, TV>();
+  constexpr int CAPR = (int)((sizeof(TA) * BR * WG + BB * sizeof(TS) - 1) / (BB * sizeof(TS)));
+  constexpr int CAPS = CAPF < 128 ? CAPF : (CAPR > 128 ? CAPR : 128);
+  constexpr int CAP = SMALL ? CAPS : CAPF;
   __shared__ int s_col[CAP];
   __shared__ alignas(16) TS s_val[CAP * BB];
   static_assert(sizeof(TS) * CAP * BB >= sizeof(TA) * BR * WG, "slice sums fit the stage");
@@ -286,7 +292,7 @@ __device__ __forceinline__ void block_rows_dia(int r0, int nbr, int i, bool on, 
 // Row product of a square operator in either layout (DIA: val is the diagonal layout's);
 // pre() issues the caller's epilogue loads (first for the BSR walk, whose x loads wait for
 // column indices anyway; after the x loads on the diagonal layout).
-template <int B, class TV, class TX, class TA, bool DIA, class Pre>
+template <int B, class TV, class TX, class TA, bool DIA, bool SMALL = false, class Pre>
 __device__ __forceinline__ void block_rows(int r0, int nbr, int i, bool on, int k, int K,
                                            const int* __restrict__ ptr,
                                            const int* __restrict__ col,
@@ -297,7 +303,8 @@ __device__ __forceinline__ void block_rows(int r0, int nbr, int i, bool on, int 
     block_rows_dia<B, TV, TX, TA>(r0, nbr, i, on, k, K, of, val, X, acc, pre);
   } else {
     pre();
-    block_rows_staged<B, B, TV, TX, TA>(r0, nbr, i, on, k, K, ptr, col, val, X, acc, qs, q);
+    block_rows_staged<B, B, TV, TX, TA, SMALL>(r0, nbr, i, on, k, K, ptr, col, val, X, acc, qs,
+                                               q);
   }
 }
 
@@ -327,7 +334,7 @@ __device__ __forceinline__ void diag_block(const MRow& m, bool has_b, const TM* 
 }
 
 // Y = alpha A X + beta Y.
-template <int BR, int BC, class TV, class TX, class TY, class TA>
+template <int BR, int BC, class TV, class TX, class TY, class TA, bool SMALL>
 __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restrict__ ptr,
                                              const int* __restrict__ col,
                                              const TV* __restrict__ val,
@@ -340,8 +347,8 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
   TY yr[BR];
   if (beta != TA(0)) load_rows_ahead<BR>(Y, nbr, i, k, K, yr);
   TA acc[BR];
-  block_rows_staged<BR, BC, TV, TX, TA>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, X,
-                                        acc, qs, m.q);
+  block_rows_staged<BR, BC, TV, TX, TA, SMALL>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col,
+                                               val, X, acc, qs, m.q);
   if (!on || m.q) return;
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
@@ -442,7 +449,7 @@ static __global__ __launch_bounds__(WG) void k_reduce_stage_m(const double* __re
 }
 
 // T = F - A Z.
-template <int B, class TV, class TX, class TF, class TA, bool DIA>
+template <int B, class TV, class TX, class TF, class TA, bool DIA, bool SMALL = false>
 __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __restrict__ ptr,
                                                    const int* __restrict__ col,
                                                    const TV* __restrict__ val,
@@ -457,9 +464,9 @@ __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __
   const bool on = i < nbr && k < K;
   TF fr[B];
   TA acc[B];
-  block_rows<B, TV, TX, TA, DIA>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, of, Z,
-                                 acc, [&] { load_rows_ahead<B>(F, nbr, i, k, K, fr); }, qs,
-                                 m.q);
+  block_rows<B, TV, TX, TA, DIA, SMALL>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, of,
+                                        Z, acc, [&] { load_rows_ahead<B>(F, nbr, i, k, K, fr); },
+                                        qs, m.q);
   if (!on || m.q) return;
 #pragma unroll
   for (int r = 0; r < B; ++r) {
@@ -469,7 +476,8 @@ __global__ __launch_bounds__(WG) void k_residual_m(int nbr, int K, const int* __
 }
 
 // Zout = Z + M (F - A Z), M block diagonal.
-template <int B, class TV, class TX, class TF, class TO, class TM, class TA, bool DIA>
+template <int B, class TV, class TX, class TF, class TO, class TM, class TA, bool DIA,
+          bool SMALL = false>
 __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __restrict__ ptr,
                                                  const int* __restrict__ col,
                                                  const TV* __restrict__ val,
@@ -492,7 +500,7 @@ __global__ __launch_bounds__(WG) void k_smooth_m(int nbr, int K, const int* __re
   TA mb[B * B];
   diag_block<B, TM, TA>(mc, mc.i0 + 1 < nbr, M, mb);
   TA acc[B];
-  block_rows<B, TV, TX, TA, DIA>(
+  block_rows<B, TV, TX, TA, DIA, SMALL>(
       lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col, val, of, Z, acc,
       [&] {
         load_rows_ahead<B>(F, nbr, i, k, K, fr);

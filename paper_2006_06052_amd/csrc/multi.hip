@@ -119,12 +119,30 @@ static int mslices(const DMat& A) {
   return qs;
 }
 
+// The small stage (128 blocks per pass) for an operator whose workgroups own few blocks.
+static bool msmall(const DMat& A, int qs) {
+  const double avg = A.nbr ? (double)A.nnzb / A.nbr : 0.0;
+  return avg * (MROWS >> qs) <= 96.0;
+}
+
 static int mgrid(int nbr, int qs) {
   const int rw = MROWS >> qs;
   return (nbr + rw - 1) / rw;
 }
 
 // ---------------------------------------------------------------- multi V-cycle
+
+// Y = A X + beta Y over [n][K] vectors (restriction, prolongation).
+template <int B, class TV, class TX, class TA>
+static void spmm(hipStream_t st, const DMat& A, int K, int qs, const TX* X, TX* Y, TA beta) {
+  const int g = mgrid(A.nbr, qs);
+  if (msmall(A, qs))
+    k_spmm<B, B, TV, TX, TX, TA, true><<<g, WG, 0, st>>>(A.nbr, K, A.ptr, A.col,
+                                                         (const TV*)A.val, X, Y, TA(1), beta, qs);
+  else
+    k_spmm<B, B, TV, TX, TX, TA, false><<<g, WG, 0, st>>>(A.nbr, K, A.ptr, A.col,
+                                                          (const TV*)A.val, X, Y, TA(1), beta, qs);
+}
 
 template <int B, class TV, class TX>
 struct CycleM {
@@ -149,6 +167,9 @@ struct CycleM {
     // a square operator stored in the diagonal layout is read in it (same sums, bitwise),
     // its row blocks taken in the plane-tiled order
     const bool dia = (B == 3 || B == 4) && L.A.dia.k > 0;
+    // the small stage pays in register count for BF16 values only (FP32 residual and
+    // smoother instantiations compile to as many registers either way)
+    const bool small = sizeof(TV) == 2 && msmall(L.A, mslices(L.A));
     const TV* av = (const TV*)(dia ? L.A.dval : L.A.val);
     MSched ms;
     const int gd = msched_of(L.A, ms);
@@ -156,20 +177,24 @@ struct CycleM {
     if (dia)
       k_residual_m<B, TV, TX, TIN, TA, true><<<gd, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col, av,
                                                                 r, z, t, L.A.dia, ms, 0);
-    else
-      k_residual_m<B, TV, TX, TIN, TA, false><<<ga, WG, 0, st>>>(
+    else if (small)
+      k_residual_m<B, TV, TX, TIN, TA, false, true><<<ga, WG, 0, st>>>(
           L.nbr, K, L.A.ptr, L.A.col, av, r, z, t, DiaOffs{}, MSched{}, qa);
-    k_spmm<B, B, TV, TX, TX, TA><<<mgrid(L.R.nbr, qr), WG, 0, st>>>(
-        L.R.nbr, K, L.R.ptr, L.R.col, (const TV*)L.R.val, t, (TX*)C.r, TA(1), TA(0), qr);
+    else
+      k_residual_m<B, TV, TX, TIN, TA, false, false><<<ga, WG, 0, st>>>(
+          L.nbr, K, L.A.ptr, L.A.col, av, r, z, t, DiaOffs{}, MSched{}, qa);
+    spmm<B, TV, TX, TA>(st, L.R, K, qr, t, (TX*)C.r, TA(0));
     TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
     run<TX, TX>(st, H, W, l + 1, K, (const TX*)C.r, zc);
-    k_spmm<B, B, TV, TX, TX, TA><<<mgrid(L.P.nbr, qp), WG, 0, st>>>(
-        L.P.nbr, K, L.P.ptr, L.P.col, (const TV*)L.P.val, zc, z, TA(1), TA(1), qp);
+    spmm<B, TV, TX, TA>(st, L.P, K, qp, zc, z, TA(1));
     if (dia)
       k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, true><<<gd, WG, 0, st>>>(
           L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, L.A.dia, ms, 0);
+    else if (small)
+      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, false, true><<<ga, WG, 0, st>>>(
+          L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, DiaOffs{}, MSched{}, qa);
     else
-      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, false><<<ga, WG, 0, st>>>(
+      k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, false, false><<<ga, WG, 0, st>>>(
           L.nbr, K, L.A.ptr, L.A.col, av, (const TM*)L.M, r, z, zout, DiaOffs{}, MSched{}, qa);
   }
 };
