@@ -102,7 +102,9 @@ def vcycle_bytes(s, hier):
     prolongation z += P z_c and the post-smoothing z + M (r - A z) (matrices, smoother
     blocks and vectors once per kernel), and the coarsest dense FP64 inverse applied as a
     matrix-vector product.  Level 0 writes the Krylov method's FP64 output and reads its
-    input in FP64 (FP64 hierarchy) or as the FP32 copy BiCGStab writes for the V-cycle."""
+    input in FP64 (FP64 hierarchy) or as the FP32 copy BiCGStab writes for the V-cycle.
+    The pre-smoothing of a level between 0 and the coarsest is done by the restriction
+    above it, from the values it computes, so r is not read for it there."""
     sv = {0: 8, 1: 4, 2: 2}[hier]
     sx = 8 if hier == 0 else 4
     nl = s.nlevels()
@@ -121,7 +123,7 @@ def vcycle_bytes(s, hier):
         P = d["p_nnzb"] * (b * b * sv + 4) + 4 * (nb + 1)
         R = d["r_nnzb"] * (b * b * sv + 4) + 4 * (d["n_agg"] + 1)
         Mb = nb * b * b * sv   # smoother blocks in the hierarchy's value precision
-        pre = Mb + n * s_in + n * sx
+        pre = Mb + (n * s_in if l == 0 else 0) + n * sx
         res = A + n * sx + n * s_in + n * sx
         rst = R + n * sx + nc * sx
         pro = P + nc * sx + 2 * n * sx

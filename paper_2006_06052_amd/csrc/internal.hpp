@@ -366,6 +366,25 @@ static void spmv_s(hipStream_t st, const DMat& M, bool trans, const Tile& tile, 
   });
 }
 
+// y = R x and z = Mc y (the coarse level's pre-smoothing from a zero guess) in one launch,
+// with R's tile; bitwise the same as spmv_s followed by the block-diagonal kernel.
+template <int B, class TV, class TX, class TM>
+static void spmv_bd_s(hipStream_t st, const DMat& R, const TX* x, TX* y, const TM* Mc, TX* z) {
+  using TA = AccOf<TV>;
+  const int nrows = R.nbr;
+  const TV* v = (const TV*)R.val;
+  tile_switch_r<B, wide_ok<B, B, TV>()>(R.tile, [&](auto SS, auto UU, auto RR) {
+    constexpr int S_ = decltype(SS)::value, U_ = decltype(UU)::value, R_ = decltype(RR)::value;
+    const int g = nwg_rows<B, S_, R_>(nrows);
+    if (R.cached)
+      k_spmv_bd<B, B, S_, U_, TV, TX, TX, TA, TM, R_, true><<<g, WG, 0, st>>>(
+          nrows, R.ptr, R.col, v, x, y, Mc, z);
+    else
+      k_spmv_bd<B, B, S_, U_, TV, TX, TX, TA, TM, R_><<<g, WG, 0, st>>>(nrows, R.ptr, R.col, v,
+                                                                         x, y, Mc, z);
+  });
+}
+
 // y = A x (FP64) with the fused partials of <w1, y> and, when two, <y, y>;
 // returns the number of partials written per dot (one per group of dot_rows block rows).
 // Launch on WG-thread workgroups; with events, the dispatch itself records the kernel's
@@ -573,8 +592,10 @@ template <int B, class TV, class TX>
 struct Cycle {
   using TM = typename SmootherOf<TV>::type;
 
+  // pre: lv[l].z already holds the pre-smoothing M r (written by the restriction above).
   template <class TIN, class TOUT>
-  static void run(hipStream_t st, DHier& H, int l, const TIN* r, TOUT* zout, bool trans) {
+  static void run(hipStream_t st, DHier& H, int l, const TIN* r, TOUT* zout, bool trans,
+                  bool pre = false) {
     DLevel& L = H.lv[l];
     const int nl = (int)H.lv.size();
     if (l == nl - 1) {
@@ -588,13 +609,19 @@ struct Cycle {
     if (H.ilu)   // z = ILU^-1 r
       ilu_sweeps<B, TV, TX, TIN, TX>(st, L.Lf, L.Uf, L.Dinv, L.nbr, H.ilu_sweeps, r, z, sy, sy2,
                                      sw, sz);
-    else
+    else if (!pre)
       k_block_diag<B, TM, TIN, TX, AccOf<TV>>
           <<<(unsigned)((L.n + WG - 1) / WG), WG, 0, st>>>(L.nbr, trans, (const TM*)L.M, r, z);
     residual_s<B, B, TV, TX, TIN>(st, L.A, trans, trans ? L.A.ttile : L.A.tile, r, z, t);
-    spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.R.tile, t, (TX*)C.r, 1.0, 0.0);
+    // a coarse level that is not the coarsest pre-smooths from a zero guess: forward
+    // block-diagonal cycles fold that product into the restriction's launch
+    const bool fold = !trans && !H.ilu && l + 1 < nl - 1;
+    if (fold)
+      spmv_bd_s<B, TV, TX, TM>(st, L.R, t, (TX*)C.r, (const TM*)C.M, (TX*)C.z);
+    else
+      spmv_s<B, B, TV, TX, TX>(st, L.R, false, L.R.tile, t, (TX*)C.r, 1.0, 0.0);
     TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
-    run<TX, TX>(st, H, l + 1, (const TX*)C.r, zc, trans);
+    run<TX, TX>(st, H, l + 1, (const TX*)C.r, zc, trans, fold);
     spmv_s<B, B, TV, TX, TX>(st, L.P, false, L.P.tile, zc, z, 1.0, 1.0);
     if (H.ilu) {   // zout = z + ILU^-1 (r - A z)
       residual_s<B, B, TV, TX, TIN>(st, L.A, false, L.A.tile, r, z, t);

@@ -608,6 +608,53 @@ __global__ __launch_bounds__(WG) void k_spmv(int nbr, const int* __restrict__ pt
   }
 }
 
+// Restriction fused with the coarse level's pre-smoothing from a zero guess: y = A x and
+// z = M y, M holding one BR x BR smoother block per block row of y.  Each lane gathers its
+// block row's BR outputs (rounded to TY, as stored in y) from the s == 0 lanes and sums
+// them against its rows of M in ascending order from zero, as the block-diagonal kernel
+// does when it reads y back, so z is bitwise the same as that two-kernel sequence.
+template <int BR, int BC, int S, int U, class TV, class TX, class TY, class TA, class TM,
+          int RPL = 1, bool CACHED = false>
+__global__ __launch_bounds__(WG) void k_spmv_bd(int nbr, const int* __restrict__ ptr,
+                                                const int* __restrict__ col,
+                                                const TV* __restrict__ val,
+                                                const TX* __restrict__ x, TY* __restrict__ y,
+                                                const TM* __restrict__ M, TY* __restrict__ z) {
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const LaneInfo L = lane_info<BR, S, RPL>(lw);
+  const bool own = L.active && L.s == 0 && L.i < nbr;
+  const size_t row0 = (size_t)L.i * BR + L.r;
+  const RowRange rr = row_range<false>(ptr, DiaOffs{}, L.i, nbr);
+  __builtin_amdgcn_sched_barrier(0);
+  // the lane's rows of M are loaded ahead of the row product
+  TM mr[RPL * BR];
+  const TM* m = M + (own ? (size_t)L.i * BR * BR : 0);
+  if constexpr (BR == 4 && sizeof(TM) >= 4)
+    load_vals<RPL * BR, TM, TM, true>(m + (own ? L.r * BR : 0), mr);
+  else
+    load_ahead<RPL * BR>(m, own ? L.r * BR : 0, true, mr);
+  TA acc[RPL];
+  row_product_r<BR, BC, S, U, false, TV, TX, TA, RPL, CACHED>(L, nbr, ptr, col, nullptr, val, x,
+                                                              acc, DiaOffs{}, rr);
+  TY yo[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) yo[q] = (TY)acc[q];
+  // row c of the block row is entry c % RPL of lane c / RPL of the group
+  TA yv[BR];
+#pragma unroll
+  for (int c = 0; c < BR; ++c) yv[c] = (TA)__shfl(yo[c % RPL], L.gbase + c / RPL, WAVE);
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      y[row0 + q] = yo[q];
+      TA out = 0;
+#pragma unroll
+      for (int c = 0; c < BR; ++c) out = fma_(to_acc<TA>(mr[q * BR + c]), yv[c], out);
+      z[row0 + q] = (TY)out;
+    }
+  }
+}
+
 // y = A x fused with the partial dot products <w1, y> and (two) <y, y> of the
 // Krylov iteration (FP64 outer operator).  The partials have a fixed partition
 // whatever the tile: one per group of DOT_ROWS consecutive block rows, summed over
