@@ -359,6 +359,44 @@ __global__ __launch_bounds__(WG) void k_spmm(int nbr, int K, const int* __restri
   }
 }
 
+// Restriction fused with the coarse level's pre-smoothing from a zero guess: Y = A X and
+// Z = M Y, M holding one BR x BR smoother block per block row of Y.  The lane that writes
+// column k of a block row holds all BR of its outputs; it multiplies them (rounded to TY, as
+// stored in Y) by the row's M block in the order of k_block_diag_m, so Z is bitwise the
+// same as that two-kernel sequence.
+template <int BR, int BC, class TV, class TX, class TY, class TA, class TM, bool SMALL>
+__global__ __launch_bounds__(WG) void k_spmm_bd(int nbr, int K, const int* __restrict__ ptr,
+                                                const int* __restrict__ col,
+                                                const TV* __restrict__ val,
+                                                const TX* __restrict__ X, TY* __restrict__ Y,
+                                                const TM* __restrict__ M, TY* __restrict__ Z,
+                                                int qs) {
+  const int lw = xcd_remap(blockIdx.x, gridDim.x);
+  const MRow m = mrow(lw, qs);
+  const int i = m.i, k = m.k;
+  const bool on = i < nbr && k < K;
+  TA acc[BR];
+  block_rows_staged<BR, BC, TV, TX, TA, SMALL>(lw * (MROWS >> qs), nbr, i, on, k, K, ptr, col,
+                                               val, X, acc, qs, m.q);
+  if (!on || m.q) return;
+  TA mb[BR * BR];
+  load_block<BR, TM, TA>(M + (size_t)i * BR * BR, mb);
+  TA y[BR];
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    const TY yo = (TY)acc[r];
+    Y[((size_t)i * BR + r) * K + k] = yo;
+    y[r] = (TA)yo;
+  }
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    TA out = 0;
+#pragma unroll
+    for (int c = 0; c < BR; ++c) out = fma_(mb[r * BR + c], y[c], out);
+    Z[((size_t)i * BR + r) * K + k] = (TY)out;
+  }
+}
+
 // Y = A X (FP64) with per-column partials of <W1_k, Y_k> and (two) <Y_k, Y_k>:
 // part[w * KL + k] and part[(G + w) * KL + k] for row block w of G = ceil(nbr / 8) (the
 // block's 8 rows summed in order).

@@ -144,14 +144,28 @@ static void spmm(hipStream_t st, const DMat& A, int K, int qs, const TX* X, TX* 
                                                           (const TV*)A.val, X, Y, TA(1), beta, qs);
 }
 
+// Y = R X and Z = Mc Y (the coarse level's pre-smoothing from a zero guess) in one launch.
+template <int B, class TV, class TX, class TA, class TM>
+static void spmm_bd(hipStream_t st, const DMat& R, int K, int qs, const TX* X, TX* Y,
+                    const TM* Mc, TX* Z) {
+  const int g = mgrid(R.nbr, qs);
+  if (msmall(R, qs))
+    k_spmm_bd<B, B, TV, TX, TX, TA, TM, true><<<g, WG, 0, st>>>(R.nbr, K, R.ptr, R.col,
+                                                               (const TV*)R.val, X, Y, Mc, Z, qs);
+  else
+    k_spmm_bd<B, B, TV, TX, TX, TA, TM, false><<<g, WG, 0, st>>>(
+        R.nbr, K, R.ptr, R.col, (const TV*)R.val, X, Y, Mc, Z, qs);
+}
+
 template <int B, class TV, class TX>
 struct CycleM {
   using TM = typename SmootherOf<TV>::type;
   using TA = AccOf<TV>;
 
+  // pre: W.lv[l].z already holds the pre-smoothing M r (written by the restriction above).
   template <class TIN, class TOUT>
   static void run(hipStream_t st, DHier& H, MultiWork& W, int l, int K, const TIN* r,
-                  TOUT* zout) {
+                  TOUT* zout, bool pre = false) {
     DLevel& L = H.lv[l];
     const int nl = (int)H.lv.size();
     if (l == nl - 1) {
@@ -173,7 +187,8 @@ struct CycleM {
     const TV* av = (const TV*)(dia ? L.A.dval : L.A.val);
     MSched ms;
     const int gd = msched_of(L.A, ms);
-    k_block_diag_m<B, TM, TIN, TX, TA><<<g, WG, 0, st>>>(L.nbr, K, (const TM*)L.M, r, z);
+    if (!pre)
+      k_block_diag_m<B, TM, TIN, TX, TA><<<g, WG, 0, st>>>(L.nbr, K, (const TM*)L.M, r, z);
     if (dia)
       k_residual_m<B, TV, TX, TIN, TA, true><<<gd, WG, 0, st>>>(L.nbr, K, L.A.ptr, L.A.col, av,
                                                                 r, z, t, L.A.dia, ms, 0);
@@ -183,9 +198,16 @@ struct CycleM {
     else
       k_residual_m<B, TV, TX, TIN, TA, false, false><<<ga, WG, 0, st>>>(
           L.nbr, K, L.A.ptr, L.A.col, av, r, z, t, DiaOffs{}, MSched{}, qa);
-    spmm<B, TV, TX, TA>(st, L.R, K, qr, t, (TX*)C.r, TA(0));
+    // a coarse level that is not the coarsest pre-smooths from a zero guess: the
+    // restriction's launch does that product too
+    const bool fold = l + 1 < nl - 1;
+    if (fold)
+      spmm_bd<B, TV, TX, TA, TM>(st, L.R, K, qr, t, (TX*)C.r, (const TM*)H.lv[l + 1].M,
+                                 (TX*)C.z);
+    else
+      spmm<B, TV, TX, TA>(st, L.R, K, qr, t, (TX*)C.r, TA(0));
     TX* zc = (l + 1 == nl - 1) ? (TX*)C.z : (TX*)C.z2;
-    run<TX, TX>(st, H, W, l + 1, K, (const TX*)C.r, zc);
+    run<TX, TX>(st, H, W, l + 1, K, (const TX*)C.r, zc, fold);
     spmm<B, TV, TX, TA>(st, L.P, K, qp, zc, z, TA(1));
     if (dia)
       k_smooth_m<B, TV, TX, TIN, TOUT, TM, TA, true><<<gd, WG, 0, st>>>(
