@@ -15,9 +15,10 @@ the speedup figures.
 
 The roofline entry is the FP64 4x4 BSR SpMV of the outer operator fused with the next
 Krylov dot products (two launches per BiCGStab iteration, the largest single kernel of
-the solve): every launch inside the timed solves records HIP start and stop events on the
-library's stream through its own dispatch (hipExtLaunchKernelGGL), and the average
-duration is set against the algorithmic bytes per
+the solve): the timed solves carry no timing events; one more solve of the same system,
+after them, records HIP start and stop events on the library's stream through each
+launch's own dispatch (hipExtLaunchKernelGGL), and the average duration is set against
+the algorithmic bytes per
 launch, nnzb*(16*8 + 4) + 4*(n_brows + 1) + 2*n_brows*4*8 for y = A x plus 8*n for the
 dot weight vector the fused kernel reads.
 """
@@ -66,18 +67,19 @@ def bsr_to_scalar_csr(ptr, col, val):
     return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
 
 
-def time_solves(s, db, steps, warmup, torch):
-    """K timed solves from x0 = 0; also the summed HIP-event durations (recorded on the
-    library's stream inside those solves) of the outer SpMV launches and of the
-    preconditioner applications."""
+def time_solves(s, db, steps, warmup, torch, mask=3):
+    """K timed solves from x0 = 0, with the library's timing events switched off; then one
+    more solve, outside the timed region, with the events of `mask` on, for the summed
+    HIP-event durations (recorded on the library's stream inside that solve) of the outer
+    SpMV launches and of the preconditioner applications."""
     dx = torch.zeros_like(db)
     info = None
+    s.set_timing(0)
     for _ in range(warmup):
         dx.zero_()
         info = s.solve(db, dx, 1e-8)
     torch.cuda.synchronize()
     times = []
-    ev = {"spmv_ms": 0.0, "spmv_calls": 0, "precond_ms": 0.0, "precond_calls": 0}
     for _ in range(steps):
         dx.zero_()
         torch.cuda.synchronize()
@@ -85,8 +87,15 @@ def time_solves(s, db, steps, warmup, torch):
         info = s.solve(db, dx, 1e-8)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+    ev = {"spmv_ms": 0.0, "spmv_calls": 0, "precond_ms": 0.0, "precond_calls": 0}
+    if mask:
+        s.set_timing(mask)
+        dt = torch.zeros_like(db)
+        tinfo = s.solve(db, dt, 1e-8)
+        torch.cuda.synchronize()
+        s.set_timing(0)
         for k in ev:
-            ev[k] += info[k]
+            ev[k] += tinfo[k]
     return times, info, dx, ev
 
 
@@ -278,12 +287,18 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
         def run():
             X.zero_()
             return s.solve_multi(B, X, rtol)
+        s.set_timing(0)
         t, infos = _median_solve(run, torch)
+        # one more solve, untimed, with events on the fused SpMM launches
+        s.set_timing(1)
+        tinfos = run()
+        torch.cuda.synchronize()
+        s.set_timing(0)
         # the outer FP64 SpMM fused with the per-column dots: the matrix once, X and Y with
         # K columns, and the K-column dot weights
         nbr_, nnzb_ = len(ptr) - 1, int(ptr[-1])
         spmm_bytes = nnzb_ * (16 * 8 + 4) + 4 * (nbr_ + 1) + 3 * nbr_ * 4 * K * 8
-        spmm_us = infos[0]["spmv_ms"] * 1e3 / max(infos[0]["spmv_calls"], 1)
+        spmm_us = tinfos[0]["spmv_ms"] * 1e3 / max(tinfos[0]["spmv_calls"], 1)
         cols = [B[:, k].contiguous() for k in range(4)]
         xc = torch.zeros_like(cols[0])
 
@@ -296,7 +311,7 @@ def secondary_workloads(mgk, S, torch, log_fn, which):
         t1, its1 = _median_solve(run1, torch)
         seq = t1 / len(cols) * K
         spmm = {"kernel": "mgk::k_spmm_dot<4, true>", "bytes_per_launch": spmm_bytes,
-                "avg_launch_us": spmm_us, "launches": infos[0]["spmv_calls"],
+                "avg_launch_us": spmm_us, "launches": tinfos[0]["spmv_calls"],
                 "achieved_gbs": spmm_bytes / spmm_us / 1e3,
                 "frac": spmm_bytes / spmm_us / 1e3 / HBM_PEAK_GBS, "traffic": None}
         # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)
@@ -688,9 +703,9 @@ def main():
     HIER = {"bsr_f64": mgk.F64, "bsr_f32": mgk.F32, "bsr_bf16": mgk.BF16, "csr_f64": mgk.F64}
 
     def make(arm):
-        """The arm's solver; every arm records HIP events around its outer SpMVs and its
-        preconditioner applications (time_spmv = 3), so all solve times carry the same
-        instrumentation."""
+        """The arm's solver, set up to record HIP events around its outer SpMVs and its
+        preconditioner applications (time_spmv = 3); time_solves switches them off for the
+        timed solves and on for one extra solve that gives the per-kernel averages."""
         t0 = time.perf_counter()
         if arm == "csr_f64":
             sp_, sc_, sv_ = bsr_to_scalar_csr(ptr, col, val)

@@ -292,6 +292,12 @@ int mgk_batch_solve(mgk_solver* s, const double* const* d_b, double* const* d_x,
 int mgk_spmv(mgk_solver* s, int32_t hier, int32_t level, int32_t which, const void* d_x,
              void* d_y);
 
+/* Restricts the timing events of later solves (mgk_info.spmv_ms, precond_ms) to the
+ * bits of mask (same meaning as mgk_params.time_spmv) that were set at setup; 0 turns
+ * them off, so a solve carries no event records, and setting the setup value again turns
+ * them back on.  Rejects a mask outside 0..3 (MGK_E_INVALID). */
+int mgk_set_timing(mgk_solver* s, int32_t mask);
+
 /* z = B r for one preconditioner application (FP64 in and out). */
 int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t transposed);
 

@@ -71,7 +71,7 @@ class LevelDesc(C.Structure):
 EXPORTS = ["mgk_params_default", "mgk_stokes_sizes", "mgk_stokes_assemble", "mgk_csr_to_bsr",
            "mgk_setup", "mgk_setup_host", "mgk_solve", "mgk_solve_noalloc",
            "mgk_solve_transposed", "mgk_solve_multi",
-           "mgk_batch_setup", "mgk_batch_solve", "mgk_spmv", "mgk_precond_apply",
+           "mgk_batch_setup", "mgk_batch_solve", "mgk_spmv", "mgk_precond_apply", "mgk_set_timing",
            "mgk_level_count", "mgk_level_info", "mgk_level_export", "mgk_ilu_info",
            "mgk_ilu_export", "mgk_theta_grad", "mgk_bsr_grad", "mgk_destroy", "mgk_last_error"]
 
@@ -104,6 +104,7 @@ def lib():
     L.mgk_batch_solve.argtypes = [P, P, P, D, P]
     L.mgk_spmv.argtypes = [P, I32, I32, I32, P, P]
     L.mgk_precond_apply.argtypes = [P, P, P, I32]
+    L.mgk_set_timing.argtypes = [P, I32]
     L.mgk_level_count.argtypes = [P, I32]
     L.mgk_level_info.argtypes = [P, I32, I32, C.POINTER(LevelDesc)]
     L.mgk_level_export.argtypes = [P, I32, I32, I32, P, P, P, P]
@@ -252,6 +253,12 @@ class Solver:
     def solve(self, b, x, rtol: float = 1e-8) -> dict:
         """x (in: initial guess, out: solution); returns the info record."""
         return self._solve(lib().mgk_solve, b, x, rtol)
+
+    def set_timing(self, mask: int):
+        """Timing events of later solves: mask & the setup's time_spmv (0 turns them off)."""
+        rc = lib().mgk_set_timing(self._h, int(mask))
+        if rc:
+            _err(rc)
 
     def solve_noalloc(self, b, x, rtol: float = 1e-8) -> dict:
         """solve() with the Krylov workspace in the library's static device array: the

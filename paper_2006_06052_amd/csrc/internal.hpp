@@ -742,6 +742,8 @@ struct mgk_solver {
   size_t part_len = 0;
   double* hsc = nullptr;     // pinned host mirror of sc
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int time_mask = 0;             // timing of the next solves: prm.time_spmv, restricted by
+                                 // mgk_set_timing
   std::vector<hipEvent_t> tev;   // timing events around outer SpMV launches
   size_t tev_used = 0;
   std::vector<hipEvent_t> pev;   // timing events around preconditioner applications

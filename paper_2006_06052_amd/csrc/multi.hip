@@ -276,7 +276,7 @@ static int outer_spmm_dot(mgk_solver* S, int K, const double* X, double* Y, int 
   const DMat& A = S->A;
   double* part = S->multi->part;
   // with time_spmv, the kernel's dispatch records its own start and end
-  const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
+  const bool timed = (S->time_mask & 1) && S->tev_used + 2 <= S->tev.size();
   hipEvent_t e0 = timed ? S->tev[S->tev_used] : nullptr;
   hipEvent_t e1 = timed ? S->tev[S->tev_used + 1] : nullptr;
   const double* v = (const double*)A.val;

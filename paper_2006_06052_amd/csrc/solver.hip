@@ -382,7 +382,7 @@ namespace mgk {
 void outer_spmv(mgk_solver* S, const double* x, double* y, bool trans, int dots,
                 const double* w1, int* nwg) {
   hipStream_t st = S->dev.stream;
-  const bool timed = (S->prm.time_spmv & 1) && S->tev_used + 2 <= S->tev.size();
+  const bool timed = (S->time_mask & 1) && S->tev_used + 2 <= S->tev.size();
   // the fused kernel's own dispatch records its start and end; the plain product (one or
   // more launches) is bracketed by event records on the stream
   hipEvent_t e0 = timed && dots ? S->tev[S->tev_used] : nullptr;
@@ -466,7 +466,7 @@ static void precond_apply(mgk_solver* S, const double* r, double* z, bool trans)
 
 // One preconditioner application z = B r, bracketed by timing events when requested.
 void precond(mgk_solver* S, const double* r, double* z, bool trans) {
-  const bool timed = (S->prm.time_spmv & 2) && S->pev_used + 2 <= S->pev.size();
+  const bool timed = (S->time_mask & 2) && S->pev_used + 2 <= S->pev.size();
   if (timed) HIPCK(hipEventRecord(S->pev[S->pev_used], S->dev.stream));
   precond_apply(S, r, z, trans);
   if (timed) {
@@ -477,7 +477,7 @@ void precond(mgk_solver* S, const double* r, double* z, bool trans) {
 
 // The AMG V-cycle of an FP32 or BF16 hierarchy from an FP32 input (the copies p32 / s32).
 void precond(mgk_solver* S, const float* r, double* z) {
-  const bool timed = (S->prm.time_spmv & 2) && S->pev_used + 2 <= S->pev.size();
+  const bool timed = (S->time_mask & 2) && S->pev_used + 2 <= S->pev.size();
   if (timed) HIPCK(hipEventRecord(S->pev[S->pev_used], S->dev.stream));
   hipStream_t st = S->dev.stream;
   DHier& H = S->H;
@@ -799,6 +799,7 @@ static void alloc_krylov(mgk_solver* S) {
   S->part2 = (double*)D.alloc(sizeof(double) * (2 * (S->part_len / RED_CHUNK + 2)));
   HIPCK(hipHostMalloc((void**)&S->hsc, sizeof(double) * SC_COUNT, hipHostMallocDefault));
   for (auto& e : S->ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  S->time_mask = S->prm.time_spmv & 3;
   if (S->prm.time_spmv & 1) {
     S->tev.resize(2 * (2 * (size_t)S->prm.maxiter + 64));
     for (auto& e : S->tev) HIPCK(hipEventCreate(&e));
@@ -1270,6 +1271,15 @@ int mgk_solve_noalloc(mgk_solver* s, const double* d_b, double* d_x, double rtol
     mgk::ScratchWorkspace ws(s, mgk::scratch_ptr(dev));
     return solve_common(s, d_b, d_x, rtol, info, false);
   });
+}
+
+int mgk_set_timing(mgk_solver* s, int32_t mask) {
+  if (!s || mask < 0 || mask > 3) {
+    mgk::g_err = "set_timing: null solver or mask outside 0..3";
+    return MGK_E_INVALID;
+  }
+  s->time_mask = mask & s->prm.time_spmv;
+  return MGK_OK;
 }
 
 int mgk_precond_apply(mgk_solver* s, const double* d_r, double* d_z, int32_t transposed) {

@@ -322,6 +322,35 @@ def test_edge_cases():
         s2.solve(bx.float(), x, 1e-8)
 
 
+def test_timing_switch_leaves_results_bitwise_equal():
+    """mgk_set_timing turns the solve's timing events off and on again; the iterates do not
+    depend on it (the events only mark points on the stream)."""
+    n = 12
+    th, bsr, A = problem(n, 1.0, 3)
+    b = dev(S.c2_rhs(n, 1e-3, 5))
+    s = gpu_solver(bsr, coarse_enough=300, hier=mgk.F32, time_spmv=3)
+    xs = []
+    for mask in (3, 0, 1, 2, 3):
+        s.set_timing(mask)
+        x = torch.zeros_like(b)
+        info = s.solve(b, x, 1e-8)
+        assert info["status"] == 0
+        assert (info["spmv_calls"] > 0) == bool(mask & 1), (mask, info["spmv_calls"])
+        assert (info["precond_calls"] > 0) == bool(mask & 2), (mask, info["precond_calls"])
+        xs.append(x)
+    for x in xs[1:]:
+        assert torch.equal(x, xs[0])
+    with pytest.raises(mgk.MgkError):
+        s.set_timing(4)
+    # bits not set at setup stay off
+    s0 = gpu_solver(bsr, coarse_enough=300, hier=mgk.F32)
+    s0.set_timing(3)
+    x = torch.zeros_like(b)
+    info = s0.solve(b, x, 1e-8)
+    assert info["spmv_calls"] == 0 and info["precond_calls"] == 0
+    assert torch.equal(x, xs[0])
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_results_independent_of_kernel_tile(storage):
     """Every engine tile sums in the same fixed order, so SpMV and whole solves are bitwise
