@@ -223,6 +223,12 @@ def test_invalid_input_rejected_before_device_work():
     with pytest.raises(mgk.MgkError) as e:
         host_solver(ptr, col, val, 4).ilu_export()     # not an ILU solver
     assert e.value.code == -5
+    hs = host_solver(ptr, col, val, 4)
+    hs.set_timing(0)                                   # a mask within 0..3 is accepted
+    for bad_mask in (-1, 4):
+        with pytest.raises(mgk.MgkError) as e:
+            hs.set_timing(bad_mask)
+        assert e.value.code == -1, bad_mask
     for bad_kw in (dict(krylov=mgk.IDRS, idr_s=0), dict(krylov=mgk.IDRS, idr_s=17),
                    dict(krylov=3), dict(coarsening=2), dict(schur_lower=2)):
         with pytest.raises(mgk.MgkError) as e:
